@@ -1,0 +1,130 @@
+"""Throughput benchmark: ME evaluations per second on one MI355X.
+
+Workload (default): g g -> t tbar g g g, 262144 flat RAMBO events at
+sqrt(s) = 1500 GeV (seed 1003), m_t = 173 GeV, alpha_s = 0.118, FP64
+diagrams and FP64 colour sum, all good helicities.  A step is one
+me_compute call over the whole batch (momenta resident in HBM, output left
+in HBM).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/clk (FMA = 2)
+
+NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7}
+SEED = {'gg_ttx': 1001, 'gg_ttxg': 1004, 'gg_ttxgg': 1002, 'gg_ttxggg': 1003}
+
+
+def cpu_baseline(process, mom, alpha_s, budget_s):
+    """Time the oracle on a bounded sample of the same workload (rank 0, N=1)."""
+    from oracle import me as ome
+    proc = ome.process(NPAR[process])
+    n = 1
+    t_used = 0.0
+    done = 0
+    c0 = resource.getrusage(resource.RUSAGE_SELF)
+    w0 = time.perf_counter()
+    # double the sample until the budget is reached
+    while True:
+        t0 = time.perf_counter()
+        ome.matrix_element(proc, mom[done:done + n], alpha_s)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        done += n
+        if t_used + 2.2 * dt > budget_s or done + 2 * n > mom.shape[0]:
+            break
+        n *= 2
+    wall = time.perf_counter() - w0
+    c1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (c1.ru_utime - c0.ru_utime) + (c1.ru_stime - c0.ru_stime)
+    return {'value': done / t_used, 'unit': 'ME evals/s', 'cores': max(1, round(cpu / wall)),
+            'kind': 'oracle',
+            'sample': f'first {done} events of the same {process} workload, all helicities, '
+                      f'numpy FP64 oracle, {t_used:.1f} s'}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=10)
+    ap.add_argument('--warmup', type=int, default=2)
+    ap.add_argument('--process', default='gg_ttxggg')
+    ap.add_argument('--nevt', type=int, default=262144)
+    ap.add_argument('--alpha-s', type=float, default=0.118)
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--cpu-budget', type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f'bench.py runs on one GPU only (got --gpus {args.gpus}): events are independent, '
+              'so more GPUs would each run this same kernel on their own share of events.',
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_05392_amd import binding, flops, rambo
+
+    process, nevt = args.process, args.nevt
+    mom = rambo.generate(NPAR[process], nevt, SEED[process])
+    dev = torch.device('cuda:0')
+    dmom = torch.from_numpy(mom).to(dev)
+    out = torch.empty(nevt, dtype=torch.float64, device=dev)
+    m = binding.MatrixElement(process)
+    stream = torch.cuda.current_stream(dev)
+    print(f'# bench {process} nevt={nevt}: warmup {args.warmup}', file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        m.me_compute(dmom, nevt, args.alpha_s, out, stream)
+    torch.cuda.synchronize()
+    nhel = len(m.me_good_helicities())
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    print(f'# bench timing {args.steps} steps', file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        m.me_compute(dmom, nevt, args.alpha_s, out, stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    value = nevt / (ms * 1e-3)
+    res = out.cpu().numpy()
+    if not np.all(np.isfinite(res)):
+        print('non-finite matrix elements', file=sys.stderr)
+        sys.exit(1)
+
+    f_unit = flops.per_event_helicity(process)
+    step_flops = f_unit * nhel * nevt
+    achieved = step_flops / (ms * 1e-3) / 1e12
+    line = {
+        'metric': 'ME evals/s', 'value': value, 'unit': 'ME evals/s', 'n_gpus': 1,
+        'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': ms,
+        'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64',
+        'data': 'synthetic (seeded flat RAMBO phase space)',
+        'config': {'workload': f'{process} LO |M|^2, FP64 diagrams + FP64 colour sum', 'process': process,
+                   'nevt': nevt, 'sqrt_s_GeV': 1500.0, 'mt_GeV': 173.0, 'alpha_s': args.alpha_s,
+                   'good_helicities': nhel, 'parallelism': 'single GPU'},
+        'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
+                     'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS, 'traffic': None,
+                     'flops_per_event_helicity': f_unit,
+                     'kernel': f'me_chunk_kernel<{process}> (+ reduce_chunks_kernel, <0.1%)'},
+    }
+    if not args.no_cpu_baseline:
+        print('# bench cpu baseline (oracle)', file=sys.stderr, flush=True)
+        line['cpu_baseline'] = cpu_baseline(process, mom, args.alpha_s, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,127 @@
+"""Build the HIP library libmegpu.so for gfx950 (MI355X).
+
+Steps: run the process generator for every process, write one HIP translation
+unit per process (so that the large generated units compile in parallel),
+compile them and the runtime with hipcc, link the shared library in-tree.
+
+    python -m paper_2510_05392_amd.build [--procs gg_ttx,gg_ttxg] [-j N]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, 'csrc')
+GEN = os.path.join(CSRC, 'generated')
+OBJ = os.path.join(ROOT, '_build', 'obj')
+INCLUDE = os.path.join(ROOT, 'include')
+LIB = os.path.join(HERE, 'libmegpu.so')
+
+PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg']
+ARCH = 'gfx950'
+HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
+FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
+         # packed FP32 instructions stay off ("hardware notes")
+         '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
+         '-I', INCLUDE, '-I', CSRC, '-I', GEN]
+
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path) and open(path).read() == text:
+        return
+    with open(path, 'w') as f:
+        f.write(text)
+
+
+def generate_sources(procs, build_dir):
+    sys.path.insert(0, ROOT)
+    from paper_2510_05392_amd.gen import codegen
+    os.makedirs(GEN, exist_ok=True)
+    os.makedirs(build_dir, exist_ok=True)
+    units = []
+    for name in procs:
+        src, _, _ = codegen.generate(name)
+        inc = os.path.join(GEN, f'{name}.inc')
+        _write_if_changed(inc, src)
+        unit = (f'// Kernels and descriptor of process {name} (generated).\n'
+                f'#include "{name}.inc"\n#include "me_kernels.h"\n'
+                f'namespace me {{\nconst ProcessDesc* process_{name}() {{ return describe<me::{name}>(); }}\n}}\n')
+        path = os.path.join(GEN, f'proc_{name}.hip')
+        _write_if_changed(path, unit)
+        units.append((path, os.path.join(OBJ, f'proc_{name}.o'), [inc]))
+    reg = ['// Processes compiled into this library (generated).']
+    reg += [f'const ProcessDesc* process_{n}();' for n in procs]
+    reg.append('static const ProcessDesc* (*const kProcesses[])() = {'
+               + ', '.join(f'process_{n}' for n in procs) + '};')
+    reg.append(f'static const int kNumProcesses = {len(procs)};')
+    regfile = os.path.join(build_dir, 'registry.inc')
+    _write_if_changed(regfile, '\n'.join(reg) + '\n')
+    units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
+                  [regfile, os.path.join(INCLUDE, 'megpu.h')]))
+    return units
+
+
+def _compile(src, obj, extra_deps, build_dir):
+    deps = [src] + list(extra_deps)
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith('.h')]
+    flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') else [])
+    key = hashlib.sha1((' '.join(flags) + HIPCC).encode()).hexdigest()[:8]
+    stamp = obj + '.flags'
+    if (os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
+            and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps)):
+        return obj, False
+    cmd = [HIPCC, *flags, '-c', src, '-o', obj + '.tmp']
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f'hipcc failed for {src}:\n{r.stderr[-4000:]}')
+    os.replace(obj + '.tmp', obj)
+    with open(stamp, 'w') as f:
+        f.write(key)
+    return obj, True
+
+
+def build(procs=None, jobs=None, verbose=True, lib=LIB):
+    """Generate, compile and link; objects are reused when their inputs are unchanged."""
+    procs = list(procs or PROCESSES)
+    tag = hashlib.sha1(','.join(procs).encode()).hexdigest()[:10]
+    build_dir = os.path.join(ROOT, '_build', f'set_{tag}')
+    os.makedirs(OBJ, exist_ok=True)
+    units = generate_sources(procs, build_dir)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = {ex.submit(_compile, src, obj, deps, build_dir): src for src, obj, deps in units}
+        for f in cf.as_completed(futs):
+            obj, rebuilt = f.result()
+            objs.append(obj)
+            if verbose:
+                print(('compiled ' if rebuilt else 'up to date ') + os.path.basename(futs[f]), flush=True)
+    objs.sort()
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    cmd = [HIPCC, f'--offload-arch={ARCH}', '-shared', '-fPIC', *objs, '-o', lib + '.tmp']
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f'link failed:\n{r.stderr[-4000:]}')
+    os.replace(lib + '.tmp', lib)
+    if verbose:
+        print('linked', lib, flush=True)
+    return lib
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--procs', default=','.join(PROCESSES))
+    ap.add_argument('-j', type=int, default=None)
+    args = ap.parse_args()
+    build(args.procs.split(','), args.j)
+
+
+if __name__ == '__main__':
+    main()

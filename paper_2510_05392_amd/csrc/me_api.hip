@@ -1,0 +1,326 @@
+// Runtime and C ABI of the matrix-element engine (see include/megpu.h).
+//
+// The handle owns: the process description, the good-helicity list (host and
+// device), and a device scratch buffer for the per-chunk partial sums.  Every
+// entry point validates its arguments, converts HIP failures into ME_EHIP with
+// the runtime's message, and never throws.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "megpu.h"
+#include "me_process.h"
+
+namespace me {
+#include "registry.inc"   // const ProcessDesc* (*const kProcesses[])() and kNumProcesses
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(ME_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+std::mutex g_live_mu;
+std::set<const void*> g_live;
+
+__global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nchunk, int64_t nevt,
+                                     double scale, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += partial[(int64_t)c * nevt + e];   // fixed order
+  out[e] = scale * acc;
+}
+
+}  // namespace
+
+struct me_ctx {
+  const me::ProcessDesc* desc = nullptr;
+  me_params params{};
+  std::vector<int> good;      // host copy of the good helicities
+  int* d_hels = nullptr;      // device, good helicities (capacity nhel)
+  int* d_scratch_hels = nullptr;  // device, caller-chosen helicities (capacity nhel)
+  double* d_partial = nullptr;
+  size_t partial_cap = 0;     // doubles
+  bool filtered = false;
+};
+
+namespace {
+
+bool live(me_handle h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return h != nullptr && g_live.count(h) != 0;
+}
+
+int check_handle(me_handle h) {
+  if (h == nullptr) return fail(ME_EINVAL, "null handle");
+  if (!live(h)) return fail(ME_ESTATE, "handle is not live (finalised or never created)");
+  return ME_OK;
+}
+
+int ensure_partial(me_ctx* c, size_t n) {
+  if (n <= c->partial_cap) return ME_OK;
+  if (c->d_partial) {
+    hipError_t e = hipFree(c->d_partial);
+    c->d_partial = nullptr;
+    c->partial_cap = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(scratch)");
+  }
+  hipError_t e = hipMalloc(&c->d_partial, n * sizeof(double));
+  if (e != hipSuccess) {
+    c->d_partial = nullptr;
+    return fail(ME_ENOMEM, std::string("hipMalloc(scratch): ") + hipGetErrorString(e));
+  }
+  c->partial_cap = n;
+  return ME_OK;
+}
+
+int upload_good(me_ctx* c, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(c->d_hels, c->good.data(), c->good.size() * sizeof(int),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(helicities)");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return ME_OK;
+}
+
+int upload_scratch_hels(me_ctx* c, const int32_t* hels, int32_t nh, hipStream_t s) {
+  for (int k = 0; k < nh; ++k)
+    if (hels[k] < 0 || hels[k] >= c->desc->nhel) return fail(ME_EINVAL, "helicity index out of range");
+  hipError_t e = hipMemcpyAsync(c->d_scratch_hels, hels, nh * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(helicities)");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return ME_OK;
+}
+
+double coupling(double alpha_s) { return std::sqrt(4.0 * M_PI * alpha_s); }
+
+}  // namespace
+
+extern "C" {
+
+int me_params_default(me_params* p) {
+  if (!p) return fail(ME_EINVAL, "null params");
+  p->mt = 173.0;
+  p->colorsum_mode = ME_CS_FP64;
+  p->all_helicities = 0;
+  return ME_OK;
+}
+
+int me_init(const char* process, const me_params* p, me_handle* out) {
+  if (!process || !out) return fail(ME_EINVAL, "null argument");
+  *out = nullptr;
+  const me::ProcessDesc* desc = nullptr;
+  for (int i = 0; i < me::kNumProcesses; ++i) {
+    const me::ProcessDesc* d = me::kProcesses[i]();
+    if (std::strcmp(d->name, process) == 0) desc = d;
+  }
+  if (!desc) return fail(ME_EINVAL, std::string("unknown process: ") + process);
+  me_params prm;
+  me_params_default(&prm);
+  if (p) prm = *p;
+  if (!(prm.mt > 0.0)) return fail(ME_EINVAL, "mt must be positive");
+  if (prm.colorsum_mode != ME_CS_FP64) return fail(ME_EINVAL, "unknown colour-sum mode");
+  me_ctx* c = new (std::nothrow) me_ctx;
+  if (!c) return fail(ME_ENOMEM, "host allocation failed");
+  c->desc = desc;
+  c->params = prm;
+  c->good.resize(desc->nhel);
+  for (int k = 0; k < desc->nhel; ++k) c->good[k] = k;
+  hipError_t e = hipMalloc(&c->d_hels, desc->nhel * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&c->d_scratch_hels, desc->nhel * sizeof(int));
+  if (e != hipSuccess) {
+    if (c->d_hels) (void)hipFree(c->d_hels);
+    delete c;
+    return fail(ME_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  int rc = upload_good(c, nullptr);
+  if (rc != ME_OK) {
+    (void)hipFree(c->d_hels);
+    (void)hipFree(c->d_scratch_hels);
+    delete c;
+    return rc;
+  }
+  c->filtered = prm.all_helicities != 0;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(c);
+  }
+  *out = c;
+  g_err.clear();
+  return ME_OK;
+}
+
+int me_finalize(me_handle h) {
+  if (h == nullptr) return ME_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!g_live.erase(h)) return fail(ME_ESTATE, "handle is not live (double finalise?)");
+  }
+  hipError_t e1 = hipFree(h->d_hels);
+  hipError_t e2 = hipFree(h->d_scratch_hels);
+  hipError_t e3 = h->d_partial ? hipFree(h->d_partial) : hipSuccess;
+  delete h;
+  if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
+  if (e3 != hipSuccess) return hip_fail(e3, "hipFree");
+  return ME_OK;
+}
+
+int me_info(me_handle h, int32_t* npar, int32_t* ncolor, int32_t* nhel, int32_t* ndiag) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (npar) *npar = h->desc->npar;
+  if (ncolor) *ncolor = h->desc->ncol;
+  if (nhel) *nhel = h->desc->nhel;
+  if (ndiag) *ndiag = h->desc->ndiag;
+  return ME_OK;
+}
+
+int me_colour_matrix(me_handle h, int32_t* cf_int, int32_t cap, int32_t* denom) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  const int n = h->desc->ncol;
+  if (!cf_int || !denom) return fail(ME_EINVAL, "null argument");
+  if (cap < n * n) return fail(ME_EINVAL, "cf_int buffer too small");
+  for (int i = 0; i < n * n; ++i) cf_int[i] = h->desc->cf_int[i];
+  *denom = h->desc->cf_den;
+  return ME_OK;
+}
+
+int me_good_helicities(me_handle h, int32_t* idx, int32_t cap, int32_t* n_out) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!n_out) return fail(ME_EINVAL, "null n_out");
+  *n_out = (int32_t)h->good.size();
+  if (idx) {
+    if (cap < (int32_t)h->good.size()) return fail(ME_EINVAL, "idx buffer too small");
+    std::copy(h->good.begin(), h->good.end(), idx);
+  }
+  return ME_OK;
+}
+
+int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
+                     const int32_t* hels, int32_t nh, double* out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0 || nh < 0 || nh > h->desc->nhel) return fail(ME_EINVAL, "bad sizes");
+  if (nevt == 0 || nh == 0) return ME_OK;
+  if (!momenta || !hels || !out) return fail(ME_EINVAL, "null pointer");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  hipStream_t s = (hipStream_t)stream;
+  rc = upload_scratch_hels(h, hels, nh, s);
+  if (rc) return rc;
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out, s};
+  hipError_t e = h->desc->helicities(a);
+  if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
+  return ME_OK;
+}
+
+int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
+             const int32_t* hels, int32_t nh, double* out, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0 || nh < 0 || nh > h->desc->nhel) return fail(ME_EINVAL, "bad sizes");
+  if (nevt == 0 || nh == 0) return ME_OK;
+  if (!momenta || !hels || !out) return fail(ME_EINVAL, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  rc = upload_scratch_hels(h, hels, nh, s);
+  if (rc) return rc;
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out, s};
+  hipError_t e = h->desc->jamps(a);
+  if (e != hipSuccess) return hip_fail(e, "jamp kernel launch");
+  return ME_OK;
+}
+
+int me_filter_helicities(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
+                         void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt <= 0 || !momenta) return fail(ME_EINVAL, "helicity filter needs events");
+  const int64_t nt = std::min<int64_t>(nevt, 16);
+  const int nhel = h->desc->nhel;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> all(nhel);
+  for (int k = 0; k < nhel; ++k) all[k] = k;
+  double* d_out = nullptr;
+  hipError_t e = hipMalloc(&d_out, sizeof(double) * nhel * nt);
+  if (e != hipSuccess) return fail(ME_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  rc = me_helicity_sums(h, momenta, nt, alpha_s, all.data(), nhel, d_out, stream);
+  std::vector<double> meh((size_t)nhel * nt);
+  if (rc == ME_OK) {
+    e = hipMemcpyAsync(meh.data(), d_out, sizeof(double) * meh.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "helicity filter readback");
+  }
+  (void)hipFree(d_out);
+  if (rc) return rc;
+  std::vector<double> tot(nt, 0.0);
+  for (int k = 0; k < nhel; ++k)
+    for (int64_t i = 0; i < nt; ++i) tot[i] += meh[k * nt + i];
+  std::vector<int> good;
+  for (int k = 0; k < nhel; ++k) {
+    double best = 0.0;
+    for (int64_t i = 0; i < nt; ++i)
+      if (tot[i] > 0.0) best = std::max(best, meh[k * nt + i] / tot[i]);
+    if (best > 1e-14) good.push_back(k);
+  }
+  if (good.empty()) return fail(ME_EINVAL, "no helicity contributes on the test events");
+  h->good = good;
+  h->filtered = true;
+  return upload_good(h, s);
+}
+
+int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+               void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !out_me2) return fail(ME_EINVAL, "null pointer");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->filtered) {
+    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  const int nhel = (int)h->good.size();
+  const int64_t blocks = (nevt + 63) / 64;
+  // enough waves to fill 256 CUs x 4 SIMDs a few times over, splitting helicities if needed
+  const int64_t target = 4096;
+  int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (target + blocks - 1) / blocks));
+  const int hpc = (nhel + nchunk - 1) / nchunk;
+  nchunk = (nhel + hpc - 1) / hpc;
+  rc = ensure_partial(h, (size_t)nchunk * nevt);
+  if (rc) return rc;
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_hels, nhel, hpc, nchunk,
+                   h->d_partial, s};
+  hipError_t e = h->desc->chunks(a);
+  if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+  const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
+                     h->d_partial, nchunk, nevt, scale, out_me2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  return ME_OK;
+}
+
+const char* me_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

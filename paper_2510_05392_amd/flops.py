@@ -1,0 +1,69 @@
+"""Algorithmic FP64 work of one (event, helicity) of the generated path.
+
+Counting rules: every real add, subtract, multiply, divide and square root is
+one flop (a fused multiply-add is two); complex add = 2, complex multiply = 6,
+complex a + b*c = 8, real x complex = 2, multiplication by +-i and negation
+are free.  The per-routine figures below are read off the device routines
+(csrc/me_device.h) at those rules, counting each distinct intermediate once;
+a process's figure is the sum over its evaluation plan (currents, amplitude
+contractions, colour-flow accumulation) plus the triangular colour quadratic
+form.  This is the number the benchmark's roofline fraction divides by the
+measured kernel time.
+"""
+from __future__ import annotations
+
+ROUTINE = {
+    'G': 24,          # ext_gluon: polar angles (10), components (14)
+    'U': 35,          # ext_ubar: helicity spinor (16), omegas (11), scaling (8)
+    'V': 37,          # ext_v: as ext_ubar plus two sign products
+    'v3': 162,        # v3_current: momenta (16), three dots (58), 1/P^2 (8), combine (80)
+    'v4': 133,        # v4_current: 1/P^2 (9), two complex dots (60), combine (64)
+    'Lh': 72,         # row_vertex: slash blocks (8), 2x2 blocks (56), coupling (8)
+    'Rh': 72,         # vertex_col
+    'L': 79,          # row_prop: q (4), propagator blocks + 1/(q^2-m^2) (11), product (56), scale (8)
+    'R': 79,          # prop_col
+    'K': 80,          # line_current: 8 complex products (48), combinations (24), coupling (8)
+    'dot': 30,        # sdot / vdot: 4 complex products, 3 complex adds
+    'jamp': 2,        # one colour-flow accumulation (complex add)
+}
+
+
+def plan_flops(plan):
+    """FP64 flops per (event, helicity) for the diagram part of an evaluation plan."""
+    total = 0
+    masks = set()
+    for key in plan.order:
+        kind = key[0]
+        if kind == 'J':
+            node = plan.trees.nodes[key[1]]
+            total += ROUTINE[node[0]]
+            if node[0] == 'v4':
+                masks.add(plan.trees.mask[key[1]])
+            else:
+                masks.add(plan.trees.mask[node[1]])
+                masks.add(plan.trees.mask[node[2]])
+        else:
+            total += ROUTINE[kind]
+            if kind in ('L', 'R'):
+                m = 0
+                for t in key[1]:
+                    m |= plan.trees.mask[t]
+                masks.add(m)
+    # momentum sums P(mask) = sum of |mask| external momenta, once per mask
+    total += sum(4 * (bin(m).count('1') - 1) for m in masks)
+    total += ROUTINE['dot'] * len(plan.amps)
+    total += ROUTINE['jamp'] * sum(len(c) for c in plan.colours)
+    return total
+
+
+def colour_sum_flops(ncol):
+    """Triangular quadratic form sum_ij CF_ij Re(J_i^* J_j) with integer CF."""
+    return 2 * ncol * ncol + 4 * ncol
+
+
+def per_event_helicity(name):
+    from .gen import codegen
+    from .gen.topology import Plan
+    n = codegen.PROCESS_NPAR[name] - 2
+    plan = Plan(n)
+    return plan_flops(plan) + colour_sum_flops(len(plan.basis))

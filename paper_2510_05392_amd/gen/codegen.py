@@ -1,0 +1,235 @@
+"""Emit HIP device code for one process from its evaluation plan.
+
+The emitted header defines, for process <name>:
+
+  constexpr int NPAR, NCOL, NHEL, IDEN, CF_DEN
+  __device__ void amplitudes(p, lam, g, mt, jamp)   -- one (event, helicity):
+        external states, currents and amplitudes of every diagram piece,
+        accumulated into the dual amplitudes jamp[NCOL]
+  __device__ double colour_sum(jamp)                 -- sum_ij CF_int[i][j] Re(J_i^* J_j)
+                                                        (triangular: off-diagonal terms
+                                                        once, doubled), not yet / CF_DEN
+  CF_INT[NCOL*NCOL] (host table)
+
+Everything is straight-line code: the generator has already resolved the
+diagram structure, so the compiler sees fixed register operands.
+"""
+from __future__ import annotations
+
+import math
+
+from .colour import colour_matrix
+from .topology import Plan
+
+PROCESS_NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
+
+
+def slot_particle(slot):
+    return slot if slot < 2 else slot + 2
+
+
+def _cx(c):
+    """(re, im) of a colour coefficient in {+-1, +-i}."""
+    c = complex(c)
+    return int(round(c.real)), int(round(c.imag))
+
+
+class Emitter:
+    def __init__(self, name, plan: Plan):
+        self.name = name
+        self.plan = plan
+        self.n = plan.n
+        self.npar = self.n + 2
+        self.lines = []
+        self.names = {}
+        self.masks_done = set()
+        self.basis_index = {p: i for i, p in enumerate(plan.basis)}
+
+    def var(self, key):
+        if key not in self.names:
+            self.names[key] = f"w{len(self.names)}"
+        return self.names[key]
+
+    def mom(self, mask):
+        """Name of the momentum flowing into the diagram through the gluons of `mask`."""
+        name = f"P{mask}"
+        if mask in self.masks_done:
+            return name
+        self.masks_done.add(mask)
+        terms = []
+        for s in range(self.n):
+            if mask >> s & 1:
+                sign = '+' if s < 2 else '-'
+                terms.append((sign, slot_particle(s)))
+        comps = []
+        for u in range(4):
+            expr = ''.join(f" {sg} p[{q}][{u}]" for sg, q in terms).strip()
+            if expr.startswith('+ '):
+                expr = expr[2:]
+            elif expr.startswith('- '):
+                expr = '-' + expr[2:]
+            comps.append(expr)
+        self.lines.append(f"  const double {name}[4] = {{{', '.join(comps)}}};")
+        return name
+
+    def tree_mask(self, t):
+        return self.plan.trees.mask[t]
+
+    def seq_mask(self, seq):
+        m = 0
+        for t in seq:
+            m |= self.tree_mask(t)
+        return m
+
+    def emit_object(self, key):
+        kind = key[0]
+        out = self.var(key)
+        L = self.lines
+        if kind == 'G':
+            s = key[1]
+            q = slot_particle(s)
+            outgoing = 'true' if s >= 2 else 'false'
+            L.append(f"  cx {out}[4]; ext_gluon(p[{q}], lam[{q}], {outgoing}, {out});")
+        elif kind == 'U':
+            L.append(f"  cx {out}[4]; ext_ubar(p[2], lam[2], mt, {out});")
+        elif kind == 'V':
+            L.append(f"  cx {out}[4]; ext_v(p[3], lam[3], mt, {out});")
+        elif kind == 'J':
+            node = self.plan.trees.nodes[key[1]]
+            if node[0] == 'v3':
+                a, b = node[1], node[2]
+                pa, pb = self.mom(self.tree_mask(a)), self.mom(self.tree_mask(b))
+                va, vb = self.var(self.plan.jkey(a)), self.var(self.plan.jkey(b))
+                L.append(f"  cx {out}[4]; v3_current({va}, {pa}, {vb}, {pb}, g, {out});")
+            else:
+                s, a, b, c = node[1], node[2], node[3], node[4]
+                pm = self.mom(self.tree_mask(key[1]))
+                va, vb, vc = (self.var(self.plan.jkey(x)) for x in (a, b, c))
+                L.append(f"  cx {out}[4]; v4_current<{s}>({va}, {vb}, {vc}, {pm}, g, {out});")
+        elif kind == 'Lh':
+            seq = key[1]
+            prev = self.var(('L', seq[:-1]) if len(seq) > 1 else ('U',))
+            j = self.var(self.plan.jkey(seq[-1]))
+            L.append(f"  cx {out}[4]; row_vertex({prev}, {j}, g, {out});")
+        elif kind == 'L':
+            seq = key[1]
+            pm = self.mom(self.seq_mask(seq))
+            src = self.var(('Lh', seq))
+            # momentum along the fermion arrow: p3 - P(seq)
+            L.append(f"  cx {out}[4]; {{ const double q[4] = {{p[2][0] - {pm}[0], p[2][1] - {pm}[1], "
+                     f"p[2][2] - {pm}[2], p[2][3] - {pm}[3]}}; row_prop({src}, q, mt, {out}); }}")
+        elif kind == 'Rh':
+            seq = key[1]
+            nxt = self.var(('R', seq[1:]) if len(seq) > 1 else ('V',))
+            j = self.var(self.plan.jkey(seq[0]))
+            L.append(f"  cx {out}[4]; vertex_col({j}, {nxt}, g, {out});")
+        elif kind == 'R':
+            seq = key[1]
+            pm = self.mom(self.seq_mask(seq))
+            src = self.var(('Rh', seq))
+            # momentum along the fermion arrow: P(seq) - p4
+            L.append(f"  cx {out}[4]; {{ const double q[4] = {{{pm}[0] - p[3][0], {pm}[1] - p[3][1], "
+                     f"{pm}[2] - p[3][2], {pm}[3] - p[3][3]}}; prop_col(q, mt, {src}, {out}); }}")
+        elif kind == 'K':
+            left = self.var(('L', key[1]) if key[1] else ('U',))
+            right = self.var(('R', key[2]) if key[2] else ('V',))
+            L.append(f"  cx {out}[4]; line_current({left}, {right}, g, {out});")
+        else:
+            raise KeyError(key)
+
+    def emit_amp(self, idx, a, b):
+        va, vb = self.var(a), self.var(b)
+        if a[0] == 'K':
+            expr = f"vdot({va}, {vb})"
+        else:
+            expr = f"sdot({va}, {vb})"
+        self.lines.append(f"  {{ const cx a = {expr};")
+        for perm, c in sorted(self.plan.colours[idx].items(), key=lambda kv: self.basis_index[kv[0]]):
+            k = self.basis_index[perm]
+            re, im = _cx(c)
+            if re == 1:
+                self.lines.append(f"    jamp[{k}] = jamp[{k}] + a;")
+            elif re == -1:
+                self.lines.append(f"    jamp[{k}] = jamp[{k}] - a;")
+            elif im == 1:
+                self.lines.append(f"    jamp[{k}] = jamp[{k}] + times_i(a);")
+            elif im == -1:
+                self.lines.append(f"    jamp[{k}] = jamp[{k}] - times_i(a);")
+            else:
+                raise ValueError(c)
+        self.lines.append("  }")
+
+    def amplitudes(self):
+        # emit each object right before its first use, amplitudes in plan order
+        done = set()
+
+        def need(key):
+            if key in done:
+                return
+            for d in self.plan.objects[key]:
+                need(d)
+            self.emit_object(key)
+            done.add(key)
+
+        for idx, a, b in self.plan.amps:
+            need(a)
+            need(b)
+            self.emit_amp(idx, a, b)
+        return self.lines
+
+
+def colour_sum_code(cf, ncol):
+    lines = ["  double acc = 0.0;"]
+    for i in range(ncol):
+        tr = [f"{cf[i][i]}.0 * jamp[{i}].r"]
+        ti = [f"{cf[i][i]}.0 * jamp[{i}].i"]
+        for j in range(i + 1, ncol):
+            c = 2 * cf[i][j]
+            if c == 0:
+                continue
+            tr.append(f"{c}.0 * jamp[{j}].r")
+            ti.append(f"{c}.0 * jamp[{j}].i")
+        lines.append(f"  {{ const double tr = {' + '.join(tr)};")
+        lines.append(f"    const double ti = {' + '.join(ti)};")
+        lines.append(f"    acc += jamp[{i}].r * tr + jamp[{i}].i * ti; }}")
+    lines.append("  return acc;")
+    return lines
+
+
+def generate(name):
+    npar = PROCESS_NPAR[name]
+    n = npar - 2
+    plan = Plan(n)
+    cf, den = colour_matrix(n)
+    ncol = len(plan.basis)
+    iden = 4 * 64 * math.factorial(npar - 4)
+    em = Emitter(name, plan)
+    body = em.amplitudes()
+    out = []
+    out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
+               f"{len(plan.pieces)} colour-structure pieces,")
+    out.append(f"// {len(plan.order)} currents, {ncol} colour flows.  Do not edit.")
+    out.append("#pragma once")
+    out.append('#include "me_device.h"')
+    out.append("namespace me {")
+    flat = ', '.join(str(cf[i][j]) for i in range(ncol) for j in range(ncol))
+    out.append(f"static const int CF_INT_{name}[{ncol * ncol}] = {{{flat}}};")
+    out.append(f"struct {name} {{")
+    out.append(f'  static constexpr const char* NAME = "{name}";')
+    out.append(f"  static constexpr int NPAR = {npar};")
+    out.append(f"  static constexpr int NCOL = {ncol};")
+    out.append(f"  static constexpr int NHEL = {1 << npar};")
+    out.append(f"  static constexpr int IDEN = {iden};")
+    out.append(f"  static constexpr int CF_DEN = {den};")
+    out.append(f"  static constexpr int NDIAG = {plan.ndiagrams};")
+    out.append(f"  static const int* cf_int() {{ return CF_INT_{name}; }}")
+    out.append("  static __device__ __forceinline__ void amplitudes(const double (*p)[4], const int* lam, "
+               "double g, double mt, cx* jamp) {")
+    out.extend('  ' + l for l in body)
+    out.append("  }")
+    out.append("  static __device__ __forceinline__ double colour_sum(const cx* jamp) {")
+    out.extend('  ' + l for l in colour_sum_code(cf, ncol))
+    out.append("  }")
+    out.append("};")
+    out.append("}  // namespace me")
+    return '\n'.join(out) + '\n', plan, (cf, den)

@@ -1,0 +1,52 @@
+"""Compile the host (CPU) build of a generated process for the tests."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, 'paper_2510_05392_amd', 'csrc')
+OUT = os.path.join(ROOT, '_build', 'cpu_harness')
+
+
+def build(name, opt='-O1'):
+    from paper_2510_05392_amd.gen import codegen
+    os.makedirs(OUT, exist_ok=True)
+    src, _, _ = codegen.generate(name)
+    hdr = os.path.join(OUT, f'{name}.inc')
+    if not os.path.exists(hdr) or open(hdr).read() != src:
+        with open(hdr, 'w') as f:
+            f.write(src)
+    lib = os.path.join(OUT, f'harness_{name}.so')
+    deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(HERE, 'harness.cpp')]
+    if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
+        cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE),
+               '-I', CSRC, f'-DPROCESS_HEADER="{hdr}"', f'-DPROCNAME={name}',
+               os.path.join(HERE, 'harness.cpp'), '-o', lib + '.tmp']
+        subprocess.run(cmd, check=True)
+        os.replace(lib + '.tmp', lib)
+    return Harness(lib)
+
+
+class Harness:
+    def __init__(self, path):
+        self.lib = ctypes.CDLL(path)
+        self.lib.harness_ncol.restype = ctypes.c_int
+        self.ncol = self.lib.harness_ncol()
+
+    def eval(self, mom, g, mt, hels, want_jamps=False):
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        meh = np.zeros((len(hels), nevt))
+        jam = np.zeros((len(hels), nevt, self.ncol, 2)) if want_jamps else None
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.harness_eval(mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
+                              ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                              ctypes.c_int(len(hels)), meh.ctypes.data_as(dp),
+                              jam.ctypes.data_as(dp) if want_jamps else None)
+        if want_jamps:
+            return meh, jam[..., 0] + 1j * jam[..., 1]
+        return meh

@@ -1,0 +1,10 @@
+// Test-only stand-in for the HIP runtime header: lets the device arithmetic of
+// the generated process code be compiled for the host so that the generator
+// and the FP64 building blocks can be checked against the oracle on a machine
+// without a GPU.  Never used by the product library.
+#pragma once
+#include <cmath>
+#define __device__
+#define __host__
+#define __forceinline__ inline
+using std::sqrt;

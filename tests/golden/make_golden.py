@@ -1,0 +1,36 @@
+"""Write the stored expected values used by the GPU parity tests.
+
+Calls only the oracle (and the seeded input generator): no value here comes
+from the HIP path.  Run from the repository root:
+
+    python tests/golden/make_golden.py
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import me  # noqa: E402
+from paper_2510_05392_amd import rambo  # noqa: E402
+
+AS = 0.118
+
+
+def main():
+    proc = me.process(7)
+    # g g -> t tbar g g g: three 64-event tiles and a ragged tail
+    mom = rambo.generate(7, 197, 1003)
+    np.savez_compressed(os.path.join(HERE, 'gg_ttxggg_seed1003_first197.npz'), momenta=mom,
+                        me=me.matrix_element(proc, mom, AS))
+    # the 262144-event benchmark workload, 64 events spread over the whole file
+    full = rambo.generate(7, 262144, 1003)
+    idx = np.unique(np.concatenate([np.linspace(0, 262143, 62).astype(int), [1, 262142]]))
+    np.savez_compressed(os.path.join(HERE, 'gg_ttxggg_seed1003_n262144_sampled.npz'), index=idx,
+                        momenta=full[idx], me=me.matrix_element(proc, full[idx], AS))
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports every entry point include/megpu.h declares.
+
+No compute call is made here (no GPU on this machine); the binding's names
+must mirror the header's.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'megpu.h')
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r'^\s*(?:int|const char\s*\*)\s+(me_\w+)\s*\(', text, re.M)))
+
+
+@pytest.fixture(scope='module')
+def libpath():
+    from paper_2510_05392_amd import binding, build
+    if os.path.exists(binding.LIB_PATH):
+        return binding.LIB_PATH
+    # not built yet: build a one-process library just for the symbol check
+    out = os.path.join(ROOT, '_build', 'abi_check', 'libmegpu.so')
+    return build.build(['gg_ttx'], lib=out, verbose=False)
+
+
+def test_header_declares_the_abi():
+    names = declared()
+    for n in ('me_init', 'me_compute', 'me_good_helicities', 'me_finalize', 'me_last_error'):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    lib = ctypes.CDLL(libpath)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_mirrors_header():
+    from paper_2510_05392_amd import binding
+    assert sorted(binding.EXPORTS) == declared()
+
+
+def test_host_only_entry_points(libpath):
+    from paper_2510_05392_amd import binding
+    lib = ctypes.CDLL(libpath)
+    lib.me_params_default.argtypes = [ctypes.POINTER(binding.me_params)]
+    p = binding.me_params()
+    assert lib.me_params_default(ctypes.byref(p)) == 0
+    assert p.mt == 173.0 and p.colorsum_mode == 0 and p.all_helicities == 0
+    assert lib.me_params_default(None) == binding.ME_EINVAL
+    lib.me_last_error.restype = ctypes.c_char_p
+    assert b'null' in lib.me_last_error()
+    # argument validation happens before any device call
+    lib.me_init.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.me_init(None, None, None) == binding.ME_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.me_init(b'gg_ttxq', None, ctypes.byref(h)) == binding.ME_EINVAL
+    assert b'unknown process' in lib.me_last_error()
+    lib.me_finalize.argtypes = [ctypes.c_void_p]
+    assert lib.me_finalize(None) == 0
+    lib.me_compute.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                               ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.me_compute(None, None, 1, 0.118, None, None) == binding.ME_EINVAL
+    bogus = ctypes.c_void_p(0x1000)
+    assert lib.me_compute(bogus, None, 1, 0.118, None, None) == binding.ME_ESTATE

@@ -1,0 +1,198 @@
+"""GPU (HIP) path vs the CPU oracle, through the C ABI.
+
+Bar: FP64 path within 1e-12 relative per event of the oracle (the tolerance
+the FP64 path is held to); per-helicity sums and dual amplitudes are compared
+relative to the largest value of the event.  Sizes span several 64-event
+tiles with a ragged tail; the full-size workloads are checked on sampled
+events.  Every test prints the case it runs before touching the GPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import closed_form, me as ome
+from paper_2510_05392_amd import rambo
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+AS = 0.118
+MT = 173.0
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'golden')
+NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2510_05392_amd import binding as b
+    b.load()
+    return b
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to('cuda')
+
+
+def _compute(binding, name, mom, **kw):
+    m = binding.MatrixElement(name, **kw)
+    out = m.compute(_dev(mom), AS)
+    torch.cuda.synchronize()
+    return m, out.cpu().numpy()
+
+
+@pytest.mark.parametrize('name,nevt,seed', [('gg_ttx', 8192, 1001), ('gg_ttx', 1, 5),
+                                            ('gg_ttxg', 64 * 3 + 17, 1004),
+                                            ('gg_ttxgg', 64 * 3 + 5, 1006)])
+def test_me_vs_oracle(binding, name, nevt, seed):
+    _say(f'case me_vs_oracle {name} nevt={nevt} seed={seed}')
+    npar = NPAR[name]
+    mom = rambo.generate(npar, nevt, seed)
+    _, gpu = _compute(binding, name, mom)
+    ref = ome.matrix_element(ome.process(npar), mom, AS)
+    rel = np.abs(gpu / ref - 1)
+    assert rel.max() < 1e-12, (rel.max(), int(rel.argmax()))
+    if name == 'gg_ttx':
+        cf = closed_form.gg_ttx(mom, AS, MT)
+        assert np.max(np.abs(gpu / cf - 1)) < 1e-12
+
+
+@pytest.mark.parametrize('name,nevt', [('gg_ttx', 70), ('gg_ttxg', 70), ('gg_ttxgg', 67)])
+def test_helicity_sums_and_jamps(binding, name, nevt):
+    _say(f'case helicity_sums_and_jamps {name} nevt={nevt}')
+    npar = NPAR[name]
+    mom = rambo.generate(npar, nevt, 77)
+    proc = ome.process(npar)
+    m = binding.MatrixElement(name)
+    hels = list(range(proc.nhel))
+    dm = _dev(mom)
+    out = torch.empty((len(hels), nevt), dtype=torch.float64, device='cuda')
+    m.me_helicity_sums(dm, nevt, AS, hels, out, torch.cuda.current_stream())
+    jam = torch.empty((len(hels), nevt, proc.ncolour, 2), dtype=torch.float64, device='cuda')
+    m.me_jamps(dm, nevt, AS, hels, jam, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ref = ome.me_helicities(proc, mom, AS)
+    scale = ref.max(axis=0)                              # per event
+    assert np.max(np.abs(out.cpu().numpy() - ref) / scale) < 1e-12
+    jg = jam.cpu().numpy()
+    jg = jg[..., 0] + 1j * jg[..., 1]
+    jo = np.stack([ome.jamps(proc, mom, h, AS) for h in hels])      # [nhel, nevt, ncol]
+    jscale = np.abs(jo).max(axis=(0, 2))                           # per event
+    # the two sides may differ by one phase per (event, helicity): external-state conventions
+    num = (jg * np.conj(jo)).sum(axis=2)
+    den = (np.abs(jo) ** 2).sum(axis=2)
+    big = den > 1e-20 * jscale[None, :] ** 2
+    phase = np.where(big, num / np.where(big, den, 1.0), 1.0)
+    assert np.allclose(np.abs(phase[big]), 1.0, atol=1e-12)
+    dev = np.abs(jg - phase[..., None] * jo).max(axis=(0, 2))
+    assert np.all(dev <= 1e-12 * jscale)
+
+
+def test_good_helicities(binding):
+    _say('case good_helicities')
+    mom = rambo.generate(4, 32, 3)
+    m, _ = _compute(binding, 'gg_ttx', mom)
+    good = m.me_good_helicities()
+    assert sorted(set(range(16)) - set(good)) == [1, 2, 13, 14]
+    for name in ('gg_ttxg', 'gg_ttxgg'):
+        mom = rambo.generate(NPAR[name], 32, 3)
+        m, _ = _compute(binding, name, mom)
+        assert m.me_good_helicities() == list(range(2 ** NPAR[name]))
+
+
+def test_all_helicities_mode_matches(binding):
+    _say('case all_helicities_mode gg_ttx')
+    mom = rambo.generate(4, 100, 9)
+    _, a = _compute(binding, 'gg_ttx', mom)
+    _, b = _compute(binding, 'gg_ttx', mom, all_helicities=True)
+    assert np.max(np.abs(a / b - 1)) < 1e-14
+
+
+def test_deterministic_and_reentrant(binding):
+    _say('case deterministic gg_ttxgg')
+    mom = rambo.generate(6, 200, 13)
+    m = binding.MatrixElement('gg_ttxgg')
+    d = _dev(mom)
+    a = m.compute(d, AS).cpu().numpy()
+    b = m.compute(d, AS).cpu().numpy()
+    assert np.array_equal(a, b)
+    small = m.compute(d[:3].contiguous(), AS).cpu().numpy()
+    assert np.max(np.abs(small / a[:3] - 1)) < 1e-14
+
+
+def test_edge_cases_and_errors(binding):
+    _say('case edge_cases')
+    m = binding.MatrixElement('gg_ttx')
+    d = _dev(rambo.generate(4, 4, 1))
+    out = torch.zeros(4, dtype=torch.float64, device='cuda')
+    m.me_compute(d, 0, AS, out)                      # nevt = 0 is a no-op
+    torch.cuda.synchronize()
+    assert torch.all(out == 0)
+    with pytest.raises(binding.MeError) as e:
+        m.me_compute(d, -1, AS, out)
+    assert e.value.code == binding.ME_EINVAL
+    with pytest.raises(binding.MeError) as e:
+        m.me_compute(None, 4, AS, out)
+    assert e.value.code == binding.ME_EINVAL
+    with pytest.raises(binding.MeError) as e:
+        binding.MatrixElement('gg_ttxq')
+    assert e.value.code == binding.ME_EINVAL
+    lib = binding.load()
+    h = m._h
+    m.me_finalize()
+    import ctypes
+    assert lib.me_finalize(h) == binding.ME_ESTATE
+    assert lib.me_compute(h, ctypes.c_void_p(d.data_ptr()), 4, AS,
+                          ctypes.c_void_p(out.data_ptr()), None) == binding.ME_ESTATE
+    for _ in range(3):                               # repeated init / finalize
+        binding.MatrixElement('gg_ttxg').me_finalize()
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f'missing golden file {path}: run tests/golden/make_golden.py')
+    return np.load(path)
+
+
+def test_ggttggg_vs_oracle_golden(binding):
+    # 3 tiles + ragged tail of g g -> t tbar g g g; expected values written by
+    # tests/golden/make_golden.py from the oracle alone
+    _say('case ggttggg golden 197 events seed 1003')
+    g = _golden('gg_ttxggg_seed1003_first197.npz')
+    mom = rambo.generate(7, 197, 1003)
+    assert np.array_equal(mom, g['momenta'])
+    _, gpu = _compute(binding, 'gg_ttxggg', mom)
+    rel = np.abs(gpu / g['me'] - 1)
+    assert rel.max() < 1e-12, (rel.max(), int(rel.argmax()))
+
+
+@pytest.mark.parametrize('name,nevt,seed,golden', [
+    ('gg_ttxgg', 524288, 1002, None),
+    ('gg_ttxggg', 262144, 1003, 'gg_ttxggg_seed1003_n262144_sampled.npz'),
+])
+def test_full_size_sampled(binding, name, nevt, seed, golden):
+    # the benchmark workloads at full size, in the benchmark's launch configuration;
+    # sampled events are checked against the oracle one by one
+    _say(f'case full_size {name} nevt={nevt}')
+    npar = NPAR[name]
+    mom = rambo.generate(npar, nevt, seed)
+    _, gpu = _compute(binding, name, mom)
+    assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
+    if golden is None:
+        idx = np.linspace(0, nevt - 1, 96).astype(int)
+        ref = ome.matrix_element(ome.process(npar), mom[idx], AS)
+    else:
+        g = _golden(golden)
+        idx = g['index']
+        assert np.array_equal(mom[idx], g['momenta'])
+        ref = g['me']
+    rel = np.abs(gpu[idx] / ref - 1)
+    assert rel.max() < 1e-12, (rel.max(), int(idx[rel.argmax()]))
