@@ -63,6 +63,7 @@ def main():
     ap.add_argument('--nevt', type=int, default=262144)
     ap.add_argument('--alpha-s', type=float, default=0.118)
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--fp64-only', action='store_true', help='skip the mixed-precision run')
     ap.add_argument('--cpu-budget', type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -80,29 +81,41 @@ def main():
     mom = rambo.generate(NPAR[process], nevt, SEED[process])
     dev = torch.device('cuda:0')
     dmom = torch.from_numpy(mom).to(dev)
-    out = torch.empty(nevt, dtype=torch.float64, device=dev)
-    m = binding.MatrixElement(process)
     stream = torch.cuda.current_stream(dev)
-    print(f'# bench {process} nevt={nevt}: warmup {args.warmup}', file=sys.stderr, flush=True)
-    for _ in range(max(1, args.warmup)):
-        m.me_compute(dmom, nevt, args.alpha_s, out, stream)
-    torch.cuda.synchronize()
-    nhel = len(m.me_good_helicities())
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    print(f'# bench timing {args.steps} steps', file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        m.me_compute(dmom, nevt, args.alpha_s, out, stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
+
+    def run(mode):
+        """Time me_compute over the batch in one colour-sum mode; returns (ms/step, ME, nhel)."""
+        out = torch.empty(nevt, dtype=torch.float64, device=dev)
+        m = binding.MatrixElement(process, colorsum_mode=mode)
+        print(f'# bench {process} nevt={nevt} mode={mode}: warmup {args.warmup}', file=sys.stderr,
+              flush=True)
+        for _ in range(max(1, args.warmup)):
+            m.me_compute(dmom, nevt, args.alpha_s, out, stream)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        print(f'# bench timing {args.steps} steps', file=sys.stderr, flush=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            m.me_compute(dmom, nevt, args.alpha_s, out, stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy()
+        if not np.all(np.isfinite(res)):
+            print('non-finite matrix elements', file=sys.stderr)
+            sys.exit(1)
+        return start.elapsed_time(stop) / args.steps, res, len(m.me_good_helicities())
+
+    ms, res, nhel = run(binding.ME_CS_FP64)
     value = nevt / (ms * 1e-3)
-    res = out.cpu().numpy()
-    if not np.all(np.isfinite(res)):
-        print('non-finite matrix elements', file=sys.stderr)
-        sys.exit(1)
+    mixed = None
+    if not args.fp64_only:
+        ms_m, res_m, _ = run(binding.ME_CS_FP16X2)
+        rel = np.abs(res_m / res - 1)
+        mixed = {'colorsum': 'split FP16 hi+lo on MFMA, FP32 accumulation, FP64 row dots',
+                 'value': nevt / (ms_m * 1e-3), 'unit': 'ME evals/s', 'ms_per_step': ms_m,
+                 'max_rel_err_vs_fp64': float(rel.max()), 'rms_rel_err_vs_fp64': float(np.sqrt(np.mean(rel ** 2))),
+                 'stated_bound': 1e-5}
 
     f_unit = flops.per_event_helicity(process)
     step_flops = f_unit * nhel * nevt
@@ -118,8 +131,10 @@ def main():
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS, 'traffic': None,
                      'flops_per_event_helicity': f_unit,
-                     'kernel': f'me_chunk_kernel<{process}> (+ reduce_chunks_kernel, <0.1%)'},
+                     'kernel': f'me_kernel<{process}> (+ reduce_chunks_kernel, <0.1%)'},
     }
+    if mixed is not None:
+        line['mixed'] = mixed
     if not args.no_cpu_baseline:
         print('# bench cpu baseline (oracle)', file=sys.stderr, flush=True)
         line['cpu_baseline'] = cpu_baseline(process, mom, args.alpha_s, args.cpu_budget)

@@ -44,7 +44,15 @@ extern "C" {
 #define ME_ESTATE (-4)  /* handle already finalised */
 
 /* colour-sum arithmetic */
-#define ME_CS_FP64 0    /* FP64 quadratic form on the vector ALUs */
+#define ME_CS_FP64 0    /* FP64 triangular quadratic form on the vector ALUs, fused with the diagrams */
+#define ME_CS_FP16X2 1  /* matrix cores: amplitudes split hi + lo in FP16 (rows scaled by a power
+                           of two), integer colour matrix exact in FP16, FP32 accumulation,
+                           final row dot products in FP64 */
+#define ME_CS_BF16X2 2  /* as ME_CS_FP16X2 in BF16 (no scaling; a colour matrix with more than 8
+                           significant bits is split hi + lo as well) */
+
+/* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
+#define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 
 typedef struct me_ctx* me_handle;
 
@@ -95,8 +103,13 @@ int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double al
 int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
              const int32_t* hels, int32_t nh, double* out, void* stream);
 
-/* Release the handle and everything it owns.  Double finalise is an error
- * (ME_ESTATE) only if the pointer is reused after being freed; passing NULL is a no-op. */
+/* Switch the colour-sum arithmetic of a handle (ME_CS_*).  In the matrix-core
+ * modes the dual amplitudes of up to ME_JAMP_SCRATCH_BYTES are staged in a
+ * library-owned device buffer between the diagram and colour-sum kernels. */
+int me_set_colorsum_mode(me_handle h, int mode);
+
+/* Release the handle and everything it owns.  Finalising a handle twice, or
+ * using it afterwards, returns ME_ESTATE; passing NULL is a no-op. */
 int me_finalize(me_handle h);
 
 /* Message for the last error on this thread ("" if none). */

@@ -20,10 +20,12 @@ ME_ENOMEM = -2
 ME_EHIP = -3
 ME_ESTATE = -4
 ME_CS_FP64 = 0
+ME_CS_FP16X2 = 1
+ME_CS_BF16X2 = 2
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
-           'me_jamps', 'me_finalize', 'me_last_error']
+           'me_jamps', 'me_set_colorsum_mode', 'me_finalize', 'me_last_error']
 
 
 class MeError(RuntimeError):
@@ -58,6 +60,7 @@ def load(path=LIB_PATH):
     lib.me_colour_matrix.argtypes = [vp, i32p, ctypes.c_int32, i32p]
     lib.me_helicity_sums.argtypes = [vp, vp, i64, ctypes.c_double, i32p, ctypes.c_int32, vp, vp]
     lib.me_jamps.argtypes = [vp, vp, i64, ctypes.c_double, i32p, ctypes.c_int32, vp, vp]
+    lib.me_set_colorsum_mode.argtypes = [vp, ctypes.c_int]
     lib.me_finalize.argtypes = [vp]
     lib.me_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-1]:
@@ -85,12 +88,14 @@ def _stream(stream):
 class MatrixElement:
     """One handle of the C ABI for one process."""
 
-    def __init__(self, process: str, mt: float = 173.0, all_helicities: bool = False):
+    def __init__(self, process: str, mt: float = 173.0, all_helicities: bool = False,
+                 colorsum_mode: int = ME_CS_FP64):
         lib = load()
         p = me_params()
         _check(lib.me_params_default(ctypes.byref(p)))
         p.mt = mt
         p.all_helicities = int(all_helicities)
+        p.colorsum_mode = int(colorsum_mode)
         h = ctypes.c_void_p()
         _check(lib.me_init(process.encode(), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -128,6 +133,9 @@ class MatrixElement:
         arr = (ctypes.c_int32 * len(hels))(*hels)
         _check(load().me_jamps(self._h, _ptr(momenta), nevt, alpha_s, arr, len(hels),
                                _ptr(out), _stream(stream)))
+
+    def me_set_colorsum_mode(self, mode):
+        _check(load().me_set_colorsum_mode(self._h, int(mode)))
 
     def me_finalize(self):
         if self._h is not None:

@@ -77,10 +77,13 @@ def _compile(src, obj, extra_deps, build_dir):
     if (os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
             and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps)):
         return obj, False
-    cmd = [HIPCC, *flags, '-c', src, '-o', obj + '.tmp']
+    # the resource-usage remarks (registers, spills, occupancy) are kept next to the object
+    cmd = [HIPCC, *flags, '-Rpass-analysis=kernel-resource-usage', '-c', src, '-o', obj + '.tmp']
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f'hipcc failed for {src}:\n{r.stderr[-4000:]}')
+    with open(obj + '.resources.txt', 'w') as f:
+        f.write('\n'.join(l for l in r.stderr.splitlines() if 'remark' in l) + '\n')
     os.replace(obj + '.tmp', obj)
     with open(stamp, 'w') as f:
         f.write(key)

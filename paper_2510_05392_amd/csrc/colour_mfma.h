@@ -1,0 +1,139 @@
+// Colour sum on the matrix cores: ME_row = J^H CF J = A^T CF A + B^T CF B for
+// J = A + iB (the paper's colour-sum equation), evaluated as a GEMM
+//     D = CF . X^T,   X = [A; B] rows split as X = X_hi + X_lo in FP16 or BF16,
+// with FP32 accumulation on v_mfma_f32_32x32x16_{f16,bf16}, followed by the row
+// dot products sum_i X[j][i] D[i][j] in FP64 against the unsplit FP64 amplitudes.
+//
+// Tile: one 64-lane wavefront handles 16 (event, helicity) rows = 32 X rows (the
+// real parts, then the imaginary parts) as the N = 32 dimension; the colour index
+// is both M (blocks of 32) and K (steps of 16).  The integer colour matrix is the
+// A operand (zero padded); it is exact in the input format (FP16 holds 11
+// significant bits, BF16 8: a BF16 matrix that needs more is split into hi + lo).
+// FP16 rows are first scaled by an exact power of two so that max |X| is in
+// [1, 2); the scale is undone on the FP64 result.
+//
+// MFMA operand layouts (32x32x16, wave64): A[i][k]: lane l holds i = l % 32,
+// k = 8 (l / 32) + t (t = 0..7); B[k][j]: j = l % 32, k = 8 (l / 32) + t;
+// D[i][j] (16 accumulators): j = l % 32, i = 8 (v / 4) + 4 (l / 32) + (v % 4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+enum { CS_FMT_FP16 = 0, CS_FMT_BF16 = 1 };
+
+template <int FMT>
+struct cs_types;
+template <>
+struct cs_types<CS_FMT_FP16> {
+  typedef half8 vec;
+  typedef _Float16 elem;
+  static __device__ __forceinline__ f32x16 mfma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct cs_types<CS_FMT_BF16> {
+  typedef bf16x8 vec;
+  typedef __bf16 elem;
+  static __device__ __forceinline__ f32x16 mfma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// J: [nrow][NCOL][2] FP64.  cf_hi / cf_lo: [MB*32][KS*16] in the MFMA format
+// (cf_lo may be null).  out[row] = ME_row * inv_den.
+template <int NCOL, int FMT>
+__global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restrict__ J, int64_t nrow,
+                                                         const void* __restrict__ cf_hi_raw,
+                                                         const void* __restrict__ cf_lo_raw,
+                                                         double inv_den, double* __restrict__ out) {
+  typedef cs_types<FMT> T;
+  typedef typename T::vec vec;
+  typedef typename T::elem elem;
+  constexpr int KS = (NCOL + 15) / 16;   // K steps
+  constexpr int MB = (NCOL + 31) / 32;   // M blocks
+  constexpr int KP = KS * 16;            // padded row length of the CF tables
+  const vec* cf_hi = reinterpret_cast<const vec*>(cf_hi_raw);
+  const vec* cf_lo = reinterpret_cast<const vec*>(cf_lo_raw);
+
+  const int l = threadIdx.x;
+  const int j = l & 31;                  // X row in the tile (N index)
+  const int half = l >> 5;               // which 8 of the 16 K values
+  const int r = j & 15;                  // (event, helicity) row in the tile
+  const int part = j >> 4;               // 0 = real parts, 1 = imaginary parts
+  const int64_t row = (int64_t)blockIdx.x * 16 + r;
+  const bool valid = row < nrow;
+  const double* x = J + (valid ? row : 0) * (NCOL * 2) + part;
+
+  // power-of-two scale of the row (both parts) so that max|X| is in [1, 2)
+  double scale = 1.0, unscale = 1.0;
+  if (FMT == CS_FMT_FP16) {
+    double m = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int c = 16 * kk + 8 * half + t;
+        if (c < NCOL && valid) m = fmax(m, fabs(x[2 * c]));
+      }
+    m = fmax(m, __shfl_xor(m, 16));
+    m = fmax(m, __shfl_xor(m, 32));
+    if (m > 0.0) {
+      const int e = ilogb(m);
+      scale = ldexp(1.0, -e);
+      unscale = ldexp(1.0, e);
+    }
+  }
+
+  f32x16 acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[mb][v] = 0.0f;
+
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    vec bh, bl;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int c = 16 * kk + 8 * half + t;
+      const double v = (c < NCOL && valid) ? x[2 * c] * scale : 0.0;
+      const elem hi = (elem)v;
+      bh[t] = hi;
+      bl[t] = (elem)(v - (double)hi);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int idx = ((32 * mb + j) * KP + 16 * kk + 8 * half) / 8;
+      const vec a = cf_hi[idx];
+      acc[mb] = T::mfma(a, bh, acc[mb]);
+      acc[mb] = T::mfma(a, bl, acc[mb]);
+      if (cf_lo) {
+        const vec a2 = cf_lo[idx];
+        acc[mb] = T::mfma(a2, bh, acc[mb]);
+        acc[mb] = T::mfma(a2, bl, acc[mb]);
+      }
+    }
+  }
+
+  // row dot products in FP64: sum_i X[j][i] D[i][j]
+  double s = 0.0;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
+      if (i < NCOL && valid) s += x[2 * i] * (double)acc[mb][v];
+    }
+  s += __shfl_xor(s, 32);   // the two halves of the M rows
+  s += __shfl_xor(s, 16);   // real + imaginary parts
+  if (l < 16 && valid) out[row] = s * unscale * inv_den;
+}
+
+}  // namespace me

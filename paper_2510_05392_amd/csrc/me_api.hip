@@ -54,8 +54,12 @@ struct me_ctx {
   std::vector<int> good;      // host copy of the good helicities
   int* d_hels = nullptr;      // device, good helicities (capacity nhel)
   int* d_scratch_hels = nullptr;  // device, caller-chosen helicities (capacity nhel)
-  double* d_partial = nullptr;
+  double* d_partial = nullptr;    // per-chunk partial sums, or per-row colour sums
   size_t partial_cap = 0;     // doubles
+  double* d_jamps = nullptr;  // staged dual amplitudes (matrix-core colour-sum modes)
+  size_t jamps_cap = 0;       // doubles
+  void* d_cf_hi = nullptr;    // colour matrix in the MFMA input format
+  void* d_cf_lo = nullptr;    // its low half when the matrix is split (BF16)
   bool filtered = false;
 };
 
@@ -110,6 +114,103 @@ int upload_scratch_hels(me_ctx* c, const int32_t* hels, int32_t nh, hipStream_t 
 
 double coupling(double alpha_s) { return std::sqrt(4.0 * M_PI * alpha_s); }
 
+int ensure_buffer(double** buf, size_t* cap, size_t n, const char* what) {
+  if (n <= *cap) return ME_OK;
+  if (*buf) {
+    hipError_t e = hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+  }
+  hipError_t e = hipMalloc(buf, n * sizeof(double));
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return fail(ME_ENOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+  }
+  *cap = n;
+  return ME_OK;
+}
+
+// Exact FP16 / BF16 encodings of small integers (the colour matrix entries).
+bool half_bits(int v, uint16_t* out) {
+  if (v == 0) { *out = 0; return true; }
+  const uint16_t sign = v < 0 ? 0x8000 : 0;
+  unsigned a = (unsigned)(v < 0 ? -v : v);
+  int e = 31 - __builtin_clz(a);
+  if (e > 15) return false;
+  unsigned mant;
+  if (e <= 10) {
+    mant = (a << (10 - e)) & 0x3ff;
+  } else {
+    if (a & ((1u << (e - 10)) - 1)) return false;   // not representable
+    mant = (a >> (e - 10)) & 0x3ff;
+  }
+  *out = sign | (uint16_t)((e + 15) << 10) | (uint16_t)mant;
+  return true;
+}
+
+bool bf16_bits(int v, uint16_t* out) {
+  const float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if (u & 0xffff) return false;
+  *out = (uint16_t)(u >> 16);
+  return true;
+}
+
+// value of the top 8 significant bits of v (so that v - hi has the rest)
+int bf16_high_part(int v) {
+  unsigned a = (unsigned)(v < 0 ? -v : v);
+  if (a == 0) return 0;
+  const int e = 31 - __builtin_clz(a);
+  if (e >= 8) a &= ~((1u << (e - 7)) - 1);
+  return v < 0 ? -(int)a : (int)a;
+}
+
+void free_tables(me_ctx* c) {
+  if (c->d_cf_hi) (void)hipFree(c->d_cf_hi);
+  if (c->d_cf_lo) (void)hipFree(c->d_cf_lo);
+  c->d_cf_hi = c->d_cf_lo = nullptr;
+}
+
+// Colour matrix tables for the matrix-core modes: [32*MB][16*KS] zero padded.
+int build_tables(me_ctx* c, int mode) {
+  free_tables(c);
+  if (mode == ME_CS_FP64) return ME_OK;
+  const int n = c->desc->ncol;
+  const int kp = ((n + 15) / 16) * 16, mp = ((n + 31) / 32) * 32;
+  std::vector<uint16_t> hi((size_t)mp * kp, 0), lo((size_t)mp * kp, 0);
+  bool split = false;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const int v = c->desc->cf_int[i * n + k];
+      uint16_t bh = 0, bl = 0;
+      if (mode == ME_CS_FP16X2) {
+        if (!half_bits(v, &bh)) return fail(ME_EINVAL, "colour matrix is not exact in FP16");
+      } else {
+        const int vh = bf16_high_part(v);
+        if (!bf16_bits(vh, &bh) || !bf16_bits(v - vh, &bl))
+          return fail(ME_EINVAL, "colour matrix is not exact in two BF16 parts");
+        if (v != vh) split = true;
+      }
+      hi[(size_t)i * kp + k] = bh;
+      lo[(size_t)i * kp + k] = bl;
+    }
+  hipError_t e = hipMalloc(&c->d_cf_hi, hi.size() * 2);
+  if (e == hipSuccess) e = hipMemcpy(c->d_cf_hi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess && split) {
+    e = hipMalloc(&c->d_cf_lo, lo.size() * 2);
+    if (e == hipSuccess) e = hipMemcpy(c->d_cf_lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    free_tables(c);
+    return hip_fail(e, "colour-matrix tables");
+  }
+  return ME_OK;
+}
+
+bool valid_mode(int m) { return m == ME_CS_FP64 || m == ME_CS_FP16X2 || m == ME_CS_BF16X2; }
+
 }  // namespace
 
 extern "C" {
@@ -135,7 +236,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   me_params_default(&prm);
   if (p) prm = *p;
   if (!(prm.mt > 0.0)) return fail(ME_EINVAL, "mt must be positive");
-  if (prm.colorsum_mode != ME_CS_FP64) return fail(ME_EINVAL, "unknown colour-sum mode");
+  if (!valid_mode(prm.colorsum_mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
   me_ctx* c = new (std::nothrow) me_ctx;
   if (!c) return fail(ME_ENOMEM, "host allocation failed");
   c->desc = desc;
@@ -150,9 +251,11 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
     return fail(ME_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
   int rc = upload_good(c, nullptr);
+  if (rc == ME_OK) rc = build_tables(c, prm.colorsum_mode);
   if (rc != ME_OK) {
     (void)hipFree(c->d_hels);
     (void)hipFree(c->d_scratch_hels);
+    free_tables(c);
     delete c;
     return rc;
   }
@@ -175,6 +278,8 @@ int me_finalize(me_handle h) {
   hipError_t e1 = hipFree(h->d_hels);
   hipError_t e2 = hipFree(h->d_scratch_hels);
   hipError_t e3 = h->d_partial ? hipFree(h->d_partial) : hipSuccess;
+  if (h->d_jamps) (void)hipFree(h->d_jamps);
+  free_tables(h);
   delete h;
   if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFree");
@@ -226,9 +331,16 @@ int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double al
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
-  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out, s};
-  hipError_t e = h->desc->helicities(a);
+  // one helicity per chunk: the per-chunk partial sums are the per-helicity sums
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out,
+                   nullptr, s};
+  hipError_t e = h->desc->launch(a);
   if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
+  const int64_t n = nevt * nh;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, 1,
+                     n, 1.0 / h->desc->cf_den, out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "scale kernel launch");
   return ME_OK;
 }
 
@@ -242,8 +354,9 @@ int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
-  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out, s};
-  hipError_t e = h->desc->jamps(a);
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, nullptr,
+                   out, s};
+  hipError_t e = h->desc->launch(a);
   if (e != hipSuccess) return hip_fail(e, "jamp kernel launch");
   return ME_OK;
 }
@@ -301,23 +414,65 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
     if (rc) return rc;
   }
   const int nhel = (int)h->good.size();
-  const int64_t blocks = (nevt + 63) / 64;
-  // enough waves to fill 256 CUs x 4 SIMDs a few times over, splitting helicities if needed
-  const int64_t target = 4096;
-  int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (target + blocks - 1) / blocks));
-  const int hpc = (nhel + nchunk - 1) / nchunk;
-  nchunk = (nhel + hpc - 1) / hpc;
-  rc = ensure_partial(h, (size_t)nchunk * nevt);
+  const double g = coupling(alpha_s);
+  if (h->params.colorsum_mode == ME_CS_FP64) {
+    const int64_t blocks = (nevt + 63) / 64;
+    // enough waves to fill 256 CUs x 4 SIMDs a few times over, splitting helicities if needed
+    const int64_t target = 4096;
+    int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (target + blocks - 1) / blocks));
+    const int hpc = (nhel + nchunk - 1) / nchunk;
+    nchunk = (nhel + hpc - 1) / hpc;
+    rc = ensure_partial(h, (size_t)nchunk * nevt);
+    if (rc) return rc;
+    me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
+                     h->d_partial, nullptr, s};
+    hipError_t e = h->desc->launch(a);
+    if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+    const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
+                       h->d_partial, nchunk, nevt, scale, out_me2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    return ME_OK;
+  }
+  // matrix-core colour sum: stage the dual amplitudes of an event chunk, one row per
+  // (helicity, event), then colour-sum every row and reduce over helicities
+  const int ncol = h->desc->ncol;
+  const int npar = h->desc->npar;
+  const size_t row_doubles = (size_t)ncol * 2;
+  int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles * nhel));
+  chunk = std::max<int64_t>(64, (chunk / 64) * 64);
+  chunk = std::min<int64_t>(chunk, nevt);
+  rc = ensure_buffer(&h->d_jamps, &h->jamps_cap, (size_t)chunk * nhel * row_doubles, "jamps");
   if (rc) return rc;
-  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_hels, nhel, hpc, nchunk,
-                   h->d_partial, s};
-  hipError_t e = h->desc->chunks(a);
-  if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
-  const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
-  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
-                     h->d_partial, nchunk, nevt, scale, out_me2);
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  rc = ensure_partial(h, (size_t)chunk * nhel);
+  if (rc) return rc;
+  const int fmt = h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1;
+  for (int64_t off = 0; off < nevt; off += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, nevt - off);
+    me::LaunchArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, 1, nhel,
+                     nullptr, h->d_jamps, s};
+    hipError_t e = h->desc->launch(a);
+    if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+    me::ColourArgs ca{h->d_jamps, n * nhel, fmt, h->d_cf_hi, h->d_cf_lo,
+                      1.0 / h->desc->cf_den, h->d_partial, s};
+    e = h->desc->colour(ca);
+    if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       h->d_partial, nhel, n, 1.0 / h->desc->iden, out_me2 + off);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  }
+  return ME_OK;
+}
+
+int me_set_colorsum_mode(me_handle h, int mode) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!valid_mode(mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
+  rc = build_tables(h, mode);
+  if (rc) return rc;
+  h->params.colorsum_mode = mode;
   return ME_OK;
 }
 

@@ -277,53 +277,87 @@ __device__ __forceinline__ void line_current(const cx* r, const cx* c, double g,
 
 // ------------------------------------------------------------------ gluon vertices
 
-// ggg vertex with legs (parent, A, B), all momenta incoming (parent: -(PA+PB)),
-// contracted with the child currents, times the gluon propagator -i/P^2 and g.
-__device__ __forceinline__ void v3_current(const cx* ja, const double* pa, const cx* jb,
-                                           const double* pb, double g, cx* out) {
-  double p[4], kma[4], pbk[4], pamb[4];
+// ggg vertex with one open leg.  (ja, pa) and (jb, pb) are the two other legs in
+// cyclic order after the open one, with their incoming momenta; the open leg's
+// incoming momentum is k = -(pa + pb).  The colour-stripped vertex
+//   V^mu = ja^mu ((k - pa).jb) + (ja.jb) (pa - pb)^mu + jb^mu ((pb - k).ja)
+// is returned as out = i f V, where f carries g and a gluon propagator.
+__device__ __forceinline__ void v3_open(const cx* ja, const double* pa, const cx* jb,
+                                        const double* pb, double f, cx* out) {
+  double kma[4], pbk[4], pamb[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    p[u] = pa[u] + pb[u];
-    kma[u] = -p[u] - pa[u];   // k1 - k2 with k1 = -P
-    pbk[u] = pb[u] + p[u];    // k3 - k1
-    pamb[u] = pa[u] - pb[u];  // k2 - k3
+    const double k = -(pa[u] + pb[u]);
+    kma[u] = k - pa[u];
+    pbk[u] = pb[u] - k;
+    pamb[u] = pa[u] - pb[u];
   }
   const cx c1 = rdot(kma, jb);
   const cx c2 = vdot(ja, jb);
   const cx c3 = rdot(pbk, ja);
-  const double f = -g / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     cx v = ja[u] * c1;
     v = fma(v, jb[u], c3);
     v = v + pamb[u] * c2;
-    out[u] = times_i(f * v);   // (-i/P^2) g v
+    out[u] = times_i(f * v);
   }
 }
 
-// gggg vertex, colour structure s, legs (parent, b, c, d) = (parent, A, B, C):
-//   s = 0: g^{mu rho} g^{nu sig} - g^{mu sig} g^{nu rho}
-//   s = 1: g^{mu nu} g^{rho sig} - g^{mu sig} g^{nu rho}
-//   s = 2: g^{mu nu} g^{rho sig} - g^{mu rho} g^{nu sig}
-// times -i g^2 and the propagator -i/P^2: overall -g^2/P^2.
+__device__ __forceinline__ double msq(const double* p) {
+  return p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3];
+}
+
+// Gluon current of a ggg vertex with children (A, B): propagator -i/P^2 on the
+// parent line, P = PA + PB:  out = (-i g / P^2) V.
+__device__ __forceinline__ void v3_current(const cx* ja, const double* pa, const cx* jb,
+                                           const double* pb, double g, cx* out) {
+  double p[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) p[u] = pa[u] + pb[u];
+  v3_open(ja, pa, jb, pb, -g / msq(p), out);
+}
+
+// gggg vertex, colour structure S, legs (0, 1, 2, 3) = (a, b, c, d) with Lorentz part
+//   S = 0: g^{ac} g^{bd} - g^{ad} g^{bc}
+//   S = 1: g^{ab} g^{cd} - g^{ad} g^{bc}
+//   S = 2: g^{ab} g^{cd} - g^{ac} g^{bd}
+// contracted with the vectors of the three legs other than H; leg H stays open.
+// out = f * (result), f carrying -i g^2 and a propagator factor.
+template <int S, int H>
+__device__ __forceinline__ void v4_open(const cx* v0, const cx* v1, const cx* v2, const cx* v3,
+                                        double f, cx* out) {
+  const cx* v[4] = {v0, v1, v2, v3};
+  // two terms (sign, a, b, c, d) = sign * g^{ab} g^{cd}
+  constexpr int T[3][2][5] = {{{1, 0, 2, 1, 3}, {-1, 0, 3, 1, 2}},
+                              {{1, 0, 1, 2, 3}, {-1, 0, 3, 1, 2}},
+                              {{1, 0, 1, 2, 3}, {-1, 0, 2, 1, 3}}};
+  cx acc[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int sg = T[S][t][0], a = T[S][t][1], b = T[S][t][2], c = T[S][t][3], d = T[S][t][4];
+    int partner;
+    cx dot;
+    if (a == H || b == H) {
+      partner = a == H ? b : a;
+      dot = vdot(v[c], v[d]);
+    } else {
+      partner = c == H ? d : c;
+      dot = vdot(v[a], v[b]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = sg > 0 ? acc[u] + v[partner][u] * dot : acc[u] - v[partner][u] * dot;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) out[u] = f * acc[u];
+}
+
+// Gluon current of a gggg piece with children (A, B, C) on legs (b, c, d):
+// -i g^2 from the vertex and -i/P^2 from the parent propagator give -g^2/P^2.
 template <int S>
 __device__ __forceinline__ void v4_current(const cx* ja, const cx* jb, const cx* jc,
                                            const double* p, double g, cx* out) {
-  const double f = -g * g / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
-  if (S == 0) {
-    const cx x = vdot(ja, jc), y = vdot(ja, jb);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) out[u] = f * (jb[u] * x - jc[u] * y);
-  } else if (S == 1) {
-    const cx x = vdot(jb, jc), y = vdot(ja, jb);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) out[u] = f * (ja[u] * x - jc[u] * y);
-  } else {
-    const cx x = vdot(jb, jc), y = vdot(ja, jc);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) out[u] = f * (ja[u] * x - jb[u] * y);
-  }
+  v4_open<S, 0>(nullptr, ja, jb, jc, -g * g / msq(p), out);
 }
 
 }  // namespace me

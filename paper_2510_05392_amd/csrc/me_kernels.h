@@ -14,6 +14,7 @@
 
 #include "me_device.h"
 #include "me_process.h"
+#include "colour_mfma.h"
 
 namespace me {
 
@@ -34,13 +35,17 @@ __device__ __forceinline__ void helicity_signs(int h, int* lam) {
   for (int q = 0; q < P::NPAR; ++q) lam[q] = ((h >> (P::NPAR - 1 - q)) & 1) ? 1 : -1;
 }
 
-// partial[c * nevt + e] = sum over the helicities of chunk c of sum_ij CF_int Re(J_i^* J_j)
+// One lane = one event; blockIdx.y = helicity chunk c.  For every good helicity
+// of the chunk the lane evaluates all diagrams into the dual amplitudes and
+// either accumulates sum_ij CF_int Re(J_i^* J_j) into partial[c * nevt + e]
+// (jamp_out == nullptr) or, with one helicity per chunk, stores the dual
+// amplitudes to jamp_out[((c * nevt + e) * NCOL + i) * 2 + {0, 1}].
 template <class P>
-__global__ void __launch_bounds__(64) me_chunk_kernel(const double* __restrict__ mom, int64_t nevt,
-                                                      double g, double mt,
-                                                      const int* __restrict__ hels, int nhel,
-                                                      int hel_per_chunk,
-                                                      double* __restrict__ partial) {
+__global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, int64_t nevt,
+                                                double g, double mt, const int* __restrict__ hels,
+                                                int nhel, int hel_per_chunk,
+                                                double* __restrict__ partial,
+                                                double* __restrict__ jamp_out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (e >= nevt) return;
@@ -52,89 +57,60 @@ __global__ void __launch_bounds__(64) me_chunk_kernel(const double* __restrict__
   for (int k = k0; k < k1; ++k) {
     int lam[P::NPAR];
     helicity_signs<P>(hels[k], lam);
+    // Opaque copy of the momenta: keeps the compiler from hoisting the
+    // helicity-independent parts of the diagram code out of this loop, which
+    // would keep hundreds of intermediates alive across iterations.
+    double q[P::NPAR][4];
+#pragma unroll
+    for (int a = 0; a < P::NPAR; ++a) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        q[a][u] = p[a][u];
+        asm volatile("" : "+v"(q[a][u]));
+      }
+    }
     cx jamp[P::NCOL];
 #pragma unroll
     for (int i = 0; i < P::NCOL; ++i) jamp[i] = cx{0.0, 0.0};
-    P::amplitudes(p, lam, g, mt, jamp);
-    acc += P::colour_sum(jamp);
+    P::amplitudes(q, lam, g, mt, jamp);
+    if (jamp_out) {
+      double* dst = jamp_out + ((int64_t)k * nevt + e) * (P::NCOL * 2);
+#pragma unroll
+      for (int i = 0; i < P::NCOL; ++i) {
+        dst[2 * i] = jamp[i].r;
+        dst[2 * i + 1] = jamp[i].i;
+      }
+    } else {
+      acc += P::colour_sum(jamp);
+    }
   }
-  partial[(int64_t)c * nevt + e] = acc;
-}
-
-// per-helicity colour sums, out[k * nevt + e] = ME_h / CF_DEN (helicity filter, tests)
-template <class P>
-__global__ void __launch_bounds__(64) me_helicity_kernel(const double* __restrict__ mom, int64_t nevt,
-                                                         double g, double mt,
-                                                         const int* __restrict__ hels,
-                                                         double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (e >= nevt) return;
-  double p[P::NPAR][4];
-  load_momenta<P>(mom, e, p);
-  int lam[P::NPAR];
-  helicity_signs<P>(hels[k], lam);
-  cx jamp[P::NCOL];
-#pragma unroll
-  for (int i = 0; i < P::NCOL; ++i) jamp[i] = cx{0.0, 0.0};
-  P::amplitudes(p, lam, g, mt, jamp);
-  out[(int64_t)k * nevt + e] = P::colour_sum(jamp) / P::CF_DEN;
-}
-
-// dual amplitudes, out[((k * nevt + e) * NCOL + i) * 2 + {0,1}] (tests)
-template <class P>
-__global__ void __launch_bounds__(64) me_jamp_kernel(const double* __restrict__ mom, int64_t nevt,
-                                                     double g, double mt,
-                                                     const int* __restrict__ hels,
-                                                     double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (e >= nevt) return;
-  double p[P::NPAR][4];
-  load_momenta<P>(mom, e, p);
-  int lam[P::NPAR];
-  helicity_signs<P>(hels[k], lam);
-  cx jamp[P::NCOL];
-#pragma unroll
-  for (int i = 0; i < P::NCOL; ++i) jamp[i] = cx{0.0, 0.0};
-  P::amplitudes(p, lam, g, mt, jamp);
-  double* dst = out + ((int64_t)k * nevt + e) * (P::NCOL * 2);
-#pragma unroll
-  for (int i = 0; i < P::NCOL; ++i) {
-    dst[2 * i] = jamp[i].r;
-    dst[2 * i + 1] = jamp[i].i;
-  }
+  if (!jamp_out) partial[(int64_t)c * nevt + e] = acc;
 }
 
 template <class P>
-hipError_t launch_chunks(const LaunchArgs& a) {
+hipError_t launch(const LaunchArgs& a) {
   const dim3 grid((unsigned)((a.nevt + 63) / 64), (unsigned)a.nchunk);
-  hipLaunchKernelGGL(me_chunk_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt,
-                     a.hels, a.nhel, a.hel_per_chunk, a.out);
+  hipLaunchKernelGGL(me_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt, a.hels,
+                     a.nhel, a.hel_per_chunk, a.out, a.jamp_out);
   return hipGetLastError();
 }
 
 template <class P>
-hipError_t launch_helicities(const LaunchArgs& a) {
-  const dim3 grid((unsigned)((a.nevt + 63) / 64), (unsigned)a.nhel);
-  hipLaunchKernelGGL(me_helicity_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt,
-                     a.hels, a.out);
-  return hipGetLastError();
-}
-
-template <class P>
-hipError_t launch_jamps(const LaunchArgs& a) {
-  const dim3 grid((unsigned)((a.nevt + 63) / 64), (unsigned)a.nhel);
-  hipLaunchKernelGGL(me_jamp_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt,
-                     a.hels, a.out);
+hipError_t launch_colour(const ColourArgs& a) {
+  const dim3 grid((unsigned)((a.nrow + 15) / 16));
+  if (a.fmt == CS_FMT_FP16)
+    hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_FP16>), grid, dim3(64), 0, a.stream,
+                       a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
+  else
+    hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_BF16>), grid, dim3(64), 0, a.stream,
+                       a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
   return hipGetLastError();
 }
 
 template <class P>
 const ProcessDesc* describe() {
-  static const ProcessDesc d = {P::NAME, P::NPAR, P::NCOL, P::NHEL, P::IDEN, P::CF_DEN, P::NDIAG,
-                                P::cf_int(), &launch_chunks<P>, &launch_helicities<P>,
-                                &launch_jamps<P>};
+  static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,      P::NHEL,    P::IDEN,
+                                P::CF_DEN, P::NDIAG, P::cf_int(), &launch<P>, &launch_colour<P>};
   return &d;
 }
 

@@ -15,19 +15,32 @@ struct LaunchArgs {
   int nhel;
   int hel_per_chunk;
   int nchunk;
-  double* out;          // device output (layout depends on the launcher)
+  double* out;          // device, partial sums [nchunk][nevt] (unused when jamp_out is set)
+  double* jamp_out;     // device, dual amplitudes [nhel][nevt][ncol][2], or nullptr
   hipStream_t stream;
 };
 
 using Launcher = hipError_t (*)(const LaunchArgs&);
 
+struct ColourArgs {
+  const double* jamps;  // device, [nrow][ncol][2]
+  int64_t nrow;
+  int fmt;              // 0 = split FP16, 1 = split BF16
+  const void* cf_hi;    // device, colour matrix in the MFMA format, [32*MB][16*KS]
+  const void* cf_lo;    // device, second half of a split colour matrix, or nullptr
+  double inv_den;       // 1 / CF denominator
+  double* out;          // device, [nrow]
+  hipStream_t stream;
+};
+
+using ColourLauncher = hipError_t (*)(const ColourArgs&);
+
 struct ProcessDesc {
   const char* name;
   int npar, ncol, nhel, iden, cf_den, ndiag;
   const int* cf_int;          // host, [ncol][ncol]
-  Launcher chunks;            // partial sums per helicity chunk: out[nchunk][nevt]
-  Launcher helicities;        // per-helicity colour sums / CF_DEN: out[nhel][nevt]
-  Launcher jamps;             // dual amplitudes: out[nhel][nevt][ncol][2]
+  Launcher launch;            // partial colour sums per helicity chunk, or dual amplitudes
+  ColourLauncher colour;      // matrix-core colour sum of stored dual amplitudes
 };
 
 }  // namespace me

@@ -18,13 +18,16 @@ ROUTINE = {
     'V': 37,          # ext_v: as ext_ubar plus two sign products
     'v3': 162,        # v3_current: momenta (16), three dots (58), 1/P^2 (8), combine (80)
     'v4': 133,        # v4_current: 1/P^2 (9), two complex dots (60), combine (64)
+    'KD3': 162,       # v3_open on a top-line current: as v3_current
+    'KD4': 133,       # v4_open on a top-line current: as v4_current
     'Lh': 72,         # row_vertex: slash blocks (8), 2x2 blocks (56), coupling (8)
     'Rh': 72,         # vertex_col
     'L': 79,          # row_prop: q (4), propagator blocks + 1/(q^2-m^2) (11), product (56), scale (8)
     'R': 79,          # prop_col
     'K': 80,          # line_current: 8 complex products (48), combinations (24), coupling (8)
     'dot': 30,        # sdot / vdot: 4 complex products, 3 complex adds
-    'jamp': 2,        # one colour-flow accumulation (complex add)
+    'ffv': 102,       # row_vertex + sdot
+    'jamp': 2,        # one complex accumulation (group sum or colour flow)
 }
 
 
@@ -33,26 +36,28 @@ def plan_flops(plan):
     total = 0
     masks = set()
     for key in plan.order:
-        kind = key[0]
-        if kind == 'J':
+        r = plan.routine(key)
+        total += ROUTINE[r]
+        if key[0] == 'J':
             node = plan.trees.nodes[key[1]]
-            total += ROUTINE[node[0]]
-            if node[0] == 'v4':
-                masks.add(plan.trees.mask[key[1]])
-            else:
-                masks.add(plan.trees.mask[node[1]])
-                masks.add(plan.trees.mask[node[2]])
-        else:
-            total += ROUTINE[kind]
-            if kind in ('L', 'R'):
-                m = 0
-                for t in key[1]:
-                    m |= plan.trees.mask[t]
-                masks.add(m)
+            kids = node[1:] if node[0] == 'v3' else node[2:]
+            masks.add(plan.trees.mask[key[1]])
+            masks.update(plan.trees.mask[c] for c in kids)
+        elif key[0] in ('L', 'R'):
+            m = 0
+            for t in key[1]:
+                m |= plan.trees.mask[t]
+            masks.add(m)
+        elif key[0] == 'KD':
+            masks.add(plan.hole_mask(key))
+            masks.update(plan.trees.mask[t] for t in key[3][-1][3])
     # momentum sums P(mask) = sum of |mask| external momenta, once per mask
     total += sum(4 * (bin(m).count('1') - 1) for m in masks)
-    total += ROUTINE['dot'] * len(plan.amps)
-    total += ROUTINE['jamp'] * sum(len(c) for c in plan.colours)
+    for amp in plan.amps:
+        total += ROUTINE['ffv'] if len(amp) == 4 else ROUTINE['dot']
+    # pieces with the same colour vector are summed, then added to each of its flows
+    for key, members in plan.colour_groups():
+        total += ROUTINE['jamp'] * (len(members) - 1 + len(key))
     return total
 
 

@@ -43,6 +43,7 @@ class Emitter:
         self.lines = []
         self.names = {}
         self.masks_done = set()
+        self.neg_done = set()
         self.basis_index = {p: i for i, p in enumerate(plan.basis)}
 
     def var(self, key):
@@ -134,33 +135,71 @@ class Emitter:
             left = self.var(('L', key[1]) if key[1] else ('U',))
             right = self.var(('R', key[2]) if key[2] else ('V',))
             L.append(f"  cx {out}[4]; line_current({left}, {right}, g, {out});")
+        elif kind == 'KD':
+            self.emit_kd(key, out)
         else:
             raise KeyError(key)
 
-    def emit_amp(self, idx, a, b):
-        va, vb = self.var(a), self.var(b)
-        if a[0] == 'K':
-            expr = f"vdot({va}, {vb})"
-        else:
-            expr = f"sdot({va}, {vb})"
-        self.lines.append(f"  {{ const cx a = {expr};")
-        for perm, c in sorted(self.plan.colours[idx].items(), key=lambda kv: self.basis_index[kv[0]]):
-            k = self.basis_index[perm]
-            re, im = _cx(c)
-            if re == 1:
-                self.lines.append(f"    jamp[{k}] = jamp[{k}] + a;")
-            elif re == -1:
-                self.lines.append(f"    jamp[{k}] = jamp[{k}] - a;")
-            elif im == 1:
-                self.lines.append(f"    jamp[{k}] = jamp[{k}] + times_i(a);")
-            elif im == -1:
-                self.lines.append(f"    jamp[{k}] = jamp[{k}] - times_i(a);")
+    def negmom(self, mask):
+        name = f"N{mask}"
+        if mask in self.neg_done:
+            return name
+        self.neg_done.add(mask)
+        pm = self.mom(mask)
+        self.lines.append(f"  const double {name}[4] = {{-{pm}[0], -{pm}[1], -{pm}[2], -{pm}[3]}};")
+        return name
+
+    def emit_kd(self, key, out):
+        """Top-line current carried through one more gluon vertex (the last step)."""
+        pre, suf, steps = key[1], key[2], key[3]
+        parent = self.var(('KD', pre, suf, steps[:-1]) if len(steps) > 1 else ('K', pre, suf))
+        kind, s, hole, sibs = steps[-1]
+        tmask = self.plan.hole_mask(key)             # subtree below the parent line
+        npt = self.negmom(tmask)                      # incoming momentum of the parent leg
+        sib_vars = [self.var(self.plan.jkey(t)) for t in sibs]
+        sib_moms = [self.mom(self.tree_mask(t)) for t in sibs]
+        f = f"(-g / msq({self.mom(tmask)}))" if kind == 'v3' else f"(-g * g / msq({self.mom(tmask)}))"
+        if kind == 'v3':
+            # legs (parent, A, B); the two given legs in cyclic order after the open one
+            if hole == 1:
+                args = f"{sib_vars[0]}, {sib_moms[0]}, {parent}, {npt}"
             else:
-                raise ValueError(c)
-        self.lines.append("  }")
+                args = f"{parent}, {npt}, {sib_vars[0]}, {sib_moms[0]}"
+            self.lines.append(f"  cx {out}[4]; v3_open({args}, {f}, {out});")
+        else:
+            legs = [parent]
+            it = iter(sib_vars)
+            for leg in range(1, 4):
+                legs.append('nullptr' if leg == hole else next(it))
+            self.lines.append(f"  cx {out}[4]; v4_open<{s}, {hole}>({', '.join(legs)}, {f}, {out});")
+
+    def amp_expr(self, objs):
+        """(setup lines, expression) of one amplitude contraction."""
+        if len(objs) == 3:
+            # quark-gluon vertex amplitude  L (i g gamma.J) R
+            left, j, right = (self.var(o) for o in objs)
+            return [f"cx t[4]; row_vertex({left}, {j}, g, t);"], f"sdot(t, {right})"
+        va, vb = self.var(objs[0]), self.var(objs[1])
+        op = 'vdot' if objs[0][0] in ('K', 'KD') else 'sdot'
+        return [], f"{op}({va}, {vb})"
+
+    @staticmethod
+    def _scaled(expr, c):
+        """expr times a unit c in {+-1, +-i}, as (sign, expression)."""
+        re, im = _cx(c)
+        if re == 1:
+            return '+', expr
+        if re == -1:
+            return '-', expr
+        if im == 1:
+            return '+', f"times_i({expr})"
+        if im == -1:
+            return '-', f"times_i({expr})"
+        raise ValueError(c)
 
     def amplitudes(self):
-        # emit each object right before its first use, amplitudes in plan order
+        """Pieces sharing one colour vector (up to a unit factor) are summed first,
+        then the sum is added once to each of its colour flows."""
         done = set()
 
         def need(key):
@@ -171,10 +210,25 @@ class Emitter:
             self.emit_object(key)
             done.add(key)
 
-        for idx, a, b in self.plan.amps:
-            need(a)
-            need(b)
-            self.emit_amp(idx, a, b)
+        for gi, (key, members) in enumerate(self.plan.scheduled_groups()):
+            first_lead = members[0][0]
+            acc = f"s{gi}"
+            for n_m, (lead, amp) in enumerate(members):
+                for o in amp[1:]:
+                    need(o)
+                setup, expr = self.amp_expr(amp[1:])
+                sign, term = self._scaled('a', lead / first_lead)
+                head = "  { " + ' '.join(setup) + f" const cx a = {expr}; "
+                if n_m == 0:
+                    assert sign == '+' and term == 'a'
+                    self.lines.append(f"  cx {acc};")
+                    self.lines.append(head + f"{acc} = a; }}")
+                else:
+                    self.lines.append(head + f"{acc} = {acc} {sign} {term}; }}")
+            # distribute the group sum over its colour flows
+            for k, rel in key:
+                sign, term = self._scaled(acc, rel * first_lead)
+                self.lines.append(f"  jamp[{k}] = jamp[{k}] {sign} {term};")
         return self.lines
 
 

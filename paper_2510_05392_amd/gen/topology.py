@@ -188,14 +188,25 @@ def piece_colour(trees, piece, memo):
 # --- evaluation plan ---------------------------------------------------------
 
 # FP64 flop estimates of each building block (add, mul = 1; used only to rank choices)
-COST = {'G': 30, 'U': 40, 'V': 40, 'v3': 140, 'v4': 120, 'Lh': 64, 'L': 80,
-        'Rh': 64, 'R': 80, 'K': 100, 'dot': 30}
+COST = {'G': 24, 'U': 35, 'V': 37, 'v3': 162, 'v4': 133, 'Lh': 72, 'L': 79,
+        'Rh': 72, 'R': 79, 'K': 80, 'KD3': 170, 'KD4': 140, 'dot': 30, 'ffv': 102}
 
 
 class Plan:
-    """Objects (currents) in evaluation order and amplitudes as contractions."""
+    """Objects (currents) in evaluation order and amplitudes as contractions.
 
-    def __init__(self, n):
+    Every diagram piece is evaluated by cutting one internal line (or at one
+    quark-gluon vertex) and contracting the memoised currents on both sides:
+      top-line cut         L . Rh  or  Lh . R
+      quark-gluon vertex   L (i g gamma.J) R                         ('ffv')
+      gluon-line cut       K . J   (line attaching a tree to the top line) or
+                           KD . J  (line inside a tree; KD is the top-line current
+                           carried through the gluon vertices above the cut)
+    A greedy pass followed by refinement sweeps picks, per piece, the cut whose
+    missing currents cost the fewest flops given all other pieces' choices.
+    """
+
+    def __init__(self, n, sweeps=6):
         self.n = n
         self.trees = Trees(n)
         self.pieces = diagram_pieces(self.trees)
@@ -203,40 +214,52 @@ class Plan:
         self.colours = [piece_colour(self.trees, p, memo) for p in self.pieces]
         self.basis = list(itertools.permutations(range(n)))
         self.ndiagrams = sum(1 for p in self.pieces if all(self.trees.is_full(t) for t in p))
-        self.objects = {}        # key -> dependency keys
-        self.order = []          # computed keys in dependency order
-        self.amps = []           # (piece index, key_a, key_b)
-        self._choose()
+        self._deps = {}
+        self._cands = [self.candidates(p) for p in self.pieces]
+        self._choose(sweeps)
 
-    # object keys: ('G', slot) ('U',) ('V',) ('J', t) ('Lh', seq) ('L', seq)
-    #              ('Rh', seq) ('R', seq) ('K', prefix, suffix)
+    # object keys: ('G', slot) ('U',) ('V',) ('J', t) ('Lh', seq) ('L', seq) ('Rh', seq)
+    #              ('R', seq) ('K', prefix, suffix) ('KD', prefix, suffix, steps)
+    # a step is (kind, s, hole_leg, siblings): the gluon vertex below the previous
+    # line, its colour structure, the leg that stays open and the other children.
     def deps(self, key):
+        hit = self._deps.get(key)
+        if hit is not None:
+            return hit
         kind = key[0]
         if kind in ('G', 'U', 'V'):
-            return ()
-        if kind == 'J':
+            out = ()
+        elif kind == 'J':
             node = self.trees.nodes[key[1]]
             if node[0] == 'leaf':
-                return (('G', node[1]),)
-            kids = node[1:] if node[0] == 'v3' else node[2:]
-            return tuple(self.jkey(c) for c in kids)
-        if kind == 'Lh':
+                out = (('G', node[1]),)
+            else:
+                kids = node[1:] if node[0] == 'v3' else node[2:]
+                out = tuple(self.jkey(c) for c in kids)
+        elif kind == 'Lh':
             seq = key[1]
             prev = ('L', seq[:-1]) if len(seq) > 1 else ('U',)
-            return (prev, self.jkey(seq[-1]))
-        if kind == 'L':
-            return (('Lh', key[1]),)
-        if kind == 'Rh':
+            out = (prev, self.jkey(seq[-1]))
+        elif kind == 'L':
+            out = (('Lh', key[1]),)
+        elif kind == 'Rh':
             seq = key[1]
             nxt = ('R', seq[1:]) if len(seq) > 1 else ('V',)
-            return (nxt, self.jkey(seq[0]))
-        if kind == 'R':
-            return (('Rh', key[1]),)
-        if kind == 'K':
+            out = (nxt, self.jkey(seq[0]))
+        elif kind == 'R':
+            out = (('Rh', key[1]),)
+        elif kind == 'K':
             left = ('L', key[1]) if key[1] else ('U',)
             right = ('R', key[2]) if key[2] else ('V',)
-            return (left, right)
-        raise KeyError(key)
+            out = (left, right)
+        elif kind == 'KD':
+            pre, suf, steps = key[1], key[2], key[3]
+            parent = ('KD', pre, suf, steps[:-1]) if len(steps) > 1 else ('K', pre, suf)
+            out = (parent,) + tuple(self.jkey(t) for t in steps[-1][3])
+        else:
+            raise KeyError(key)
+        self._deps[key] = out
+        return out
 
     def jkey(self, t):
         node = self.trees.nodes[t]
@@ -244,58 +267,249 @@ class Plan:
             return ('G', node[1])
         return ('J', t)
 
-    def cost(self, key):
+    def routine(self, key):
+        """Name of the device routine that computes object `key`."""
         kind = key[0]
         if kind == 'J':
-            return COST[self.trees.nodes[key[1]][0]]
-        return COST[kind]
+            return self.trees.nodes[key[1]][0]
+        if kind == 'KD':
+            return 'KD3' if key[3][-1][0] == 'v3' else 'KD4'
+        return kind
 
-    def _missing_cost(self, key, seen):
-        if key in self.objects or key in seen:
-            return 0
-        seen.add(key)
-        return self.cost(key) + sum(self._missing_cost(d, seen) for d in self.deps(key))
+    def cost(self, key):
+        return COST[self.routine(key)]
 
-    def _add(self, key):
-        if key in self.objects:
+    def hole_mask(self, key):
+        """Gluons below the open line of a K / KD current (the parent-line subtree for KD)."""
+        full = (1 << self.n) - 1
+        m = full
+        for t in key[1] + key[2]:
+            m &= ~self.trees.mask[t]
+        if key[0] == 'KD':
+            for step in key[3][:-1]:
+                for t in step[3]:
+                    m &= ~self.trees.mask[t]
+        return m
+
+    def _lines(self, t, steps):
+        """(steps, subtree) for every gluon line strictly inside tree t."""
+        node = self.trees.nodes[t]
+        if node[0] == 'leaf':
             return
-        ds = self.deps(key)
-        for d in ds:
-            self._add(d)
-        self.objects[key] = ds
-        self.order.append(key)
+        kids = node[1:] if node[0] == 'v3' else node[2:]
+        s = 0 if node[0] == 'v3' else node[1]
+        for pos, child in enumerate(kids):
+            sibs = tuple(k for i, k in enumerate(kids) if i != pos)
+            st = steps + ((node[0], s, pos + 1, sibs),)
+            yield st, child
+            yield from self._lines(child, st)
 
     def candidates(self, piece):
+        """(contraction cost, required objects) for every way to evaluate a piece."""
         m = len(piece)
         out = []
         for j in range(1, m):
             pre, suf = piece[:j], piece[j:]
-            out.append((('L', pre), ('Rh', suf)))
-            out.append((('Lh', pre), ('R', suf) if suf else ('V',)))
+            out.append((COST['dot'], (('L', pre), ('Rh', suf))))
+            out.append((COST['dot'], (('Lh', pre), ('R', suf))))
         if m == 1:
-            out.append((('Lh', piece), ('V',)))
+            out.append((COST['dot'], (('Lh', piece), ('V',))))
         for j in range(m):
-            out.append((('K', piece[:j], piece[j + 1:]), self.jkey(piece[j])))
+            pre, suf = piece[:j], piece[j + 1:]
+            left = ('L', pre) if pre else ('U',)
+            right = ('R', suf) if suf else ('V',)
+            out.append((COST['ffv'], (left, self.jkey(piece[j]), right)))
+            out.append((COST['dot'], (('K', pre, suf), self.jkey(piece[j]))))
+            for steps, sub in self._lines(piece[j], ()):
+                out.append((COST['dot'], (('KD', pre, suf, steps), self.jkey(sub))))
         return out
 
-    def _choose(self):
-        # visit pieces so that those sharing long prefixes are adjacent
+    # --- greedy choice with refinement ------------------------------------
+    def _missing(self, key, seen):
+        if self.refs.get(key, 0) > 0 or key in seen:
+            return 0
+        seen.add(key)
+        c = self.cost(key)
+        if self.amortise:
+            c = c / self.popularity.get(key, 1)
+        return c + sum(self._missing(d, seen) for d in self.deps(key))
+
+    def _closure(self, objs, out):
+        for o in objs:
+            if o not in out:
+                out.add(o)
+                self._closure(self.deps(o), out)
+
+    def _inc(self, key):
+        r = self.refs.get(key, 0)
+        self.refs[key] = r + 1
+        if r == 0:
+            for d in self.deps(key):
+                self._inc(d)
+
+    def _dec(self, key):
+        r = self.refs[key] - 1
+        self.refs[key] = r
+        if r == 0:
+            for d in self.deps(key):
+                self._dec(d)
+
+    def _best(self, i):
+        best = None
+        for c, objs in self._cands[i]:
+            seen = set()
+            tot = c + sum(self._missing(o, seen) for o in objs)
+            if best is None or tot < best[0]:
+                best = (tot, objs)
+        return best[1]
+
+    def _choose(self, sweeps):
+        self.refs = {}
+        # popularity: in how many pieces' candidate sets (with dependencies) an object appears
+        self.popularity = {}
+        for cands in self._cands:
+            objs = set()
+            for _, c in cands:
+                self._closure(c, objs)
+            for o in objs:
+                self.popularity[o] = self.popularity.get(o, 0) + 1
         order = sorted(range(len(self.pieces)), key=lambda i: (len(self.pieces[i]), self.pieces[i]))
+        choice = [None] * len(self.pieces)
+        # first pass: costs amortised over the pieces that could share an object
+        self.amortise = True
         for i in order:
+            choice[i] = self._best(i)
+            for o in choice[i]:
+                self._inc(o)
+        self.amortise = False
+        for _ in range(sweeps):
+            changed = 0
+            for i in order:
+                for o in choice[i]:
+                    self._dec(o)
+                new = self._best(i)
+                if new != choice[i]:
+                    changed += 1
+                choice[i] = new
+                for o in new:
+                    self._inc(o)
+            if not changed:
+                break
+        self.choice = choice
+        # evaluation order: dependencies first, in the order pieces are visited
+        self.objects = {}
+        self.order = []
+
+        def add(key):
+            if key in self.objects:
+                return
+            for d in self.deps(key):
+                add(d)
+            self.objects[key] = self.deps(key)
+            self.order.append(key)
+
+        self.amps = []
+        for i in order:
+            for o in choice[i]:
+                add(o)
+            self.amps.append((i,) + tuple(choice[i]))
+
+    def colour_groups(self):
+        """Amplitudes grouped by colour vector (equal up to a unit factor).
+
+        Returns [(key, members)], key = ((colour index, coefficient relative to
+        the lead), ...), members = [(lead coefficient, amp), ...], in order of
+        first appearance in self.amps.
+        """
+        index = {p: i for i, p in enumerate(self.basis)}
+        groups = {}
+        order = []
+        for amp in self.amps:
+            items = sorted((index[w], complex(v)) for w, v in self.colours[amp[0]].items())
+            lead = items[0][1]
+            key = tuple((i, v / lead) for i, v in items)
+            if key not in groups:
+                groups[key] = []
+                order.append(key)
+            groups[key].append((lead, amp))
+        return [(k, groups[k]) for k in order]
+
+    def scheduled_groups(self, alpha=1.0):
+        """colour_groups() reordered to keep few currents alive at once.
+
+        List scheduling: repeatedly emit the group whose evaluation creates the
+        fewest new currents net of the currents it retires (a current retires
+        after its last consumer); the order only affects register pressure.
+        """
+        groups = self.colour_groups()
+        gops = []
+        for key, members in groups:
+            ops = []
+            for lead, amp in members:
+                for o in amp[1:]:
+                    if o not in ops:
+                        ops.append(o)
+            gops.append(ops)
+        uses = {}
+        for k in self.order:
+            for d in self.objects[k]:
+                uses[d] = uses.get(d, 0) + 1
+        for ops in gops:
+            for o in ops:
+                uses[o] = uses.get(o, 0) + 1
+        computed, alive = set(), set()
+        remaining = list(range(len(groups)))
+        out = []
+
+        def closure(ops):
+            res, seen = [], set()
+
+            def rec(k):
+                if k in computed or k in seen:
+                    return
+                seen.add(k)
+                for d in self.objects[k]:
+                    rec(d)
+                res.append(k)
+            for o in ops:
+                rec(o)
+            return res
+
+        while remaining:
             best = None
-            for a, b in self.candidates(self.pieces[i]):
-                seen = set()
-                c = self._missing_cost(a, seen) + self._missing_cost(b, seen)
-                if best is None or c < best[0]:
-                    best = (c, a, b)
-            _, a, b = best
-            self._add(a)
-            self._add(b)
-            self.amps.append((i, a, b))
+            for g in remaining:
+                new = closure(gops[g])
+                dec = {}
+                for k in new:
+                    for d in self.objects[k]:
+                        dec[d] = dec.get(d, 0) + 1
+                for o in gops[g]:
+                    dec[o] = dec.get(o, 0) + 1
+                newset = set(new)
+                freed = sum(1 for o, c in dec.items()
+                            if uses[o] == c and (o in alive or o in newset))
+                score = len(new) - alpha * freed
+                if best is None or score < best[0]:
+                    best = (score, g, new)
+            _, g, new = best
+            for k in new:
+                computed.add(k)
+                alive.add(k)
+                for d in self.objects[k]:
+                    uses[d] -= 1
+            for o in gops[g]:
+                uses[o] -= 1
+            alive = {o for o in alive if uses[o] > 0}
+            remaining.remove(g)
+            out.append(groups[g])
+        return out
 
     # --- summaries -----------------------------------------------------------
     def flops(self):
-        return sum(self.cost(k) for k in self.order) + COST['dot'] * len(self.amps)
+        tot = sum(self.cost(k) for k in self.order)
+        for a in self.amps:
+            tot += COST['ffv'] if len(a) == 4 else COST['dot']
+        return tot
 
     def counts(self):
         out = {}
@@ -303,4 +517,5 @@ class Plan:
             kind = k[0] if k[0] != 'J' else self.trees.nodes[k[1]][0]
             out[kind] = out.get(kind, 0) + 1
         out['amp'] = len(self.amps)
+        out['ffv'] = sum(1 for a in self.amps if len(a) == 4)
         return out

@@ -1,0 +1,85 @@
+"""The process generator of the HIP path, checked on the CPU.
+
+The generator (its own diagram enumeration, colour reduction, colour matrix
+and evaluation plan) is compared with the oracle, and its emitted device code
+is compiled for the host (test-only stand-in header) and evaluated against
+the oracle per helicity.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import colour as ocolour, me as ome
+from paper_2510_05392_amd import flops, rambo
+from paper_2510_05392_amd.gen import colour as gcolour, topology
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from cpu_harness import build as harness  # noqa: E402
+
+AS = 0.118
+
+
+@pytest.mark.parametrize('n,ndiag', [(2, 3), (3, 16), (4, 123), (5, 1240)])
+def test_generator_diagram_counts(n, ndiag):
+    plan = topology.Plan(n, sweeps=0) if n < 5 else topology.Plan(n)
+    assert plan.ndiagrams == ndiag
+    assert len(plan.amps) == len(plan.pieces)
+
+
+@pytest.mark.parametrize('n', [2, 3, 4, 5])
+def test_generator_colour_matrix_matches_oracle(n):
+    cf, den = gcolour.colour_matrix(n)
+    ref = ocolour.colour_matrix(n)
+    for i, row in enumerate(cf):
+        for j, v in enumerate(row):
+            assert v == ref[i][j] * den
+
+
+@pytest.mark.parametrize('n', [2, 3, 4])
+def test_generator_colour_coefficients_match_oracle(n):
+    # the same multiset of (colour flow, coefficient) over all diagram pieces
+    plan = topology.Plan(n, sweeps=0)
+    proc = ome.process(n + 2)
+    mine = [str(sorted(((w, complex(c)) for w, c in col.items()), key=str)) for col in plan.colours]
+    theirs = [str(sorted(((proc.basis[s], c) for s, c in cf), key=str)) for cf in proc.coefs]
+    assert len(mine) == len(theirs)
+    assert sorted(map(str, mine)) == sorted(map(str, theirs))
+
+
+def test_every_piece_is_evaluated_once():
+    for n in (3, 4, 5):
+        plan = topology.Plan(n)
+        assert sorted(a[0] for a in plan.amps) == list(range(len(plan.pieces)))
+        # every group member appears exactly once in the emitted schedule
+        seen = [a[0] for _, mem in plan.scheduled_groups() for _, a in mem]
+        assert sorted(seen) == list(range(len(plan.pieces)))
+
+
+def test_flop_model_is_positive_and_monotone():
+    f = [flops.per_event_helicity(p) for p in ('gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg')]
+    assert all(b > 4 * a for a, b in zip(f, f[1:]))
+
+
+@pytest.mark.parametrize('name,npar,nevt,opt,hels', [
+    ('gg_ttx', 4, 16, '-O1', None), ('gg_ttxg', 5, 8, '-O1', None),
+    ('gg_ttxgg', 6, 6, '-O1', None), ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127))])
+def test_generated_code_on_host_vs_oracle(name, npar, nevt, opt, hels):
+    h = harness.build(name, opt)
+    mom = rambo.generate(npar, nevt, 5)
+    proc = ome.process(npar)
+    hels = list(range(2 ** npar)) if hels is None else list(hels)
+    meh, jam = h.eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels, want_jamps=True)
+    ref = ome.me_helicities(proc, mom, AS, hels)
+    assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
+    # dual amplitudes agree up to one phase per (event, helicity)
+    jo = np.stack([ome.jamps(proc, mom, hh, AS) for hh in hels])
+    jscale = np.abs(jo).max(axis=(0, 2))
+    num = (jam * np.conj(jo)).sum(axis=2)
+    den = (np.abs(jo) ** 2).sum(axis=2)
+    ok = den > 1e-20 * jscale[None, :] ** 2
+    ph = np.where(ok, num / np.where(ok, den, 1), 1)
+    dev = np.abs(jam - ph[..., None] * jo).max(axis=(0, 2))
+    assert np.all(dev <= 1e-12 * jscale)

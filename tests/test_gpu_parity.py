@@ -196,3 +196,64 @@ def test_full_size_sampled(binding, name, nevt, seed, golden):
         ref = g['me']
     rel = np.abs(gpu[idx] / ref - 1)
     assert rel.max() < 1e-12, (rel.max(), int(idx[rel.argmax()]))
+
+
+# --- matrix-core colour sums ---------------------------------------------------
+# Stated error bounds (relative, per event) of the split-precision colour sums:
+# FP16 hi + lo keeps 22 significant bits of every (row-scaled) amplitude, BF16
+# hi + lo 16; FP32 accumulation over <= 128 terms adds ~1e-7.  With the colour
+# matrix dominated by its diagonal the quadratic form amplifies these by a few.
+MIXED_BOUND = {1: 1e-5, 2: 2e-4}
+
+
+@pytest.mark.parametrize('name,mode,nevt,seed', [('gg_ttx', 2, 133, 3), ('gg_ttxg', 1, 133, 4),
+                                                 ('gg_ttxgg', 2, 64 * 3 + 5, 1006),
+                                                 ('gg_ttxgg', 1, 64 * 3 + 5, 1006)])
+def test_mixed_colour_sum_vs_oracle(binding, name, mode, nevt, seed):
+    _say(f'case mixed colour sum {name} mode={mode} nevt={nevt}')
+    npar = NPAR[name]
+    mom = rambo.generate(npar, nevt, seed)
+    m, gpu = _compute(binding, name, mom, colorsum_mode=mode)
+    ref = ome.matrix_element(ome.process(npar), mom, AS)
+    rel = np.abs(gpu / ref - 1)
+    _say(f'  max rel err {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}')
+    assert rel.max() < MIXED_BOUND[mode], rel.max()
+    again = m.compute(_dev(mom), AS).cpu().numpy()
+    assert np.array_equal(again, gpu)
+
+
+def test_mixed_colour_sum_ggttggg_golden(binding):
+    _say('case mixed colour sum gg_ttxggg golden 197 events')
+    g = _golden('gg_ttxggg_seed1003_first197.npz')
+    mom = rambo.generate(7, 197, 1003)
+    for mode in (1, 2):
+        _, gpu = _compute(binding, 'gg_ttxggg', mom, colorsum_mode=mode)
+        rel = np.abs(gpu / g['me'] - 1)
+        _say(f'  mode {mode}: max rel err {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}')
+        assert rel.max() < MIXED_BOUND[mode], rel.max()
+
+
+def test_mixed_full_size_ggttggg(binding):
+    _say('case mixed colour sum gg_ttxggg full size 262144')
+    g = _golden('gg_ttxggg_seed1003_n262144_sampled.npz')
+    mom = rambo.generate(7, 262144, 1003)
+    _, gpu = _compute(binding, 'gg_ttxggg', mom, colorsum_mode=1)
+    idx = g['index']
+    rel = np.abs(gpu[idx] / g['me'] - 1)
+    assert np.all(np.isfinite(gpu)) and rel.max() < MIXED_BOUND[1], rel.max()
+
+
+def test_set_colorsum_mode(binding):
+    _say('case set_colorsum_mode')
+    mom = rambo.generate(6, 70, 8)
+    m = binding.MatrixElement('gg_ttxgg')
+    d = _dev(mom)
+    a = m.compute(d, AS).cpu().numpy()
+    m.me_set_colorsum_mode(binding.ME_CS_BF16X2)
+    b = m.compute(d, AS).cpu().numpy()
+    m.me_set_colorsum_mode(binding.ME_CS_FP64)
+    c = m.compute(d, AS).cpu().numpy()
+    assert np.array_equal(a, c)
+    assert np.max(np.abs(b / a - 1)) < MIXED_BOUND[2]
+    with pytest.raises(binding.MeError):
+        m.me_set_colorsum_mode(7)
