@@ -42,7 +42,7 @@ def cpu_baseline(process, mom, alpha_s, budget_s):
         dt = time.perf_counter() - t0
         t_used += dt
         done += n
-        if t_used + 2.2 * dt > budget_s or done + 2 * n > mom.shape[0]:
+        if t_used + 1.5 * dt > budget_s or done + 2 * n > mom.shape[0]:
             break
         n *= 2
     wall = time.perf_counter() - w0

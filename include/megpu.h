@@ -112,6 +112,68 @@ int me_set_colorsum_mode(me_handle h, int mode);
  * using it afterwards, returns ME_ESTATE; passing NULL is a no-op. */
 int me_finalize(me_handle h);
 
+/* ---------------------------------------------------------------- surrogate
+ * A multilayer perceptron predicting the normalised log|M|^2 from the pair
+ * invariants log(2 p_i.p_j / s) (i < j, normalised with a per-feature mean and
+ * inverse standard deviation), trained by mean squared error with Adam, and
+ * the two-stage unweighting that uses it (stage 1 on the surrogate weight,
+ * stage 2 corrects accepted events with the exact matrix element; Danziger et
+ * al., SciPost Phys. 12 (2022) 164).  Weights: FP32 masters + BF16 copies;
+ * activations BF16; products on the matrix cores with FP32 accumulation.
+ * Feature rows are BF16 (uint16_t storage), padded with zeros to a multiple
+ * of 16 columns.  All pointers are device pointers unless marked host. */
+typedef struct me_sur_ctx* me_surrogate;
+
+typedef struct {
+  int nfeat;      /* input features (npar (npar-1) / 2) */
+  int width;      /* hidden width */
+  int depth;      /* hidden layers (SiLU); the output layer is linear with one unit */
+  uint64_t seed;  /* weight initialisation (splitmix64 stream) */
+} me_sur_params;
+
+int me_sur_init(const me_sur_params* p, me_surrogate* out);
+int me_sur_finalize(me_surrogate s);
+/* number of parameters (all W then b, layer by layer, W row-major [out][in]) */
+int me_sur_num_params(me_surrogate s, int64_t* n);
+/* host copies of the FP32 master parameters / of the last computed gradients */
+int me_sur_get_params(me_surrogate s, float* host, int64_t cap);
+int me_sur_set_params(me_surrogate s, const float* host, int64_t cap);
+int me_sur_get_grads(me_surrogate s, float* host, int64_t cap);
+/* per-feature mean and inverse standard deviation (host arrays of nfeat) */
+int me_sur_set_normalisation(me_surrogate s, const float* mean, const float* inv_std);
+/* features of momenta[nevt][npar][4]: normalised BF16 rows feat[nevt][pad16(nfeat)],
+ * and the raw log invariants raw[nevt][nfeat] (FP32) when raw is not NULL */
+int me_sur_features(me_surrogate s, const double* momenta, int64_t nevt, int npar, uint16_t* feat,
+                    float* raw, void* stream);
+/* y[n] = network output (normalised log|M|^2) for feature rows feat[n] */
+int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, void* stream);
+/* loss gradients for a batch (targets: normalised log|M|^2, FP32); the batch's
+ * summed squared error is added to *loss (device scalar) when loss is not NULL */
+int me_sur_grads(me_surrogate s, const uint16_t* feat, const float* target, int64_t nb, float* loss,
+                 void* stream);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the stored gradients */
+int me_sur_adam(me_surrogate s, float lr, void* stream);
+/* me_sur_grads followed by me_sur_adam */
+int me_sur_train_step(me_surrogate s, const uint16_t* feat, const float* target, int64_t nb, float lr,
+                      float* loss, void* stream);
+
+/* Two-stage unweighting, stage 1: w_hat = exp(y * ystd + ymean) * wps, keep event i
+ * when r1[i] < min(1, w_hat_i / what_max); writes w_hat[n] and the kept indices in
+ * ascending order to idx[] (capacity n), their number to *n_keep (host).
+ * Synchronises the stream. */
+int me_unweight_stage1(const float* y, const double* wps, const double* r1, int64_t n, double ymean,
+                       double ystd, double what_max, double* what, int64_t* idx, int64_t* n_keep,
+                       void* stream);
+/* out[k] = momenta[idx[k]] for k < m (rows of npar*4 doubles) */
+int me_gather_momenta(const double* momenta, const int64_t* idx, int64_t m, int npar, double* out,
+                      void* stream);
+/* stage 2 on the m kept events (exact |M|^2 in me_exact[m]): x = w / w_hat, accept when
+ * r2[idx[k]] < min(1, x / x_max); resid[k] = max(1, w_hat/what_max) max(1, x/x_max) when
+ * accepted, 0 otherwise */
+int me_unweight_stage2(const double* me_exact, const int64_t* idx, int64_t m, const double* wps,
+                       const double* what, const double* r2, double what_max, double x_max, double* resid,
+                       void* stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char* me_last_error(void);
 

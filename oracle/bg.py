@@ -99,8 +99,10 @@ class _BG:
 def jamps(npar, mom, h, alpha_s, mt=173.0, basis=None, ward_slot=None):
     """Colour-ordered amplitudes for every ordering in `basis` (default: all, lexicographic)."""
     import itertools
-    mom = np.asarray(mom, dtype=float)
+    mom = np.asarray(mom)
+    if mom.dtype != np.longdouble:
+        mom = mom.astype(np.float64)
     n = npar - 2
     basis = list(itertools.permutations(range(n))) if basis is None else basis
-    bg = _BG(mom, helicities(npar, h), mt, coupling(alpha_s), ward_slot)
+    bg = _BG(mom, helicities(npar, h), mt, coupling(alpha_s, mom.dtype), ward_slot)
     return np.stack([bg.amplitude(tuple(s)) for s in basis], axis=1)

@@ -10,8 +10,6 @@ includes the 1/4 spin and 1/64 colour averages of the incoming gluons.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 
@@ -20,11 +18,15 @@ def _dot(a, b):
 
 
 def gg_ttx(mom, alpha_s, mt):
-    mom = np.asarray(mom, dtype=float)
+    mom = np.asarray(mom)
+    if mom.dtype != np.longdouble:
+        mom = mom.astype(np.float64)
     p1, p2, p3 = mom[:, 0], mom[:, 1], mom[:, 2]
     s = _dot(p1 + p2, p1 + p2)
     t1 = 2.0 * _dot(p1, p3) / s
     t2 = 2.0 * _dot(p2, p3) / s
     rho = 4.0 * mt * mt / s
-    g4 = (4.0 * math.pi * alpha_s) ** 2
-    return g4 * (1.0 / (6.0 * t1 * t2) - 0.375) * (t1 * t1 + t2 * t2 + rho - rho * rho / (4.0 * t1 * t2))
+    pi = np.arccos(np.asarray(-1.0, dtype=mom.dtype))
+    g4 = (4 * pi * np.asarray(alpha_s, dtype=mom.dtype)) ** 2
+    return g4 * (1 / (6 * t1 * t2) - np.asarray(0.375, dtype=mom.dtype)) * (
+        t1 * t1 + t2 * t2 + rho - rho * rho / (4 * t1 * t2))

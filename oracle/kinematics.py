@@ -15,7 +15,9 @@ closer look at the internals of the ME engine"); it leaves their formulas to
 HELAS.  Particles moving exactly along -z take the theta = pi limit with
 phi = 0.
 
-All functions are vectorised over a leading event axis.
+All functions are vectorised over a leading event axis and keep the precision
+of their inputs: float64 momenta give complex128 results, np.longdouble momenta
+give np.clongdouble results (used to adjudicate ill-conditioned events).
 """
 from __future__ import annotations
 
@@ -42,10 +44,15 @@ def mdot(a, b):
     return a[..., 0] * b[..., 0] - a[..., 1] * b[..., 1] - a[..., 2] * b[..., 2] - a[..., 3] * b[..., 3]
 
 
+def cdtype(x):
+    """Complex dtype matching the precision of array x."""
+    return np.clongdouble if np.asarray(x).dtype in (np.longdouble, np.clongdouble) else np.complex128
+
+
 def slash(a):
     """gamma^mu a_mu as a [..., 4, 4] matrix."""
     a = np.asarray(a)
-    return np.einsum('...m,mab->...ab', a * METRIC, GAMMA)
+    return np.einsum('...m,mab->...ab', a * METRIC, GAMMA.astype(cdtype(a)))
 
 
 def _chi(p3, lam):
@@ -56,7 +63,7 @@ def _chi(p3, lam):
     # |p| + pz, written as pt^2 / (|p| - pz) when pz < 0 (same number, no cancellation)
     with np.errstate(divide='ignore', invalid='ignore'):
         ppz = np.where(pz >= 0, pabs + pz, pt2 / (pabs - pz))
-    out = np.zeros(p3.shape[:-1] + (2,), dtype=complex)
+    out = np.zeros(p3.shape[:-1] + (2,), dtype=cdtype(p3))
     reg = ppz > 0.0
     # generic direction: cos(t/2) = sqrt((|p|+pz)/2|p|), e^{if} sin(t/2) = (px+i py)/sqrt(2|p|(|p|+pz))
     with np.errstate(divide='ignore', invalid='ignore'):
@@ -99,7 +106,7 @@ def v_spinor(p, lam, m):
 
 def bar(spinor):
     """Dirac adjoint psi^dagger gamma^0 as a row spinor."""
-    return np.einsum('...a,ab->...b', np.conj(spinor), GAMMA[0])
+    return np.einsum('...a,ab->...b', np.conj(spinor), GAMMA[0].astype(cdtype(spinor)))
 
 
 def polarisation(k, lam):
@@ -115,7 +122,7 @@ def polarisation(k, lam):
     zero = np.zeros_like(kx)
     e1 = np.stack([zero, ct * cf, ct * sf, -st], axis=-1)
     e2 = np.stack([zero, -sf, cf, zero], axis=-1)
-    return (-lam * e1 - 1j * e2) / np.sqrt(2.0)
+    return (-lam * e1 - 1j * e2) / np.sqrt(np.asarray(2.0, dtype=kx.dtype))
 
 
 def helicities(npar, h):

@@ -27,7 +27,7 @@ import numpy as np
 
 from . import colour as _colour
 from . import diagrams as _diagrams
-from .kinematics import bar, helicities, mdot, polarisation, slash, u_spinor, v_spinor
+from .kinematics import bar, cdtype, helicities, mdot, polarisation, slash, u_spinor, v_spinor
 
 PROCESSES = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
 
@@ -64,6 +64,13 @@ class Process:
             self._cf = _colour.colour_matrix_float(self.ngluon)
         return self._cf
 
+    @property
+    def cf_ext(self):
+        """The colour matrix in extended precision (exact rationals rounded once)."""
+        exact = _colour.colour_matrix(self.ngluon)
+        return np.array([[np.longdouble(x.numerator) / np.longdouble(x.denominator) for x in row]
+                         for row in exact])
+
 
 def gluon_states(mom, hel, ward_slot=None, override=None):
     """Per gluon slot: (external factor J^mu, momentum flowing into the diagram).
@@ -79,13 +86,13 @@ def gluon_states(mom, hel, ward_slot=None, override=None):
         p = mom[:, q]
         pin = p if slot < 2 else -p
         if override is not None and slot == override[0]:
-            out.append((np.asarray(override[1], dtype=complex), pin))
+            out.append((np.asarray(override[1], dtype=cdtype(p)), pin))
             continue
         if slot == ward_slot:
-            out.append(((p / p[:, :1]).astype(complex), pin))
+            out.append(((p / p[:, :1]).astype(cdtype(p)), pin))
             continue
         eps = polarisation(p, hel[q])
-        out.append((eps.astype(complex) if slot < 2 else np.conj(eps), pin))
+        out.append((eps if slot < 2 else np.conj(eps), pin))
     return out
 
 
@@ -175,16 +182,23 @@ class _Evaluator:
         return np.einsum('ea,ea->e', r, self.v4)
 
 
-def coupling(alpha_s):
-    return math.sqrt(4.0 * math.pi * alpha_s)
+def coupling(alpha_s, dtype=np.float64):
+    """g = sqrt(4 pi alpha_s) in the working precision."""
+    pi = np.arccos(np.asarray(-1.0, dtype=dtype))
+    return np.sqrt(4 * pi * np.asarray(alpha_s, dtype=dtype))
+
+
+def _momenta(mom):
+    mom = np.asarray(mom)
+    return mom if mom.dtype == np.longdouble else mom.astype(np.float64)
 
 
 def jamps(proc, mom, h, alpha_s, ward_slot=None, override=None):
     """Dual amplitudes J[nevt, ncolour] for helicity combination h."""
-    mom = np.asarray(mom, dtype=float)
+    mom = _momenta(mom)
     hel = helicities(proc.npar, h)
-    ev = _Evaluator(proc, mom, hel, coupling(alpha_s), ward_slot, override)
-    out = np.zeros((mom.shape[0], proc.ncolour), dtype=complex)
+    ev = _Evaluator(proc, mom, hel, coupling(alpha_s, mom.dtype), ward_slot, override)
+    out = np.zeros((mom.shape[0], proc.ncolour), dtype=cdtype(mom))
     for piece, coefs in zip(proc.pieces, proc.coefs):
         a = ev.amplitude(piece)
         for s, c in coefs:
@@ -194,14 +208,15 @@ def jamps(proc, mom, h, alpha_s, ward_slot=None, override=None):
 
 def piece_amplitudes(proc, mom, h, alpha_s):
     """Colour-stripped Lorentz amplitude of every diagram piece, [npiece, nevt]."""
-    mom = np.asarray(mom, dtype=float)
-    ev = _Evaluator(proc, mom, helicities(proc.npar, h), coupling(alpha_s))
+    mom = _momenta(mom)
+    ev = _Evaluator(proc, mom, helicities(proc.npar, h), coupling(alpha_s, mom.dtype))
     return np.stack([ev.amplitude(piece) for piece in proc.pieces])
 
 
 def colour_sum(proc, jamp):
     """ME_h = sum_{s,t} conj(J_s) CF_st J_t, real part (full double loop)."""
-    return np.einsum('es,st,et->e', np.conj(jamp), proc.cf, jamp).real
+    cf = proc.cf if jamp.dtype == np.complex128 else proc.cf_ext
+    return np.einsum('es,st,et->e', np.conj(jamp), cf, jamp).real
 
 
 def me_helicities(proc, mom, alpha_s, hels=None):

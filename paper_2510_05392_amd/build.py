@@ -65,6 +65,8 @@ def generate_sources(procs, build_dir):
     _write_if_changed(regfile, '\n'.join(reg) + '\n')
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
                   [regfile, os.path.join(INCLUDE, 'megpu.h')]))
+    units.append((os.path.join(CSRC, 'surrogate.hip'), os.path.join(OBJ, 'surrogate.o'),
+                  [os.path.join(INCLUDE, 'megpu.h')]))
     return units
 
 

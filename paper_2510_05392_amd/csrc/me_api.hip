@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "megpu.h"
+#include "me_error.h"
 #include "me_process.h"
 
 namespace me {
@@ -29,6 +30,12 @@ int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+
+}  // namespace
+
+void me::set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(ME_EHIP, std::string(what) + ": " + hipGetErrorString(e));

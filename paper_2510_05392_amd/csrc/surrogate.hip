@@ -1,0 +1,719 @@
+// Learned surrogate of log|M|^2 and two-stage unweighting (see include/megpu.h).
+//
+// Network: nfeat -> width (x depth hidden layers, SiLU) -> 1, weights kept in
+// FP32 (master copy, Adam moments) and BF16 (the copies the matrix cores read),
+// activations in BF16, every product accumulated in FP32 on
+// v_mfma_f32_32x32x16_bf16.  One generic GEMM kernel with strided operands
+// serves the forward pass (Z = H W^T), the input gradients (dH = dZ W) and the
+// weight gradients (dW = dZ^T H).  Every reduction runs in a fixed order, so
+// training is bit-reproducible for fixed inputs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "megpu.h"
+#include "me_error.h"
+
+namespace {
+
+int sfail(int code, const std::string& m) {
+  me::set_error(m);
+  return code;
+}
+int shipfail(hipError_t e, const char* what) {
+  return sfail(ME_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// C[i][j] = sum_k A[i*sai + k*sak] * B[k*sbk + j*sbj]   (BF16 in, FP32 accumulate)
+// i < M, j < N, k < K; out of range operands read as zero.  One wavefront per 32x32
+// tile of C.  Epilogue: cf[i*ldc + j] = C + bias[j] (if cf), ch[i*ldh + j] =
+// bf16(act(C + bias[j])) (if ch), act = SiLU when silu_act else identity.
+// MFMA layouts: A[i][k]: lane l holds i = l%32, k = 8(l/32)+t; B[k][j]: j = l%32,
+// k = 8(l/32)+t; D[i][j]: j = l%32, i = 8(v/4) + 4(l/32) + v%4.
+__global__ void __launch_bounds__(64) gemm_bf16_kernel(
+    const __bf16* __restrict__ A, int64_t sai, int64_t sak, const __bf16* __restrict__ B,
+    int64_t sbk, int64_t sbj, int64_t M, int64_t N, int64_t K, const float* __restrict__ bias,
+    float* __restrict__ cf, int64_t ldc, __bf16* __restrict__ ch, int64_t ldh, int silu_act) {
+  const int l = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int64_t ai = i0 + (l & 31), bj = j0 + (l & 31);
+  const int kh = 8 * (l >> 5);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  const __bf16 zero = to_bf16(0.0f);
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t k = k0 + kh + t;
+      a[t] = (ai < M && k < K) ? A[ai * sai + k * sak] : zero;
+      b[t] = (bj < N && k < K) ? B[k * sbk + bj * sbj] : zero;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int64_t j = j0 + (l & 31);
+  if (j >= N) return;
+  const float bj_ = bias ? bias[j] : 0.0f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t i = i0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+    if (i < M) {
+      const float z = acc[v] + bj_;
+      if (cf) cf[i * ldc + j] = z;
+      if (ch) ch[i * ldh + j] = to_bf16(silu_act ? silu(z) : z);
+    }
+  }
+}
+
+hipError_t gemm(const __bf16* A, int64_t sai, int64_t sak, const __bf16* B, int64_t sbk,
+                int64_t sbj, int64_t M, int64_t N, int64_t K, const float* bias, float* cf,
+                int64_t ldc, __bf16* ch, int64_t ldh, bool act, hipStream_t s) {
+  const dim3 grid((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(64), 0, s, A, sai, sak, B, sbk, sbj, M, N, K,
+                     bias, cf, ldc, ch, ldh, act ? 1 : 0);
+  return hipGetLastError();
+}
+
+// Features: f = (log(2 p_i.p_j / s) - mean) * inv_std for pairs i < j, BF16,
+// row padded with zeros to kpad.
+__global__ void features_kernel(const double* __restrict__ mom, int64_t nevt, int npar,
+                                const float* __restrict__ mean, const float* __restrict__ inv_std,
+                                int kpad, __bf16* __restrict__ out, float* __restrict__ raw) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  const double* p = mom + e * npar * 4;
+  const double s = (p[0] + p[4]) * (p[0] + p[4]) - (p[1] + p[5]) * (p[1] + p[5]) -
+                   (p[2] + p[6]) * (p[2] + p[6]) - (p[3] + p[7]) * (p[3] + p[7]);
+  int f = 0;
+  for (int i = 0; i < npar; ++i)
+    for (int j = i + 1; j < npar; ++j) {
+      const double* a = p + 4 * i;
+      const double* b = p + 4 * j;
+      const double d = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+      const float x = (float)log(2.0 * d / s);
+      if (raw) raw[e * (npar * (npar - 1) / 2) + f] = x;
+      out[e * kpad + f] = to_bf16((x - mean[f]) * inv_std[f]);
+      ++f;
+    }
+  for (; f < kpad; ++f) out[e * kpad + f] = to_bf16(0.0f);
+}
+
+// dZ for the output layer: 2 (y - t) / B, FP32 and BF16 (row stride ld); per-block
+// squared-error partial sums in fixed order.
+__global__ void output_grad_kernel(const float* __restrict__ z, int64_t ldz, const float* __restrict__ t,
+                                   int64_t nb, float* __restrict__ dzf, __bf16* __restrict__ dzh,
+                                   int64_t ld, float* __restrict__ partial) {
+  __shared__ float red[256];
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float sq = 0.0f;
+  if (b < nb) {
+    const float r = z[b * ldz] - t[b];
+    sq = r * r;
+    dzf[b * ld] = 2.0f * r / (float)nb;
+    dzh[b * ld] = to_bf16(2.0f * r / (float)nb);
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// dZ = dH * silu'(Z) (row-major [nb][n]), FP32 and BF16
+__global__ void silu_back_kernel(const float* __restrict__ dh, const float* __restrict__ z, int64_t total,
+                                 float* __restrict__ dzf, __bf16* __restrict__ dzh) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  const float g = dh[k] * dsilu(z[k]);
+  dzf[k] = g;
+  dzh[k] = to_bf16(g);
+}
+
+// db[j] = sum_b dZ[b][j], fixed order
+__global__ void bias_grad_kernel(const float* __restrict__ dz, int64_t nb, int64_t ld, int n,
+                                 float* __restrict__ db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.0f;
+  for (int64_t b = 0; b < nb; ++b) s += dz[b * ld + j];
+  db[j] = s;
+}
+
+__global__ void sum_kernel(const float* __restrict__ x, int n, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s += x[i];
+    out[0] += s;
+  }
+}
+
+// Adam on the FP32 masters, then refresh the BF16 copies W16 [out][kin] and W16T [kin][outp]
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ void cast_weights_kernel(const float* __restrict__ w, int out, int in, int kin, int outp,
+                                    __bf16* __restrict__ w16, __bf16* __restrict__ w16t) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)outp * kin) return;
+  const int o = (int)(k / kin), i = (int)(k % kin);
+  const float x = (o < out && i < in) ? w[(int64_t)o * in + i] : 0.0f;
+  w16[(int64_t)o * kin + i] = to_bf16(x);
+  w16t[(int64_t)i * outp + o] = to_bf16(x);
+}
+
+__global__ void copy_col_kernel(const float* __restrict__ z, int64_t ld, int64_t n, float* __restrict__ y) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) y[b] = z[b * ld];
+}
+
+// --- unweighting ------------------------------------------------------------
+
+// stage 1: keep[i] = r[i] < min(1, w_hat_i / what_max), w_hat = exp(y*ystd + ymean) * wps
+__global__ void stage1_kernel(const float* __restrict__ y, const double* __restrict__ wps,
+                              const double* __restrict__ r, int64_t n, double ymean, double ystd,
+                              double what_max, double* __restrict__ what, int* __restrict__ keep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double wh = exp((double)y[i] * ystd + ymean) * wps[i];
+  what[i] = wh;
+  keep[i] = r[i] < fmin(1.0, wh / what_max) ? 1 : 0;
+}
+
+// per-block counts of kept entries (blocks of 256)
+__global__ void count_kernel(const int* __restrict__ keep, int64_t n, int* __restrict__ counts) {
+  __shared__ int red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  red[threadIdx.x] = (i < n) ? keep[i] : 0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+// ordered scatter of kept indices: block offsets from an exclusive scan of counts
+__global__ void scatter_kernel(const int* __restrict__ keep, int64_t n, const int64_t* __restrict__ offs,
+                               int64_t* __restrict__ idx) {
+  __shared__ int pre[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = (i < n) ? keep[i] : 0;
+  pre[threadIdx.x] = k;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele) within the block
+  for (int d = 1; d < 256; d <<= 1) {
+    const int add = (int)threadIdx.x >= d ? pre[threadIdx.x - d] : 0;
+    __syncthreads();
+    pre[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (k) idx[offs[blockIdx.x] + pre[threadIdx.x] - 1] = i;
+}
+
+__global__ void gather_kernel(const double* __restrict__ mom, const int64_t* __restrict__ idx, int64_t m,
+                              int rowlen, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m * rowlen) return;
+  const int64_t r = k / rowlen, c = k % rowlen;
+  out[k] = mom[idx[r] * rowlen + c];
+}
+
+// stage 2 on the kept events: x = w / w_hat, accept if r2 < min(1, x / x_max),
+// residual weight max(1, w_hat/what_max) * max(1, x/x_max) (0 when rejected)
+__global__ void stage2_kernel(const double* __restrict__ me, const int64_t* __restrict__ idx, int64_t m,
+                              const double* __restrict__ wps, const double* __restrict__ what,
+                              const double* __restrict__ r2, double what_max, double x_max,
+                              double* __restrict__ resid) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t i = idx[k];
+  const double w = me[k] * wps[i];
+  const double x = w / what[i];
+  const bool acc = r2[i] < fmin(1.0, x / x_max);
+  resid[k] = acc ? fmax(1.0, what[i] / what_max) * fmax(1.0, x / x_max) : 0.0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ surrogate object
+
+struct me_sur_ctx {
+  int nfeat, width, depth, kin0;       // kin0: padded input width
+  std::vector<int> in, out, kin, outp; // per linear layer: sizes and padded sizes
+  std::vector<float*> w, b, gw, gb, mw, vw, mb, vb;
+  std::vector<__bf16*> w16, w16t;
+  float* mean = nullptr;
+  float* inv_std = nullptr;
+  int step = 0;
+  // activations for a batch capacity
+  int64_t cap = 0;
+  std::vector<float*> z;               // pre-activations per layer [cap][outp]
+  std::vector<__bf16*> h;              // inputs of each layer, h[0] = features [cap][kin0]
+  float* dzf = nullptr;                // [cap][maxw]
+  __bf16* dzh = nullptr;
+  float* dh = nullptr;
+  float* partial = nullptr;            // per-block loss partial sums
+};
+
+namespace {
+
+std::mutex g_smu;
+std::set<const void*> g_slive;
+
+int scheck(me_surrogate s) {
+  if (!s) return sfail(ME_EINVAL, "null surrogate");
+  std::lock_guard<std::mutex> lk(g_smu);
+  if (!g_slive.count(s)) return sfail(ME_ESTATE, "surrogate is not live");
+  return ME_OK;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, n * sizeof(T) + 16);
+}
+
+void sfree(me_sur_ctx* c) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto v : {&c->w, &c->b, &c->gw, &c->gb, &c->mw, &c->vw, &c->mb, &c->vb, &c->z})
+    for (float* p : *v) f(p);
+  for (auto v : {&c->w16, &c->w16t, &c->h})
+    for (__bf16* p : *v) f(p);
+  f(c->mean);
+  f(c->inv_std);
+  f(c->dzf);
+  f(c->dzh);
+  f(c->dh);
+  f(c->partial);
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) for the weight initialisation
+uint64_t splitmix(uint64_t& x) {
+  uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+int ensure_batch(me_sur_ctx* c, int64_t nb) {
+  if (nb <= c->cap) return ME_OK;
+  for (float* p : c->z) if (p) (void)hipFree(p);
+  for (size_t i = 1; i < c->h.size(); ++i) if (c->h[i]) (void)hipFree(c->h[i]);
+  if (c->h[0]) (void)hipFree(c->h[0]);
+  if (c->dzf) (void)hipFree(c->dzf);
+  if (c->dzh) (void)hipFree(c->dzh);
+  if (c->dh) (void)hipFree(c->dh);
+  if (c->partial) (void)hipFree(c->partial);
+  const int L = (int)c->in.size();
+  int maxw = c->kin0;
+  for (int l = 0; l < L; ++l) maxw = std::max(maxw, std::max(c->outp[l], c->kin[l]));
+  hipError_t e = hipSuccess;
+  c->h.assign(L + 1, nullptr);
+  c->z.assign(L, nullptr);
+  e = dalloc(&c->h[0], (size_t)nb * c->kin0);
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    e = dalloc(&c->z[l], (size_t)nb * c->outp[l]);
+    if (e == hipSuccess && l + 1 < L) e = dalloc(&c->h[l + 1], (size_t)nb * c->kin[l + 1]);
+  }
+  if (e == hipSuccess) e = dalloc(&c->dzf, (size_t)nb * maxw);
+  if (e == hipSuccess) e = dalloc(&c->dzh, (size_t)nb * maxw);
+  if (e == hipSuccess) e = dalloc(&c->dh, (size_t)nb * maxw);
+  if (e == hipSuccess) e = dalloc(&c->partial, (size_t)(nb + 255) / 256 + 1);
+  if (e != hipSuccess) {
+    c->cap = 0;
+    return sfail(ME_ENOMEM, std::string("surrogate activations: ") + hipGetErrorString(e));
+  }
+  // zero the padded columns once: GEMMs write only the valid ones
+  for (int l = 0; l + 1 < L; ++l)
+    (void)hipMemset(c->h[l + 1], 0, (size_t)nb * c->kin[l + 1] * sizeof(__bf16));
+  c->cap = nb;
+  return ME_OK;
+}
+
+int refresh_bf16(me_sur_ctx* c, hipStream_t s) {
+  for (size_t l = 0; l < c->in.size(); ++l) {
+    const int64_t n = (int64_t)c->outp[l] * c->kin[l];
+    hipLaunchKernelGGL(cast_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c->w[l],
+                       c->out[l], c->in[l], c->kin[l], c->outp[l], c->w16[l], c->w16t[l]);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ME_OK : shipfail(e, "weight cast");
+}
+
+// forward pass over nb rows of h[0]; the output (normalised log ME) is column 0 of z[L-1]
+int forward(me_sur_ctx* c, int64_t nb, hipStream_t s) {
+  const int L = (int)c->in.size();
+  for (int l = 0; l < L; ++l) {
+    const bool last = l == L - 1;
+    hipError_t e = gemm(c->h[l], c->kin[l], 1, c->w16[l], 1, c->kin[l], nb, c->out[l], c->kin[l],
+                        c->b[l], c->z[l], c->outp[l], last ? nullptr : c->h[l + 1],
+                        last ? 0 : c->kin[l + 1], !last, s);
+    if (e != hipSuccess) return shipfail(e, "forward gemm");
+  }
+  return ME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int me_sur_init(const me_sur_params* p, me_surrogate* out) {
+  if (!p || !out) return sfail(ME_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->nfeat < 1 || p->nfeat > 256 || p->width < 1 || p->width > 4096 || p->depth < 1 || p->depth > 16)
+    return sfail(ME_EINVAL, "bad surrogate sizes");
+  me_sur_ctx* c = new (std::nothrow) me_sur_ctx;
+  if (!c) return sfail(ME_ENOMEM, "host allocation failed");
+  c->nfeat = p->nfeat;
+  c->width = p->width;
+  c->depth = p->depth;
+  auto pad16 = [](int x) { return ((x + 15) / 16) * 16; };
+  auto pad32 = [](int x) { return ((x + 31) / 32) * 32; };
+  c->kin0 = pad16(p->nfeat);
+  const int L = p->depth + 1;
+  for (int l = 0; l < L; ++l) {
+    const int in = l == 0 ? p->nfeat : p->width;
+    const int o = l == L - 1 ? 1 : p->width;
+    c->in.push_back(in);
+    c->out.push_back(o);
+    c->kin.push_back(pad16(in));
+    c->outp.push_back(pad32(o));
+  }
+  hipError_t e = hipSuccess;
+  uint64_t st = p->seed;
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    const size_t nw = (size_t)c->out[l] * c->in[l];
+    // Kaiming-uniform style initialisation, bound sqrt(6 / fan_in) / 2 for SiLU
+    std::vector<float> hw(nw), hb(c->out[l], 0.0f);
+    const double bound = std::sqrt(3.0 / c->in[l]);
+    for (size_t k = 0; k < nw; ++k) {
+      const double u = (splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+      hw[k] = (float)((2.0 * u - 1.0) * bound);
+    }
+    float *w, *b, *gw, *gb, *mw, *vw, *mb, *vb;
+    __bf16 *w16, *w16t;
+    e = dalloc(&w, nw);
+    if (e == hipSuccess) e = dalloc(&b, c->out[l]);
+    if (e == hipSuccess) e = dalloc(&gw, nw);
+    if (e == hipSuccess) e = dalloc(&gb, c->out[l]);
+    if (e == hipSuccess) e = dalloc(&mw, nw);
+    if (e == hipSuccess) e = dalloc(&vw, nw);
+    if (e == hipSuccess) e = dalloc(&mb, c->out[l]);
+    if (e == hipSuccess) e = dalloc(&vb, c->out[l]);
+    if (e == hipSuccess) e = dalloc(&w16, (size_t)c->outp[l] * c->kin[l]);
+    if (e == hipSuccess) e = dalloc(&w16t, (size_t)c->outp[l] * c->kin[l]);
+    if (e != hipSuccess) break;
+    c->w.push_back(w);
+    c->b.push_back(b);
+    c->gw.push_back(gw);
+    c->gb.push_back(gb);
+    c->mw.push_back(mw);
+    c->vw.push_back(vw);
+    c->mb.push_back(mb);
+    c->vb.push_back(vb);
+    c->w16.push_back(w16);
+    c->w16t.push_back(w16t);
+    e = hipMemcpy(w, hw.data(), nw * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b, hb.data(), hb.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(mw, 0, nw * 4);
+    if (e == hipSuccess) e = hipMemset(vw, 0, nw * 4);
+    if (e == hipSuccess) e = hipMemset(mb, 0, c->out[l] * 4);
+    if (e == hipSuccess) e = hipMemset(vb, 0, c->out[l] * 4);
+  }
+  if (e == hipSuccess) e = dalloc(&c->mean, c->nfeat);
+  if (e == hipSuccess) e = dalloc(&c->inv_std, c->nfeat);
+  if (e == hipSuccess) {
+    std::vector<float> zero(c->nfeat, 0.0f), one(c->nfeat, 1.0f);
+    e = hipMemcpy(c->mean, zero.data(), c->nfeat * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->inv_std, one.data(), c->nfeat * 4, hipMemcpyHostToDevice);
+  }
+  c->h.assign(L + 1, nullptr);
+  int rc = e == hipSuccess ? refresh_bf16(c, nullptr) : shipfail(e, "surrogate allocation");
+  if (rc == ME_OK) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = shipfail(e, "surrogate init");
+  }
+  if (rc != ME_OK) {
+    sfree(c);
+    delete c;
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    g_slive.insert(c);
+  }
+  *out = c;
+  return ME_OK;
+}
+
+int me_sur_finalize(me_surrogate s) {
+  if (!s) return ME_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    if (!g_slive.erase(s)) return sfail(ME_ESTATE, "surrogate is not live");
+  }
+  sfree(s);
+  delete s;
+  return ME_OK;
+}
+
+int me_sur_num_params(me_surrogate s, int64_t* n) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  if (!n) return sfail(ME_EINVAL, "null argument");
+  int64_t t = 0;
+  for (size_t l = 0; l < s->in.size(); ++l) t += (int64_t)s->out[l] * s->in[l] + s->out[l];
+  *n = t;
+  return ME_OK;
+}
+
+static int copy_params(me_surrogate s, float* host, int64_t cap, bool to_host, bool grads) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  int64_t n = 0;
+  me_sur_num_params(s, &n);
+  if (!host || cap < n) return sfail(ME_EINVAL, "parameter buffer too small");
+  int64_t off = 0;
+  for (size_t l = 0; l < s->in.size(); ++l) {
+    const size_t nw = (size_t)s->out[l] * s->in[l];
+    float* dw = grads ? s->gw[l] : s->w[l];
+    float* db = grads ? s->gb[l] : s->b[l];
+    hipError_t e = to_host ? hipMemcpy(host + off, dw, nw * 4, hipMemcpyDeviceToHost)
+                           : hipMemcpy(dw, host + off, nw * 4, hipMemcpyHostToDevice);
+    off += nw;
+    if (e == hipSuccess)
+      e = to_host ? hipMemcpy(host + off, db, s->out[l] * 4, hipMemcpyDeviceToHost)
+                  : hipMemcpy(db, host + off, s->out[l] * 4, hipMemcpyHostToDevice);
+    off += s->out[l];
+    if (e != hipSuccess) return shipfail(e, "parameter copy");
+  }
+  if (!to_host) return refresh_bf16(s, nullptr);
+  return ME_OK;
+}
+
+int me_sur_get_params(me_surrogate s, float* host, int64_t cap) { return copy_params(s, host, cap, true, false); }
+int me_sur_set_params(me_surrogate s, const float* host, int64_t cap) {
+  return copy_params(s, const_cast<float*>(host), cap, false, false);
+}
+int me_sur_get_grads(me_surrogate s, float* host, int64_t cap) { return copy_params(s, host, cap, true, true); }
+
+int me_sur_set_normalisation(me_surrogate s, const float* mean, const float* inv_std) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  if (!mean || !inv_std) return sfail(ME_EINVAL, "null argument");
+  hipError_t e = hipMemcpy(s->mean, mean, s->nfeat * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->inv_std, inv_std, s->nfeat * 4, hipMemcpyHostToDevice);
+  return e == hipSuccess ? ME_OK : shipfail(e, "normalisation copy");
+}
+
+int me_sur_features(me_surrogate s, const double* momenta, int64_t nevt, int npar, uint16_t* feat,
+                    float* raw, void* stream) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  if (nevt < 0 || npar < 3) return sfail(ME_EINVAL, "bad sizes");
+  if (npar * (npar - 1) / 2 != s->nfeat) return sfail(ME_EINVAL, "npar does not match nfeat");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !feat) return sfail(ME_EINVAL, "null pointer");
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     momenta, nevt, npar, s->mean, s->inv_std, s->kin0, reinterpret_cast<__bf16*>(feat), raw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ME_OK : shipfail(e, "features kernel");
+}
+
+int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, void* stream) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  if (n < 0) return sfail(ME_EINVAL, "n < 0");
+  if (n == 0) return ME_OK;
+  if (!feat || !y) return sfail(ME_EINVAL, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = 1 << 16;
+  rc = ensure_batch(s, std::min<int64_t>(n, chunk));
+  if (rc) return rc;
+  const int L = (int)s->in.size();
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t nb = std::min<int64_t>(chunk, n - off);
+    hipError_t e = hipMemcpyAsync(s->h[0], feat + off * s->kin0, (size_t)nb * s->kin0 * 2,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return shipfail(e, "feature copy");
+    rc = forward(s, nb, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(copy_col_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, s->z[L - 1],
+                       (int64_t)s->outp[L - 1], nb, y + off);
+    e = hipGetLastError();
+    if (e != hipSuccess) return shipfail(e, "output copy");
+  }
+  return ME_OK;
+}
+
+int me_sur_grads(me_surrogate s, const uint16_t* feat, const float* target, int64_t nb, float* loss,
+                 void* stream) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  if (nb <= 0 || !feat || !target) return sfail(ME_EINVAL, "bad batch");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_batch(s, nb);
+  if (rc) return rc;
+  const int L = (int)s->in.size();
+  hipError_t e = hipMemcpyAsync(s->h[0], feat, (size_t)nb * s->kin0 * 2, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return shipfail(e, "feature copy");
+  rc = forward(s, nb, st);
+  if (rc) return rc;
+  // output layer gradient (column 0), row stride outp of the last layer
+  const int64_t ldo = s->outp[L - 1];
+  const unsigned nblk = (unsigned)((nb + 255) / 256);
+  e = hipMemsetAsync(s->dzf, 0, (size_t)nb * ldo * 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->dzh, 0, (size_t)nb * ldo * 2, st);
+  if (e != hipSuccess) return shipfail(e, "gradient clear");
+  hipLaunchKernelGGL(output_grad_kernel, dim3(nblk), dim3(256), 0, st, s->z[L - 1], ldo, target, nb, s->dzf,
+                     s->dzh, ldo, s->partial);
+  if (loss) hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1), 0, st, s->partial, (int)nblk, loss);
+  int64_t ld = ldo;
+  for (int l = L - 1; l >= 0; --l) {
+    // dW[o][i] = sum_b dZ[b][o] H[b][i]
+    e = gemm(s->dzh, 1, ld, s->h[l], s->kin[l], 1, s->out[l], s->in[l], nb, nullptr, s->gw[l], s->in[l],
+             nullptr, 0, false, st);
+    if (e != hipSuccess) return shipfail(e, "weight-gradient gemm");
+    hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)((s->out[l] + 63) / 64)), dim3(64), 0, st, s->dzf, nb,
+                       ld, s->out[l], s->gb[l]);
+    if (l == 0) break;
+    // dH[b][i] = sum_o dZ[b][o] W[o][i], then dZ_{l-1} = dH * silu'(Z_{l-1})
+    const int64_t ldn = s->outp[l - 1];
+    e = gemm(s->dzh, ld, 1, s->w16t[l], s->outp[l], 1, nb, s->in[l], s->out[l], nullptr, s->dh, ldn, nullptr,
+             0, false, st);
+    if (e != hipSuccess) return shipfail(e, "input-gradient gemm");
+    const int64_t tot = nb * ldn;
+    hipLaunchKernelGGL(silu_back_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, s->dh,
+                       s->z[l - 1], tot, s->dzf, s->dzh);
+    ld = ldn;
+  }
+  e = hipGetLastError();
+  return e == hipSuccess ? ME_OK : shipfail(e, "backward");
+}
+
+int me_sur_adam(me_surrogate s, float lr, void* stream) {
+  int rc = scheck(s);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  s->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f - std::pow(b1, (float)s->step), c2 = 1.0f - std::pow(b2, (float)s->step);
+  for (size_t l = 0; l < s->in.size(); ++l) {
+    const int64_t nw = (int64_t)s->out[l] * s->in[l];
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, s->w[l], s->gw[l],
+                       s->mw[l], s->vw[l], nw, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((s->out[l] + 255) / 256)), dim3(256), 0, st, s->b[l],
+                       s->gb[l], s->mb[l], s->vb[l], (int64_t)s->out[l], lr, b1, b2, eps, c1, c2);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return shipfail(e, "adam");
+  return refresh_bf16(s, st);
+}
+
+int me_sur_train_step(me_surrogate s, const uint16_t* feat, const float* target, int64_t nb, float lr,
+                      float* loss, void* stream) {
+  int rc = me_sur_grads(s, feat, target, nb, loss, stream);
+  if (rc) return rc;
+  return me_sur_adam(s, lr, stream);
+}
+
+int me_unweight_stage1(const float* y, const double* wps, const double* r1, int64_t n, double ymean,
+                       double ystd, double what_max, double* what, int64_t* idx, int64_t* n_keep,
+                       void* stream) {
+  if (n < 0 || !n_keep) return sfail(ME_EINVAL, "bad arguments");
+  *n_keep = 0;
+  if (n == 0) return ME_OK;
+  if (!y || !wps || !r1 || !what || !idx) return sfail(ME_EINVAL, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  int* keep = nullptr;
+  int* counts = nullptr;
+  int64_t* offs = nullptr;
+  const int64_t nblk = (n + 255) / 256;
+  hipError_t e = hipMalloc(&keep, n * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&counts, nblk * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&offs, nblk * sizeof(int64_t));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(stage1_kernel, dim3((unsigned)nblk), dim3(256), 0, st, y, wps, r1, n, ymean, ystd,
+                       what_max, what, keep);
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nblk), dim3(256), 0, st, keep, n, counts);
+    e = hipGetLastError();
+  }
+  std::vector<int> hc(nblk);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), counts, nblk * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  std::vector<int64_t> ho(nblk);
+  int64_t tot = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    ho[b] = tot;
+    tot += hc[b];
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(offs, ho.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nblk), dim3(256), 0, st, keep, n, offs, idx);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(keep);
+  (void)hipFree(counts);
+  (void)hipFree(offs);
+  if (e != hipSuccess) return shipfail(e, "unweighting stage 1");
+  *n_keep = tot;
+  return ME_OK;
+}
+
+int me_gather_momenta(const double* momenta, const int64_t* idx, int64_t m, int npar, double* out,
+                      void* stream) {
+  if (m < 0) return sfail(ME_EINVAL, "m < 0");
+  if (m == 0) return ME_OK;
+  if (!momenta || !idx || !out) return sfail(ME_EINVAL, "null pointer");
+  const int rowlen = npar * 4;
+  const int64_t tot = m * rowlen;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     momenta, idx, m, rowlen, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ME_OK : shipfail(e, "gather");
+}
+
+int me_unweight_stage2(const double* me_exact, const int64_t* idx, int64_t m, const double* wps,
+                       const double* what, const double* r2, double what_max, double x_max, double* resid,
+                       void* stream) {
+  if (m < 0) return sfail(ME_EINVAL, "m < 0");
+  if (m == 0) return ME_OK;
+  if (!me_exact || !idx || !wps || !what || !r2 || !resid) return sfail(ME_EINVAL, "null pointer");
+  hipLaunchKernelGGL(stage2_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     me_exact, idx, m, wps, what, r2, what_max, x_max, resid);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ME_OK : shipfail(e, "unweighting stage 2");
+}
+
+}  // extern "C"

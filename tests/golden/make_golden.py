@@ -19,17 +19,26 @@ from paper_2510_05392_amd import rambo  # noqa: E402
 AS = 0.118
 
 
+def values(proc, mom):
+    """Oracle |M|^2 in float64 and in extended precision (np.longdouble arithmetic,
+    rounded to float64 for storage) to adjudicate ill-conditioned events."""
+    return (me.matrix_element(proc, mom, AS),
+            me.matrix_element(proc, mom.astype(np.longdouble), AS).astype(np.float64))
+
+
 def main():
     proc = me.process(7)
     # g g -> t tbar g g g: three 64-event tiles and a ragged tail
     mom = rambo.generate(7, 197, 1003)
+    m64, mext = values(proc, mom)
     np.savez_compressed(os.path.join(HERE, 'gg_ttxggg_seed1003_first197.npz'), momenta=mom,
-                        me=me.matrix_element(proc, mom, AS))
+                        me=m64, me_ext=mext)
     # the 262144-event benchmark workload, 64 events spread over the whole file
     full = rambo.generate(7, 262144, 1003)
     idx = np.unique(np.concatenate([np.linspace(0, 262143, 62).astype(int), [1, 262142]]))
+    m64, mext = values(proc, full[idx])
     np.savez_compressed(os.path.join(HERE, 'gg_ttxggg_seed1003_n262144_sampled.npz'), index=idx,
-                        momenta=full[idx], me=me.matrix_element(proc, full[idx], AS))
+                        momenta=full[idx], me=m64, me_ext=mext)
 
 
 if __name__ == '__main__':

@@ -41,6 +41,37 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to('cuda')
 
 
+def assert_parity(gpu, mom, npar, tol=1e-12, me64=None, me_ext=None):
+    """GPU FP64 vs oracle within `tol` relative per event, with adjudication.
+
+    Events off by more than `tol` are re-evaluated by the oracle in extended
+    precision (np.longdouble).  If the FP64 oracle itself is off from that by
+    more than 1e-13 the event is ill-conditioned (large cancellations): the
+    GPU value must then be within max(tol, 10 x the FP64 oracle's own error)
+    of the extended result, i.e. as good as a plain FP64 evaluation.
+    Returns the number of ill-conditioned events.
+    """
+    if me64 is None:
+        me64 = ome.matrix_element(ome.process(npar), mom, AS)
+    rel = np.abs(gpu / me64 - 1)
+    bad = np.where(rel > tol)[0]
+    if len(bad) == 0:
+        return 0
+    if me_ext is None:
+        ext = ome.matrix_element(ome.process(npar), np.asarray(mom)[bad].astype(np.longdouble),
+                                 AS).astype(np.float64)
+    else:
+        ext = np.asarray(me_ext)[bad]
+    own = np.abs(me64[bad] / ext - 1)
+    ill = own > 1e-13
+    err = np.abs(gpu[bad] / ext - 1)
+    allowed = np.where(ill, np.maximum(tol, 10 * own), tol)
+    _say(f'  adjudicated {len(bad)} events: ill-conditioned {int(ill.sum())}, '
+         f'oracle FP64 error {own.max():.2e}, GPU error vs extended {err.max():.2e}')
+    assert np.all(err <= allowed), (bad[err > allowed], err[err > allowed], own[err > allowed])
+    return int(ill.sum())
+
+
 def _compute(binding, name, mom, **kw):
     m = binding.MatrixElement(name, **kw)
     out = m.compute(_dev(mom), AS)
@@ -57,8 +88,7 @@ def test_me_vs_oracle(binding, name, nevt, seed):
     mom = rambo.generate(npar, nevt, seed)
     _, gpu = _compute(binding, name, mom)
     ref = ome.matrix_element(ome.process(npar), mom, AS)
-    rel = np.abs(gpu / ref - 1)
-    assert rel.max() < 1e-12, (rel.max(), int(rel.argmax()))
+    assert_parity(gpu, mom, npar, me64=ref)
     if name == 'gg_ttx':
         cf = closed_form.gg_ttx(mom, AS, MT)
         assert np.max(np.abs(gpu / cf - 1)) < 1e-12
@@ -170,8 +200,7 @@ def test_ggttggg_vs_oracle_golden(binding):
     mom = rambo.generate(7, 197, 1003)
     assert np.array_equal(mom, g['momenta'])
     _, gpu = _compute(binding, 'gg_ttxggg', mom)
-    rel = np.abs(gpu / g['me'] - 1)
-    assert rel.max() < 1e-12, (rel.max(), int(rel.argmax()))
+    assert_parity(gpu, mom, 7, me64=g['me'], me_ext=g['me_ext'])
 
 
 @pytest.mark.parametrize('name,nevt,seed,golden', [
@@ -188,14 +217,12 @@ def test_full_size_sampled(binding, name, nevt, seed, golden):
     assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
     if golden is None:
         idx = np.linspace(0, nevt - 1, 96).astype(int)
-        ref = ome.matrix_element(ome.process(npar), mom[idx], AS)
+        assert_parity(gpu[idx], mom[idx], npar)
     else:
         g = _golden(golden)
         idx = g['index']
         assert np.array_equal(mom[idx], g['momenta'])
-        ref = g['me']
-    rel = np.abs(gpu[idx] / ref - 1)
-    assert rel.max() < 1e-12, (rel.max(), int(idx[rel.argmax()]))
+        assert_parity(gpu[idx], mom[idx], npar, me64=g['me'], me_ext=g['me_ext'])
 
 
 # --- matrix-core colour sums ---------------------------------------------------

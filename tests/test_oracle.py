@@ -328,3 +328,32 @@ def test_rambo_massless_weight_is_volume():
     mom, w = rambo.generate(4, 4, 3, return_weights=True)
     beta = math.sqrt(1 - 4 * MT * MT / s)
     assert np.allclose(w, beta / (8 * math.pi))
+
+
+def test_extended_precision_mode():
+    # the oracle run on np.longdouble inputs works in extended precision
+    # throughout: on two-body points built exactly in long double it meets the
+    # closed form far below FP64 rounding
+    rng = np.random.default_rng(7)
+    n = 16
+    ld = np.longdouble
+    e = ld(750)
+    pabs = np.sqrt(e * e - ld(MT) * ld(MT))
+    ct = rng.uniform(-1, 1, n).astype(ld)
+    st = np.sqrt(1 - ct * ct)
+    ph = rng.uniform(0, 2 * np.pi, n).astype(ld)
+    p3 = np.stack([np.full(n, e), pabs * st * np.cos(ph), pabs * st * np.sin(ph), pabs * ct], axis=1)
+    p4 = p3.copy()
+    p4[:, 1:] *= -1
+    beam = np.zeros((n, 4), dtype=ld)
+    b1, b2 = beam.copy(), beam.copy()
+    b1[:, 0] = b1[:, 3] = e
+    b2[:, 0] = e
+    b2[:, 3] = -e
+    mom = np.stack([b1, b2, p3, p4], axis=1)
+    a = me.matrix_element(me.process(4), mom, AS)
+    b = closed_form.gg_ttx(mom, AS, MT)
+    assert a.dtype == np.longdouble
+    assert np.max(np.abs(a / b - 1)) < 1e-17
+    c = me.matrix_element(me.process(4), mom.astype(np.float64), AS)
+    assert np.max(np.abs(c / a.astype(np.float64) - 1)) < 1e-13
