@@ -64,6 +64,9 @@ def main():
     ap.add_argument('--alpha-s', type=float, default=0.118)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--fp64-only', action='store_true', help='skip the mixed-precision run')
+    ap.add_argument('--autotune', action=argparse.BooleanOptionalAction, default=True,
+                    help='pick the FP64 launch configuration with the library autotuner first')
+    ap.add_argument('--no-graph', action='store_true', help='do not replay me_compute from a hipGraph')
     ap.add_argument('--cpu-budget', type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -86,7 +89,12 @@ def main():
     def run(mode):
         """Time me_compute over the batch in one colour-sum mode; returns (ms/step, ME, nhel)."""
         out = torch.empty(nevt, dtype=torch.float64, device=dev)
-        m = binding.MatrixElement(process, colorsum_mode=mode)
+        m = binding.MatrixElement(process, colorsum_mode=mode, use_graph=not args.no_graph)
+        tuned = None
+        if args.autotune and mode == binding.ME_CS_FP64:
+            nt = min(nevt, 65536)
+            print(f'# bench autotune on {nt} events', file=sys.stderr, flush=True)
+            tuned = m.me_autotune(dmom[:nt], nt, args.alpha_s, out[:nt], stream)
         print(f'# bench {process} nevt={nevt} mode={mode}: warmup {args.warmup}', file=sys.stderr,
               flush=True)
         for _ in range(max(1, args.warmup)):
@@ -104,13 +112,13 @@ def main():
         if not np.all(np.isfinite(res)):
             print('non-finite matrix elements', file=sys.stderr)
             sys.exit(1)
-        return start.elapsed_time(stop) / args.steps, res, len(m.me_good_helicities())
+        return start.elapsed_time(stop) / args.steps, res, len(m.me_good_helicities()), tuned
 
-    ms, res, nhel = run(binding.ME_CS_FP64)
+    ms, res, nhel, tuned = run(binding.ME_CS_FP64)
     value = nevt / (ms * 1e-3)
     mixed = None
     if not args.fp64_only:
-        ms_m, res_m, _ = run(binding.ME_CS_FP16X2)
+        ms_m, res_m, _, _ = run(binding.ME_CS_FP16X2)
         rel = np.abs(res_m / res - 1)
         mixed = {'colorsum': 'split FP16 hi+lo on MFMA, FP32 accumulation, FP64 row dots',
                  'value': nevt / (ms_m * 1e-3), 'unit': 'ME evals/s', 'ms_per_step': ms_m,
@@ -127,7 +135,8 @@ def main():
         'data': 'synthetic (seeded flat RAMBO phase space)',
         'config': {'workload': f'{process} LO |M|^2, FP64 diagrams + FP64 colour sum', 'process': process,
                    'nevt': nevt, 'sqrt_s_GeV': 1500.0, 'mt_GeV': 173.0, 'alpha_s': args.alpha_s,
-                   'good_helicities': nhel, 'parallelism': 'single GPU'},
+                   'good_helicities': nhel, 'parallelism': 'single GPU', 'launch': tuned,
+                   'hipgraph': not args.no_graph},
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS, 'traffic': None,
                      'flops_per_event_helicity': f_unit,

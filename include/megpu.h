@@ -60,6 +60,8 @@ typedef struct {
   double mt;            /* top mass in GeV (default 173.0); gluons are massless */
   int colorsum_mode;    /* ME_CS_* (default ME_CS_FP64) */
   int all_helicities;   /* 1: skip the filter and sum all 2^npar helicities (default 0) */
+  int use_graph;        /* 1: capture the launch sequence of me_compute in a hipGraph on the first
+                           call with given (momenta, out, nevt, alpha_s) and replay it afterwards */
 } me_params;
 
 /* Fill *p with the defaults. */
@@ -107,6 +109,20 @@ int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
  * modes the dual amplitudes of up to ME_JAMP_SCRATCH_BYTES are staged in a
  * library-owned device buffer between the diagram and colour-sum kernels. */
 int me_set_colorsum_mode(me_handle h, int mode);
+
+/* Launch configuration of the FP64 path: persistent = 1 runs a grid of
+ * waves_per_simd x (4 x compute units) wavefronts that take work items
+ * (64-event tile, hel_per_item helicities; 0 = all) from an atomic counter;
+ * persistent = 0 launches one workgroup per item, splitting the helicities so
+ * that about target_waves wavefronts are launched.  Results do not depend on
+ * the configuration beyond rounding order of the helicity sum. */
+int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves);
+
+/* Autotuner: times a fixed set of launch configurations on these events (writing
+ * out_me2, synchronising the stream) and keeps the fastest; best[4] (host, may be
+ * NULL) receives (persistent, waves_per_simd, hel_per_item, target_waves). */
+int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+                void* stream, int32_t* best);
 
 /* Release the handle and everything it owns.  Finalising a handle twice, or
  * using it afterwards, returns ME_ESTATE; passing NULL is a no-op. */

@@ -25,7 +25,12 @@ ME_CS_BF16X2 = 2
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
-           'me_jamps', 'me_set_colorsum_mode', 'me_finalize', 'me_last_error']
+           'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_finalize',
+           'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
+           'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
+           'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
+           'me_unweight_stage1', 'me_gather_momenta', 'me_unweight_stage2',
+           'me_last_error']
 
 
 class MeError(RuntimeError):
@@ -36,7 +41,12 @@ class MeError(RuntimeError):
 
 class me_params(ctypes.Structure):
     _fields_ = [('mt', ctypes.c_double), ('colorsum_mode', ctypes.c_int),
-                ('all_helicities', ctypes.c_int)]
+                ('all_helicities', ctypes.c_int), ('use_graph', ctypes.c_int)]
+
+
+class me_sur_params(ctypes.Structure):
+    _fields_ = [('nfeat', ctypes.c_int), ('width', ctypes.c_int), ('depth', ctypes.c_int),
+                ('seed', ctypes.c_uint64)]
 
 
 _lib = None
@@ -61,7 +71,25 @@ def load(path=LIB_PATH):
     lib.me_helicity_sums.argtypes = [vp, vp, i64, ctypes.c_double, i32p, ctypes.c_int32, vp, vp]
     lib.me_jamps.argtypes = [vp, vp, i64, ctypes.c_double, i32p, ctypes.c_int32, vp, vp]
     lib.me_set_colorsum_mode.argtypes = [vp, ctypes.c_int]
+    lib.me_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.me_autotune.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, i32p]
     lib.me_finalize.argtypes = [vp]
+    fp, dbl = ctypes.POINTER(ctypes.c_float), ctypes.c_double
+    lib.me_sur_init.argtypes = [ctypes.POINTER(me_sur_params), ctypes.POINTER(vp)]
+    lib.me_sur_finalize.argtypes = [vp]
+    lib.me_sur_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.me_sur_get_params.argtypes = [vp, fp, i64]
+    lib.me_sur_set_params.argtypes = [vp, fp, i64]
+    lib.me_sur_get_grads.argtypes = [vp, fp, i64]
+    lib.me_sur_set_normalisation.argtypes = [vp, fp, fp]
+    lib.me_sur_features.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp, vp]
+    lib.me_sur_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.me_sur_grads.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.me_sur_adam.argtypes = [vp, ctypes.c_float, vp]
+    lib.me_sur_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, vp, vp]
+    lib.me_unweight_stage1.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, vp, vp, ctypes.POINTER(i64), vp]
+    lib.me_gather_momenta.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp]
+    lib.me_unweight_stage2.argtypes = [vp, vp, i64, vp, vp, vp, dbl, dbl, vp, vp]
     lib.me_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = ctypes.c_int
@@ -89,13 +117,14 @@ class MatrixElement:
     """One handle of the C ABI for one process."""
 
     def __init__(self, process: str, mt: float = 173.0, all_helicities: bool = False,
-                 colorsum_mode: int = ME_CS_FP64):
+                 colorsum_mode: int = ME_CS_FP64, use_graph: bool = False):
         lib = load()
         p = me_params()
         _check(lib.me_params_default(ctypes.byref(p)))
         p.mt = mt
         p.all_helicities = int(all_helicities)
         p.colorsum_mode = int(colorsum_mode)
+        p.use_graph = int(use_graph)
         h = ctypes.c_void_p()
         _check(lib.me_init(process.encode(), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -134,6 +163,14 @@ class MatrixElement:
         _check(load().me_jamps(self._h, _ptr(momenta), nevt, alpha_s, arr, len(hels),
                                _ptr(out), _stream(stream)))
 
+    def me_set_launch(self, persistent, waves_per_simd=1, hel_per_item=0, target_waves=4096):
+        _check(load().me_set_launch(self._h, persistent, waves_per_simd, hel_per_item, target_waves))
+
+    def me_autotune(self, momenta, nevt, alpha_s, out, stream=None):
+        best = (ctypes.c_int32 * 4)()
+        _check(load().me_autotune(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream), best))
+        return dict(zip(('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves'), list(best)))
+
     def me_set_colorsum_mode(self, mode):
         _check(load().me_set_colorsum_mode(self._h, int(mode)))
 
@@ -163,3 +200,90 @@ class MatrixElement:
             stream = torch.cuda.current_stream(momenta.device)
         self.me_compute(momenta, nevt, alpha_s, out, stream)
         return out
+
+
+class Surrogate:
+    """A handle of the surrogate C ABI (MLP on pair invariants, BF16 on the matrix cores)."""
+
+    def __init__(self, nfeat, width=256, depth=4, seed=1):
+        lib = load()
+        p = me_sur_params(nfeat, width, depth, seed)
+        h = ctypes.c_void_p()
+        _check(lib.me_sur_init(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self.nfeat, self.width, self.depth = nfeat, width, depth
+        self.kpad = ((nfeat + 15) // 16) * 16
+        n = ctypes.c_int64()
+        _check(lib.me_sur_num_params(h, ctypes.byref(n)))
+        self.nparams = n.value
+
+    def _host(self, arr):
+        import numpy as np
+        arr = np.ascontiguousarray(arr, dtype=np.float32)
+        return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def me_sur_get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(load().me_sur_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size))
+        return out
+
+    def me_sur_set_params(self, flat):
+        arr, ptr = self._host(flat)
+        _check(load().me_sur_set_params(self._h, ptr, arr.size))
+
+    def me_sur_get_grads(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(load().me_sur_get_grads(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size))
+        return out
+
+    def me_sur_set_normalisation(self, mean, inv_std):
+        m, pm = self._host(mean)
+        s, ps = self._host(inv_std)
+        _check(load().me_sur_set_normalisation(self._h, pm, ps))
+
+    def me_sur_features(self, momenta, nevt, npar, feat, raw=None, stream=None):
+        _check(load().me_sur_features(self._h, _ptr(momenta), nevt, npar, _ptr(feat), _ptr(raw),
+                                      _stream(stream)))
+
+    def me_sur_predict(self, feat, n, y, stream=None):
+        _check(load().me_sur_predict(self._h, _ptr(feat), n, _ptr(y), _stream(stream)))
+
+    def me_sur_grads(self, feat, target, nb, loss=None, stream=None):
+        _check(load().me_sur_grads(self._h, _ptr(feat), _ptr(target), nb, _ptr(loss), _stream(stream)))
+
+    def me_sur_adam(self, lr, stream=None):
+        _check(load().me_sur_adam(self._h, lr, _stream(stream)))
+
+    def me_sur_train_step(self, feat, target, nb, lr, loss=None, stream=None):
+        _check(load().me_sur_train_step(self._h, _ptr(feat), _ptr(target), nb, lr, _ptr(loss),
+                                        _stream(stream)))
+
+    def me_sur_finalize(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(load().me_sur_finalize(h))
+
+    def __del__(self):
+        try:
+            self.me_sur_finalize()
+        except Exception:
+            pass
+
+
+def me_unweight_stage1(y, wps, r1, n, ymean, ystd, what_max, what, idx, stream=None):
+    """Returns the number of stage-1 events (their indices are in idx[:n_keep])."""
+    nk = ctypes.c_int64()
+    _check(load().me_unweight_stage1(_ptr(y), _ptr(wps), _ptr(r1), n, ymean, ystd, what_max, _ptr(what),
+                                     _ptr(idx), ctypes.byref(nk), _stream(stream)))
+    return nk.value
+
+
+def me_gather_momenta(momenta, idx, m, npar, out, stream=None):
+    _check(load().me_gather_momenta(_ptr(momenta), _ptr(idx), m, npar, _ptr(out), _stream(stream)))
+
+
+def me_unweight_stage2(me_exact, idx, m, wps, what, r2, what_max, x_max, resid, stream=None):
+    _check(load().me_unweight_stage2(_ptr(me_exact), _ptr(idx), m, _ptr(wps), _ptr(what), _ptr(r2),
+                                     what_max, x_max, _ptr(resid), _stream(stream)))

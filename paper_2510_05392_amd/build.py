@@ -24,6 +24,8 @@ INCLUDE = os.path.join(ROOT, 'include')
 LIB = os.path.join(HERE, 'libmegpu.so')
 
 PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg']
+# headers the generated process units include
+PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h']
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
@@ -55,7 +57,8 @@ def generate_sources(procs, build_dir):
                 f'namespace me {{\nconst ProcessDesc* process_{name}() {{ return describe<me::{name}>(); }}\n}}\n')
         path = os.path.join(GEN, f'proc_{name}.hip')
         _write_if_changed(path, unit)
-        units.append((path, os.path.join(OBJ, f'proc_{name}.o'), [inc]))
+        units.append((path, os.path.join(OBJ, f'proc_{name}.o'),
+                      [inc] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
     reg = ['// Processes compiled into this library (generated).']
     reg += [f'const ProcessDesc* process_{n}();' for n in procs]
     reg.append('static const ProcessDesc* (*const kProcesses[])() = {'
@@ -64,15 +67,15 @@ def generate_sources(procs, build_dir):
     regfile = os.path.join(build_dir, 'registry.inc')
     _write_if_changed(regfile, '\n'.join(reg) + '\n')
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
-                  [regfile, os.path.join(INCLUDE, 'megpu.h')]))
+                  [regfile, os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_process.h'),
+                   os.path.join(CSRC, 'me_error.h')]))
     units.append((os.path.join(CSRC, 'surrogate.hip'), os.path.join(OBJ, 'surrogate.o'),
-                  [os.path.join(INCLUDE, 'megpu.h')]))
+                  [os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_error.h')]))
     return units
 
 
 def _compile(src, obj, extra_deps, build_dir):
     deps = [src] + list(extra_deps)
-    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith('.h')]
     flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') else [])
     key = hashlib.sha1((' '.join(flags) + HIPCC).encode()).hexdigest()[:8]
     stamp = obj + '.flags'

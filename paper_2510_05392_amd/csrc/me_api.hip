@@ -53,6 +53,8 @@ __global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nch
   out[e] = scale * acc;
 }
 
+__global__ void zero_counter_kernel(int* c) { *c = 0; }
+
 }  // namespace
 
 struct me_ctx {
@@ -68,6 +70,21 @@ struct me_ctx {
   void* d_cf_hi = nullptr;    // colour matrix in the MFMA input format
   void* d_cf_lo = nullptr;    // its low half when the matrix is split (BF16)
   bool filtered = false;
+  // launch configuration of the FP64 path (defaults, or picked by me_autotune)
+  int persistent = 0;         // 1: persistent grid with a work counter
+  int waves_per_simd = 1;     // persistent grid size per SIMD
+  int hel_per_item = 0;       // helicities per work item (0: all)
+  int target_waves = 4096;    // grid path: waves to aim for (helicity chunks fill the rest)
+  int* d_counter = nullptr;   // persistent work counter
+  int simds = 1024;           // compute units x 4
+  // captured launch sequence of the last (momenta, out, nevt, alpha_s)
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  const void* g_mom = nullptr;
+  const void* g_out = nullptr;
+  int64_t g_nevt = -1;
+  double g_alpha = 0.0;
+  int g_mode = -1;
 };
 
 namespace {
@@ -227,6 +244,7 @@ int me_params_default(me_params* p) {
   p->mt = 173.0;
   p->colorsum_mode = ME_CS_FP64;
   p->all_helicities = 0;
+  p->use_graph = 0;
   return ME_OK;
 }
 
@@ -268,6 +286,21 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   }
   c->filtered = prm.all_helicities != 0;
   {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->simds = 4 * cus;
+  }
+  if (hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(c->d_hels);
+    (void)hipFree(c->d_scratch_hels);
+    if (c->d_counter) (void)hipFree(c->d_counter);
+    free_tables(c);
+    delete c;
+    return fail(ME_ENOMEM, "work counter / capture stream");
+  }
+  {
     std::lock_guard<std::mutex> lk(g_live_mu);
     g_live.insert(c);
   }
@@ -286,6 +319,9 @@ int me_finalize(me_handle h) {
   hipError_t e2 = hipFree(h->d_scratch_hels);
   hipError_t e3 = h->d_partial ? hipFree(h->d_partial) : hipSuccess;
   if (h->d_jamps) (void)hipFree(h->d_jamps);
+  if (h->d_counter) (void)hipFree(h->d_counter);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   free_tables(h);
   delete h;
   if (e1 != hipSuccess) return hip_fail(e1, "hipFree");
@@ -406,33 +442,54 @@ int me_filter_helicities(me_handle h, const double* momenta, int64_t nevt, doubl
   return upload_good(h, s);
 }
 
-int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
-               void* stream) {
-  int rc = check_handle(h);
-  if (rc) return rc;
-  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
-  if (nevt == 0) return ME_OK;
-  if (!momenta || !out_me2) return fail(ME_EINVAL, "null pointer");
-  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
-  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
-  hipStream_t s = (hipStream_t)stream;
-  if (!h->filtered) {
-    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
-    if (rc) return rc;
+namespace {
+
+// Size the scratch of one me_compute call (outside any capture).
+int prepare(me_ctx* h, int64_t nevt) {
+  const int nhel = (int)h->good.size();
+  if (h->params.colorsum_mode == ME_CS_FP64) {
+    size_t rows;
+    if (h->persistent) {
+      const int hpi = h->hel_per_item > 0 ? std::min(h->hel_per_item, nhel) : nhel;
+      rows = (size_t)((nhel + hpi - 1) / hpi);
+    } else {
+      rows = (size_t)nhel;   // upper bound on the number of chunks
+    }
+    return ensure_partial(h, rows * nevt);
   }
+  const size_t row_doubles = (size_t)h->desc->ncol * 2;
+  int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles * nhel));
+  chunk = std::min<int64_t>(std::max<int64_t>(64, (chunk / 64) * 64), nevt);
+  int rc = ensure_buffer(&h->d_jamps, &h->jamps_cap, (size_t)chunk * nhel * row_doubles, "jamps");
+  if (rc) return rc;
+  return ensure_partial(h, (size_t)chunk * nhel);
+}
+
+// Enqueue the kernels of one me_compute call on stream s (capturable: no
+// allocation, no synchronisation, no memset).
+int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+            hipStream_t s) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
   if (h->params.colorsum_mode == ME_CS_FP64) {
-    const int64_t blocks = (nevt + 63) / 64;
-    // enough waves to fill 256 CUs x 4 SIMDs a few times over, splitting helicities if needed
-    const int64_t target = 4096;
-    int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (target + blocks - 1) / blocks));
-    const int hpc = (nhel + nchunk - 1) / nchunk;
-    nchunk = (nhel + hpc - 1) / hpc;
-    rc = ensure_partial(h, (size_t)nchunk * nevt);
-    if (rc) return rc;
+    int nchunk, hpc;
+    if (h->persistent) {
+      hpc = h->hel_per_item > 0 ? std::min(h->hel_per_item, nhel) : nhel;
+      nchunk = (nhel + hpc - 1) / hpc;
+    } else {
+      const int64_t blocks = (nevt + 63) / 64;
+      // enough waves to fill the compute units, splitting helicities if needed
+      nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (h->target_waves + blocks - 1) / blocks));
+      hpc = (nhel + nchunk - 1) / nchunk;
+      nchunk = (nhel + hpc - 1) / hpc;
+    }
     me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
                      h->d_partial, nullptr, s};
+    if (h->persistent) {
+      hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, h->d_counter);
+      a.counter = h->d_counter;
+      a.waves = h->simds * h->waves_per_simd;
+    }
     hipError_t e = h->desc->launch(a);
     if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
     const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
@@ -448,12 +505,7 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   const int npar = h->desc->npar;
   const size_t row_doubles = (size_t)ncol * 2;
   int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles * nhel));
-  chunk = std::max<int64_t>(64, (chunk / 64) * 64);
-  chunk = std::min<int64_t>(chunk, nevt);
-  rc = ensure_buffer(&h->d_jamps, &h->jamps_cap, (size_t)chunk * nhel * row_doubles, "jamps");
-  if (rc) return rc;
-  rc = ensure_partial(h, (size_t)chunk * nhel);
-  if (rc) return rc;
+  chunk = std::min<int64_t>(std::max<int64_t>(64, (chunk / 64) * 64), nevt);
   const int fmt = h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1;
   for (int64_t off = 0; off < nevt; off += chunk) {
     const int64_t n = std::min<int64_t>(chunk, nevt - off);
@@ -469,6 +521,141 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                        h->d_partial, nhel, n, 1.0 / h->desc->iden, out_me2 + off);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  }
+  return ME_OK;
+}
+
+void drop_graph(me_ctx* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->g_nevt = -1;
+}
+
+}  // namespace
+
+int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+               void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !out_me2) return fail(ME_EINVAL, "null pointer");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->filtered) {
+    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  rc = prepare(h, nevt);
+  if (rc) return rc;
+  if (!h->params.use_graph) return enqueue(h, momenta, nevt, alpha_s, out_me2, s);
+  // replay the captured sequence when the call matches the captured one
+  if (!(h->graph && h->g_mom == momenta && h->g_out == out_me2 && h->g_nevt == nevt &&
+        h->g_alpha == alpha_s && h->g_mode == h->params.colorsum_mode)) {
+    drop_graph(h);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    rc = enqueue(h, momenta, nevt, alpha_s, out_me2, h->capture_stream);
+    e = hipStreamEndCapture(h->capture_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->graph = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    h->g_mom = momenta;
+    h->g_out = out_me2;
+    h->g_nevt = nevt;
+    h->g_alpha = alpha_s;
+    h->g_mode = h->params.colorsum_mode;
+  }
+  hipError_t e = hipGraphLaunch(h->graph, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ME_OK;
+}
+
+int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (persistent < 0 || persistent > 1 || waves_per_simd < 1 || waves_per_simd > 8 || hel_per_item < 0 ||
+      target_waves < 1)
+    return fail(ME_EINVAL, "bad launch configuration");
+  h->persistent = persistent;
+  h->waves_per_simd = waves_per_simd;
+  h->hel_per_item = hel_per_item;
+  h->target_waves = target_waves;
+  drop_graph(h);
+  return ME_OK;
+}
+
+int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+                void* stream, int32_t* best) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt <= 0 || !momenta || !out_me2) return fail(ME_EINVAL, "autotune needs events");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->filtered) {
+    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  struct Cand { int p, w, hpi, tw; };
+  std::vector<Cand> cands = {{0, 1, 0, 1024}, {0, 1, 0, 4096}, {0, 1, 0, 16384},
+                             {1, 1, 0, 0},    {1, 1, 8, 0},    {1, 2, 8, 0},
+                             {1, 1, 1, 0},    {1, 2, 1, 0}};
+  const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
+            save_tw = h->target_waves, save_graph = h->params.use_graph;
+  h->params.use_graph = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(ME_EHIP, "hipEventCreate");
+  float best_ms = 0.0f;
+  int best_i = -1;
+  for (size_t i = 0; i < cands.size() && rc == ME_OK; ++i) {
+    h->persistent = cands[i].p;
+    h->waves_per_simd = cands[i].w;
+    h->hel_per_item = cands[i].hpi;
+    h->target_waves = cands[i].tw > 0 ? cands[i].tw : save_tw;
+    rc = prepare(h, nevt);
+    if (rc == ME_OK) rc = enqueue(h, momenta, nevt, alpha_s, out_me2, s);   // warm-up
+    if (rc) break;
+    (void)hipEventRecord(a, s);
+    rc = enqueue(h, momenta, nevt, alpha_s, out_me2, s);
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess) rc = fail(ME_EHIP, "hipEventSynchronize");
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (rc == ME_OK && (best_i < 0 || ms < best_ms)) {
+      best_ms = ms;
+      best_i = (int)i;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  h->params.use_graph = save_graph;
+  drop_graph(h);
+  if (rc || best_i < 0) {
+    h->persistent = save_p;
+    h->waves_per_simd = save_w;
+    h->hel_per_item = save_hpi;
+    h->target_waves = save_tw;
+    return rc ? rc : fail(ME_EHIP, "autotune found no configuration");
+  }
+  h->persistent = cands[best_i].p;
+  h->waves_per_simd = cands[best_i].w;
+  h->hel_per_item = cands[best_i].hpi;
+  h->target_waves = cands[best_i].tw > 0 ? cands[best_i].tw : save_tw;
+  if (best) {
+    best[0] = h->persistent;
+    best[1] = h->waves_per_simd;
+    best[2] = h->hel_per_item;
+    best[3] = h->target_waves;
   }
   return ME_OK;
 }

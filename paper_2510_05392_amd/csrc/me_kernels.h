@@ -35,20 +35,21 @@ __device__ __forceinline__ void helicity_signs(int h, int* lam) {
   for (int q = 0; q < P::NPAR; ++q) lam[q] = ((h >> (P::NPAR - 1 - q)) & 1) ? 1 : -1;
 }
 
-// One lane = one event; blockIdx.y = helicity chunk c.  For every good helicity
-// of the chunk the lane evaluates all diagrams into the dual amplitudes and
-// either accumulates sum_ij CF_int Re(J_i^* J_j) into partial[c * nevt + e]
+// Work item = (event tile of 64 lanes, helicity chunk c).  For every good
+// helicity of its chunk a lane evaluates all diagrams into the dual amplitudes
+// and either accumulates sum_ij CF_int Re(J_i^* J_j) into partial[c * nevt + e]
 // (jamp_out == nullptr) or, with one helicity per chunk, stores the dual
 // amplitudes to jamp_out[((c * nevt + e) * NCOL + i) * 2 + {0, 1}].
+// Items come from the grid (counter == nullptr: block (x, y) = tile x, chunk y)
+// or, persistently, from an atomic work counter: every wave takes items until
+// the counter passes nitems, so every wave reaches the exit.  Outputs depend
+// only on the item, never on which wave ran it (bit-reproducible).
 template <class P>
-__global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, int64_t nevt,
-                                                double g, double mt, const int* __restrict__ hels,
-                                                int nhel, int hel_per_chunk,
-                                                double* __restrict__ partial,
-                                                double* __restrict__ jamp_out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (e >= nevt) return;
+__device__ __forceinline__ void run_item(const double* __restrict__ mom, int64_t nevt, double g,
+                                         double mt, const int* __restrict__ hels, int nhel,
+                                         int hel_per_chunk, int64_t e, int c,
+                                         double* __restrict__ partial,
+                                         double* __restrict__ jamp_out) {
   double p[P::NPAR][4];
   load_momenta<P>(mom, e, p);
   const int k0 = c * hel_per_chunk;
@@ -87,11 +88,37 @@ __global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, 
   if (!jamp_out) partial[(int64_t)c * nevt + e] = acc;
 }
 
+__device__ __forceinline__ int next_item(int* counter) {
+  int v = 0;
+  if (threadIdx.x == 0) v = atomicAdd(counter, 1);
+  return __shfl(v, 0);
+}
+
+template <class P>
+__global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, int64_t nevt,
+                                                double g, double mt, const int* __restrict__ hels,
+                                                int nhel, int hel_per_chunk, int ntiles, int nitems,
+                                                int* __restrict__ counter,
+                                                double* __restrict__ partial,
+                                                double* __restrict__ jamp_out) {
+  int item = counter ? next_item(counter) : (int)(blockIdx.x + (int64_t)ntiles * blockIdx.y);
+  while (item < nitems) {
+    const int tile = item % ntiles;
+    const int c = item / ntiles;
+    const int64_t e = (int64_t)tile * 64 + threadIdx.x;
+    if (e < nevt) run_item<P>(mom, nevt, g, mt, hels, nhel, hel_per_chunk, e, c, partial, jamp_out);
+    if (!counter) break;
+    item = next_item(counter);
+  }
+}
+
 template <class P>
 hipError_t launch(const LaunchArgs& a) {
-  const dim3 grid((unsigned)((a.nevt + 63) / 64), (unsigned)a.nchunk);
+  const int ntiles = (int)((a.nevt + 63) / 64);
+  const int nitems = ntiles * a.nchunk;
+  const dim3 grid = a.counter ? dim3((unsigned)a.waves) : dim3((unsigned)ntiles, (unsigned)a.nchunk);
   hipLaunchKernelGGL(me_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt, a.hels,
-                     a.nhel, a.hel_per_chunk, a.out, a.jamp_out);
+                     a.nhel, a.hel_per_chunk, ntiles, nitems, a.counter, a.out, a.jamp_out);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ struct LaunchArgs {
   double* out;          // device, partial sums [nchunk][nevt] (unused when jamp_out is set)
   double* jamp_out;     // device, dual amplitudes [nhel][nevt][ncol][2], or nullptr
   hipStream_t stream;
+  int* counter = nullptr;  // device work counter (zeroed before the launch) for a persistent grid
+  int waves = 0;           // persistent grid size (wavefronts) when counter is set
 };
 
 using Launcher = hipError_t (*)(const LaunchArgs&);

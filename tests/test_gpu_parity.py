@@ -284,3 +284,61 @@ def test_set_colorsum_mode(binding):
     assert np.max(np.abs(b / a - 1)) < MIXED_BOUND[2]
     with pytest.raises(binding.MeError):
         m.me_set_colorsum_mode(7)
+
+
+# --- launch configurations, graph replay, autotuner -------------------------------
+
+def test_persistent_launch_matches_grid_launch(binding):
+    _say('case persistent launch gg_ttxgg 197 events')
+    mom = rambo.generate(6, 197, 21)
+    d = _dev(mom)
+    m = binding.MatrixElement('gg_ttxgg')
+    a = m.compute(d, AS).cpu().numpy()
+    for cfg in ((1, 1, 0), (1, 2, 8), (1, 1, 1)):
+        m.me_set_launch(cfg[0], cfg[1], cfg[2], 4096)
+        b = m.compute(d, AS).cpu().numpy()
+        assert np.max(np.abs(b / a - 1)) < 1e-14, cfg
+        assert np.array_equal(b, m.compute(d, AS).cpu().numpy())     # reproducible
+    with pytest.raises(binding.MeError):
+        m.me_set_launch(2, 1, 0, 4096)
+
+
+@pytest.mark.parametrize('mode', [0, 1])
+def test_graph_replay_matches_eager(binding, mode):
+    _say(f'case graph replay gg_ttxg mode={mode}')
+    mom = rambo.generate(5, 300, 31)
+    mom2 = rambo.generate(5, 300, 32)
+    eager = binding.MatrixElement('gg_ttxg', colorsum_mode=mode)
+    graph = binding.MatrixElement('gg_ttxg', colorsum_mode=mode, use_graph=True)
+    d = _dev(mom)
+    out = torch.empty(300, dtype=torch.float64, device='cuda')
+    ref = eager.compute(d, AS).cpu().numpy()
+    ref2 = eager.compute(_dev(mom2), AS).cpu().numpy()
+    s = torch.cuda.current_stream()
+    for rep in range(4):
+        # new contents in the same buffer between replays, with eager work in between
+        d.copy_(torch.from_numpy(mom if rep % 2 == 0 else mom2))
+        torch.cuda.synchronize()
+        graph.me_compute(d, 300, AS, out, s)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got, ref if rep % 2 == 0 else ref2), rep
+        _ = eager.compute(d, AS)
+    # a different batch size is captured afresh
+    graph.me_compute(d[:100].contiguous(), 100, AS, out, s)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(out[:100].cpu().numpy() / ref2[:100] - 1)) < 1e-14
+
+
+def test_autotune_keeps_results(binding):
+    _say('case autotune gg_ttxgg 8192 events')
+    mom = rambo.generate(6, 8192, 41)
+    d = _dev(mom)
+    m = binding.MatrixElement('gg_ttxgg')
+    ref = m.compute(d, AS).cpu().numpy()
+    out = torch.empty(8192, dtype=torch.float64, device='cuda')
+    best = m.me_autotune(d, 8192, AS, out)
+    _say(f'  chosen {best}')
+    assert best['persistent'] in (0, 1)
+    got = m.compute(d, AS).cpu().numpy()
+    assert np.max(np.abs(got / ref - 1)) < 1e-14
