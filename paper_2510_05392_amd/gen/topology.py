@@ -434,13 +434,59 @@ class Plan:
             groups[key].append((lead, amp))
         return [(k, groups[k]) for k in order]
 
-    def scheduled_groups(self, alpha=1.0):
+    def peak_live(self, groups):
+        """Largest number of currents alive at once when groups run in this order."""
+        events = []
+        seen = set()
+
+        def need(k):
+            if k in seen:
+                return
+            for d in self.objects[k]:
+                need(d)
+            seen.add(k)
+            events.append(('obj', k))
+
+        for gi, (key, members) in enumerate(groups):
+            for lead, amp in members:
+                for o in amp[1:]:
+                    need(o)
+            events.append(('grp', gi))
+        last = {}
+        for i, ev in enumerate(events):
+            if ev[0] == 'obj':
+                for d in self.objects[ev[1]]:
+                    last[d] = i
+            else:
+                for lead, amp in groups[ev[1]][1]:
+                    for o in amp[1:]:
+                        last[o] = i
+        alive, peak = set(), 0
+        for i, ev in enumerate(events):
+            if ev[0] == 'obj':
+                alive.add(ev[1])
+            peak = max(peak, len(alive))
+            if ev[0] == 'grp':
+                alive = {o for o in alive if last.get(o, -1) > i}
+        return peak
+
+    def scheduled_groups(self, alphas=(0.5, 0.75, 1.0)):
         """colour_groups() reordered to keep few currents alive at once.
 
         List scheduling: repeatedly emit the group whose evaluation creates the
-        fewest new currents net of the currents it retires (a current retires
-        after its last consumer); the order only affects register pressure.
+        fewest new currents net of alpha x the currents it retires (a current
+        retires after its last consumer); the order with the smallest peak over
+        a few alphas is kept.  The order only affects register pressure.
         """
+        best = None
+        for a in alphas:
+            order = self._schedule(a)
+            pk = self.peak_live(order)
+            if best is None or pk < best[0]:
+                best = (pk, order)
+        return best[1]
+
+    def _schedule(self, alpha):
         groups = self.colour_groups()
         gops = []
         for key, members in groups:
