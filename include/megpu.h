@@ -78,6 +78,30 @@ int me_init(const char* process, const me_params* p, me_handle* out);
 int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                double* out_me2, void* stream);
 
+/* As me_compute with a running coupling: alpha_s[i] (device, [nevt]) is the
+ * strong coupling of event i, g_i = sqrt(4 pi alpha_s[i]) (the paper's engine
+ * takes alpha_s per event from a scale computed outside it).  Never replayed
+ * from a captured graph.  The helicity filter, if it has not run, uses
+ * alpha_s = 0.118 (which helicities contribute does not depend on it). */
+int me_compute_alphas(me_handle h, const double* momenta, int64_t nevt, const double* alpha_s,
+                      double* out_me2, void* stream);
+
+/* Helicity and colour selection for event output (the paper's engine returns
+ * one helicity and one leading colour per event, drawn with two random
+ * numbers).  With r_hel[i], r_col[i] in [0, 1) (device, [nevt]):
+ *   sel_hel[i] = the good helicity h drawn with probability ME_h / ME (inverse
+ *                CDF over the good helicities in ascending order: the first h
+ *                whose running sum exceeds r_hel * ME), as a helicity index
+ *                in [0, 2^npar) (bit npar-1-q set = particle q has helicity +1);
+ *   sel_col[i] = the colour flow drawn with probability |J_c(h)|^2 /
+ *                sum_c' |J_c'(h)|^2 for that helicity (same inverse-CDF rule
+ *                over the flows in the order of me_jamps);
+ *   out_me2[i] = as me_compute (FP64).
+ * All outputs are device arrays of nevt entries.  Costs one me_compute plus
+ * one helicity's dual amplitudes per event. */
+int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, const double* r_hel,
+              const double* r_col, double* out_me2, int32_t* sel_hel, int32_t* sel_col, void* stream);
+
 /* Helicity filter (the paper's good-helicity selection): evaluates every
  * helicity on the first min(nevt, 16) events and keeps h when
  * max_events ME_h / ME > 1e-14.  Synchronises the stream. */
@@ -123,6 +147,22 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
  * NULL) receives (persistent, waves_per_simd, hel_per_item, target_waves). */
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
+
+/* Uneven multi-process batch in one persistent launch (the paper evaluates one
+ * process per executable; batching several is an addition).  Segment i is
+ * process hs[i] on momenta[i] ([nevts[i]][npar_i][4], device) with results in
+ * outs[i] ([nevts[i]], device), all at the same alpha_s.  Work items
+ * (segment, 64-event tile, good helicity) are numbered heaviest process first
+ * and taken from one atomic counter by a persistent grid; per-helicity partial
+ * sums go to each handle's own scratch and are reduced in fixed order, so the
+ * results equal those of me_compute in ME_CS_FP64 mode up to the rounding
+ * order of the helicity sum, whatever the handles' colour-sum modes.
+ * 1 <= nproc <= 8; a handle may appear once; segments with nevts[i] = 0 are
+ * skipped.  Handles not yet filtered run their helicity filter first
+ * (synchronising the stream).  Errors: ME_EINVAL for bad sizes, null pointers
+ * or a repeated handle, ME_ESTATE for a dead handle. */
+int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* momenta,
+                     const int64_t* nevts, double alpha_s, double* const* outs, void* stream);
 
 /* Release the handle and everything it owns.  Finalising a handle twice, or
  * using it afterwards, returns ME_ESTATE; passing NULL is a no-op. */

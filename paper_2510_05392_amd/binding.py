@@ -25,7 +25,9 @@ ME_CS_BF16X2 = 2
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
-           'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_finalize',
+           'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
+           'me_compute_alphas', 'me_select',
+           'me_finalize',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
            'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
@@ -73,6 +75,10 @@ def load(path=LIB_PATH):
     lib.me_set_colorsum_mode.argtypes = [vp, ctypes.c_int]
     lib.me_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.me_autotune.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, i32p]
+    lib.me_compute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(i64), ctypes.c_double, ctypes.POINTER(vp), vp]
+    lib.me_compute_alphas.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.me_select.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.me_finalize.argtypes = [vp]
     fp, dbl = ctypes.POINTER(ctypes.c_float), ctypes.c_double
     lib.me_sur_init.argtypes = [ctypes.POINTER(me_sur_params), ctypes.POINTER(vp)]
@@ -113,6 +119,17 @@ def _stream(stream):
     return ctypes.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
 
 
+def me_compute_batch(handles, momenta, nevts, alpha_s, outs, stream=None):
+    """One launch over several processes: handles[i] (MatrixElement) on momenta[i] -> outs[i]."""
+    n = len(handles)
+    vp = ctypes.c_void_p
+    hs = (vp * n)(*[h._h.value for h in handles])
+    ms = (vp * n)(*[_ptr(m).value for m in momenta])
+    ns = (ctypes.c_int64 * n)(*nevts)
+    os_ = (vp * n)(*[_ptr(o).value for o in outs])
+    _check(load().me_compute_batch(n, hs, ms, ns, alpha_s, os_, _stream(stream)))
+
+
 class MatrixElement:
     """One handle of the C ABI for one process."""
 
@@ -136,6 +153,14 @@ class MatrixElement:
     # the binding names mirror the C entry points
     def me_compute(self, momenta, nevt, alpha_s, out, stream=None):
         _check(load().me_compute(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream)))
+
+    def me_compute_alphas(self, momenta, nevt, alpha_s, out, stream=None):
+        _check(load().me_compute_alphas(self._h, _ptr(momenta), nevt, _ptr(alpha_s), _ptr(out),
+                                        _stream(stream)))
+
+    def me_select(self, momenta, nevt, alpha_s, r_hel, r_col, out, sel_hel, sel_col, stream=None):
+        _check(load().me_select(self._h, _ptr(momenta), nevt, alpha_s, _ptr(r_hel), _ptr(r_col), _ptr(out),
+                                _ptr(sel_hel), _ptr(sel_col), _stream(stream)))
 
     def me_filter_helicities(self, momenta, nevt, alpha_s, stream=None):
         _check(load().me_filter_helicities(self._h, _ptr(momenta), nevt, alpha_s, _stream(stream)))

@@ -29,7 +29,8 @@ PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h']
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
-         # packed FP32 instructions stay off ("hardware notes")
+         # the compiler may not form packed FP32 (v_pk_*_f32) instructions: they
+         # are kept out of every kernel as a correctness precaution
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
          '-I', INCLUDE, '-I', CSRC, '-I', GEN]
 
@@ -64,8 +65,20 @@ def generate_sources(procs, build_dir):
     reg.append('static const ProcessDesc* (*const kProcesses[])() = {'
                + ', '.join(f'process_{n}' for n in procs) + '};')
     reg.append(f'static const int kNumProcesses = {len(procs)};')
+    reg.append('// one persistent kernel over all of them (multi-process batches)')
+    reg.append('hipError_t launch_batch_all(const BatchArgs& a, int waves, hipStream_t stream);')
+    batch = ['// Multi-process batch kernel over the processes of this library (generated).']
+    batch += [f'#include "{n}.inc"' for n in procs]
+    batch += ['#include "me_kernels.h"', 'namespace me {',
+              'hipError_t launch_batch_all(const BatchArgs& a, int waves, hipStream_t stream) {',
+              '  return launch_batch<' + ', '.join(f'me::{n}' for n in procs) + '>(a, waves, stream);',
+              '}', '}']
+    batchfile = os.path.join(build_dir, 'batch.hip')
+    _write_if_changed(batchfile, '\n'.join(batch) + '\n')
     regfile = os.path.join(build_dir, 'registry.inc')
     _write_if_changed(regfile, '\n'.join(reg) + '\n')
+    units.insert(0, (batchfile, os.path.join(build_dir, 'batch.o'),
+                     [os.path.join(GEN, f'{n}.inc') for n in procs] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
                   [regfile, os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_process.h'),
                    os.path.join(CSRC, 'me_error.h')]))
@@ -74,12 +87,12 @@ def generate_sources(procs, build_dir):
     return units
 
 
-def _compile(src, obj, extra_deps, build_dir):
+def _compile(src, obj, extra_deps, build_dir, force=False):
     deps = [src] + list(extra_deps)
-    flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') else [])
+    flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') or src.startswith(build_dir) else [])
     key = hashlib.sha1((' '.join(flags) + HIPCC).encode()).hexdigest()[:8]
     stamp = obj + '.flags'
-    if (os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
+    if (not force and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
             and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps)):
         return obj, False
     # the resource-usage remarks (registers, spills, occupancy) are kept next to the object
@@ -95,17 +108,20 @@ def _compile(src, obj, extra_deps, build_dir):
     return obj, True
 
 
-def build(procs=None, jobs=None, verbose=True, lib=LIB):
-    """Generate, compile and link; objects are reused when their inputs are unchanged."""
+def build(procs=None, jobs=None, verbose=True, lib=LIB, force=False):
+    """Generate, compile and link.  Objects are reused when their inputs are
+    unchanged, unless force is set (then every unit is compiled again)."""
     procs = list(procs or PROCESSES)
     tag = hashlib.sha1(','.join(procs).encode()).hexdigest()[:10]
     build_dir = os.path.join(ROOT, '_build', f'set_{tag}')
     os.makedirs(OBJ, exist_ok=True)
     units = generate_sources(procs, build_dir)
+    # the largest units first: the batch kernel and the process with most diagrams
+    units.sort(key=lambda u: (not u[0].endswith('batch.hip'), -len(os.path.basename(u[0]))))
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, src, obj, deps, build_dir): src for src, obj, deps in units}
+        futs = {ex.submit(_compile, src, obj, deps, build_dir, force): src for src, obj, deps in units}
         for f in cf.as_completed(futs):
             obj, rebuilt = f.result()
             objs.append(obj)
@@ -127,8 +143,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--procs', default=','.join(PROCESSES))
     ap.add_argument('-j', type=int, default=None)
+    ap.add_argument('--force', action='store_true', help='compile every unit again')
     args = ap.parse_args()
-    build(args.procs.split(','), args.j)
+    build(args.procs.split(','), args.j, force=args.force)
 
 
 if __name__ == '__main__':

@@ -55,10 +55,60 @@ __global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nch
 
 __global__ void zero_counter_kernel(int* c) { *c = 0; }
 
+// Inverse-CDF draw over non-negative weights w[k * stride + e], k = 0..n-1, in
+// ascending k: the first k whose running sum exceeds r * total; when rounding
+// leaves none (r close to 1), the last k with a positive weight.
+__device__ int draw(const double* __restrict__ w, int n, int64_t stride, int64_t e, double r,
+                    double* total) {
+  double tot = 0.0;
+  for (int k = 0; k < n; ++k) tot += w[k * stride + e];
+  const double t = r * tot;
+  double cum = 0.0;
+  int pick = -1, last = 0;
+  for (int k = 0; k < n; ++k) {
+    const double x = w[k * stride + e];
+    cum += x;
+    if (x > 0.0) last = k;
+    if (pick < 0 && t < cum) pick = k;
+  }
+  *total = tot;
+  return pick < 0 ? last : pick;
+}
+
+// Helicity draw with probability ME_h / ME from the per-helicity sums
+// partial[k][e] (k over the good helicities); also writes the summed |M|^2.
+__global__ void select_hel_kernel(const double* __restrict__ partial, int nhel, int64_t nevt,
+                                  const int* __restrict__ hels, const double* __restrict__ r,
+                                  double scale, double* __restrict__ out, int* __restrict__ sel) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double tot;
+  const int k = draw(partial, nhel, nevt, e, r[e], &tot);
+  sel[e] = hels[k];
+  out[e] = scale * tot;
+}
+
+// Colour-flow draw with probability |J_i|^2 / sum_j |J_j|^2 from the dual
+// amplitudes jamps[e][i][2] of the drawn helicity.
+__global__ void select_col_kernel(const double* __restrict__ jamps, int ncol, int64_t nevt,
+                                  const double* __restrict__ r, double* __restrict__ w,
+                                  int* __restrict__ sel) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  // weights staged as w[i][e] so that draw() reads them like the helicity sums
+  for (int i = 0; i < ncol; ++i) {
+    const double re = jamps[(e * ncol + i) * 2], im = jamps[(e * ncol + i) * 2 + 1];
+    w[i * nevt + e] = re * re + im * im;
+  }
+  double tot;
+  sel[e] = draw(w, ncol, nevt, e, r[e], &tot);
+}
+
 }  // namespace
 
 struct me_ctx {
   const me::ProcessDesc* desc = nullptr;
+  int proc_index = 0;         // position in the library's process list (batch kernel)
   me_params params{};
   std::vector<int> good;      // host copy of the good helicities
   int* d_hels = nullptr;      // device, good helicities (capacity nhel)
@@ -100,8 +150,17 @@ int check_handle(me_handle h) {
   return ME_OK;
 }
 
+// A captured launch sequence refers to the scratch buffers by address: it is
+// dropped whenever one of them is reallocated.
+void drop_graph(me_ctx* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->g_nevt = -1;
+}
+
 int ensure_partial(me_ctx* c, size_t n) {
   if (n <= c->partial_cap) return ME_OK;
+  drop_graph(c);
   if (c->d_partial) {
     hipError_t e = hipFree(c->d_partial);
     c->d_partial = nullptr;
@@ -137,6 +196,14 @@ int upload_scratch_hels(me_ctx* c, const int32_t* hels, int32_t nh, hipStream_t 
 }
 
 double coupling(double alpha_s) { return std::sqrt(4.0 * M_PI * alpha_s); }
+
+int ensure_buffer(double** buf, size_t* cap, size_t n, const char* what);
+
+int ensure_jamps(me_ctx* c, size_t n) {
+  if (n <= c->jamps_cap) return ME_OK;
+  drop_graph(c);
+  return ensure_buffer(&c->d_jamps, &c->jamps_cap, n, "jamps");
+}
 
 int ensure_buffer(double** buf, size_t* cap, size_t n, const char* what) {
   if (n <= *cap) return ME_OK;
@@ -252,9 +319,13 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   if (!process || !out) return fail(ME_EINVAL, "null argument");
   *out = nullptr;
   const me::ProcessDesc* desc = nullptr;
+  int proc_index = -1;
   for (int i = 0; i < me::kNumProcesses; ++i) {
     const me::ProcessDesc* d = me::kProcesses[i]();
-    if (std::strcmp(d->name, process) == 0) desc = d;
+    if (std::strcmp(d->name, process) == 0) {
+      desc = d;
+      proc_index = i;
+    }
   }
   if (!desc) return fail(ME_EINVAL, std::string("unknown process: ") + process);
   me_params prm;
@@ -265,6 +336,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   me_ctx* c = new (std::nothrow) me_ctx;
   if (!c) return fail(ME_ENOMEM, "host allocation failed");
   c->desc = desc;
+  c->proc_index = proc_index;
   c->params = prm;
   c->good.resize(desc->nhel);
   for (int k = 0; k < desc->nhel; ++k) c->good[k] = k;
@@ -460,7 +532,7 @@ int prepare(me_ctx* h, int64_t nevt) {
   const size_t row_doubles = (size_t)h->desc->ncol * 2;
   int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles * nhel));
   chunk = std::min<int64_t>(std::max<int64_t>(64, (chunk / 64) * 64), nevt);
-  int rc = ensure_buffer(&h->d_jamps, &h->jamps_cap, (size_t)chunk * nhel * row_doubles, "jamps");
+  int rc = ensure_jamps(h, (size_t)chunk * nhel * row_doubles);
   if (rc) return rc;
   return ensure_partial(h, (size_t)chunk * nhel);
 }
@@ -468,7 +540,7 @@ int prepare(me_ctx* h, int64_t nevt) {
 // Enqueue the kernels of one me_compute call on stream s (capturable: no
 // allocation, no synchronisation, no memset).
 int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
-            hipStream_t s) {
+            hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
   if (h->params.colorsum_mode == ME_CS_FP64) {
@@ -485,6 +557,7 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     }
     me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
                      h->d_partial, nullptr, s};
+    a.alphas = alphas;
     if (h->persistent) {
       hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, h->d_counter);
       a.counter = h->d_counter;
@@ -511,6 +584,7 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     const int64_t n = std::min<int64_t>(chunk, nevt - off);
     me::LaunchArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, 1, nhel,
                      nullptr, h->d_jamps, s};
+    a.alphas = alphas ? alphas + off : nullptr;
     hipError_t e = h->desc->launch(a);
     if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
     me::ColourArgs ca{h->d_jamps, n * nhel, fmt, h->d_cf_hi, h->d_cf_lo,
@@ -523,12 +597,6 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
   }
   return ME_OK;
-}
-
-void drop_graph(me_ctx* h) {
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  h->graph = nullptr;
-  h->g_nevt = -1;
 }
 
 }  // namespace
@@ -578,6 +646,149 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   }
   hipError_t e = hipGraphLaunch(h->graph, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ME_OK;
+}
+
+int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* momenta,
+                     const int64_t* nevts, double alpha_s, double* const* outs, void* stream) {
+  if (nproc < 1 || nproc > me::kBatchMaxSeg) return fail(ME_EINVAL, "nproc must be in [1, 8]");
+  if (!hs || !momenta || !nevts || !outs) return fail(ME_EINVAL, "null argument");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < nproc; ++i) {
+    int rc = check_handle(hs[i]);
+    if (rc) return rc;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(ME_EINVAL, "a handle may appear only once in a batch");
+    if (nevts[i] < 0 || nevts[i] > (int64_t)64 * 0x7fffff) return fail(ME_EINVAL, "bad nevt");
+    if (nevts[i] > 0 && (!momenta[i] || !outs[i])) return fail(ME_EINVAL, "null pointer");
+  }
+  // segments with events, heaviest process first so that the tail of the
+  // persistent grid runs the cheapest items
+  std::vector<int> order;
+  for (int i = 0; i < nproc; ++i)
+    if (nevts[i] > 0) order.push_back(i);
+  if (order.empty()) return ME_OK;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return hs[a]->desc->ndiag > hs[b]->desc->ndiag; });
+  for (int i : order) {
+    me_ctx* h = hs[i];
+    if (!h->filtered) {
+      int rc = me_filter_helicities(h, momenta[i], nevts[i], alpha_s, stream);
+      if (rc) return rc;
+    }
+    int rc = ensure_partial(h, h->good.size() * (size_t)nevts[i]);
+    if (rc) return rc;
+  }
+  me::BatchArgs a{};
+  int64_t items = 0;
+  for (int i : order) {
+    me_ctx* h = hs[i];
+    me::BatchSeg& g = a.seg[a.nseg++];
+    g.mom = momenta[i];
+    g.nevt = nevts[i];
+    g.g = coupling(alpha_s);
+    g.mt = h->params.mt;
+    g.hels = h->d_hels;
+    g.nhel = (int)h->good.size();
+    g.ntiles = (int)((nevts[i] + 63) / 64);
+    g.item0 = (int)items;
+    g.proc = h->proc_index;
+    g.partial = h->d_partial;
+    items += (int64_t)g.ntiles * g.nhel;
+    if (items > 0x7fffffff) return fail(ME_EINVAL, "batch has too many work items");
+  }
+  a.nitems = (int)items;
+  me_ctx* h0 = hs[order[0]];
+  a.counter = h0->d_counter;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, a.counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+  e = me::launch_batch_all(a, h0->simds * 2, s);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  for (int i : order) {
+    me_ctx* h = hs[i];
+    const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevts[i] + 255) / 256)), dim3(256), 0, s,
+                       h->d_partial, (int)h->good.size(), nevts[i], scale, outs[i]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  }
+  return ME_OK;
+}
+
+int me_compute_alphas(me_handle h, const double* momenta, int64_t nevt, const double* alpha_s,
+                      double* out_me2, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !alpha_s || !out_me2) return fail(ME_EINVAL, "null pointer");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  if (!h->filtered) {
+    // the filter needs one coupling; the good helicities do not depend on it
+    rc = me_filter_helicities(h, momenta, nevt, 0.118, stream);
+    if (rc) return rc;
+  }
+  rc = prepare(h, nevt);
+  if (rc) return rc;
+  return enqueue(h, momenta, nevt, 0.118, out_me2, (hipStream_t)stream, alpha_s);
+}
+
+int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, const double* r_hel,
+              const double* r_col, double* out_me2, int32_t* sel_hel, int32_t* sel_col, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !r_hel || !r_col || !out_me2 || !sel_hel || !sel_col)
+    return fail(ME_EINVAL, "null pointer");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->filtered) {
+    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  const int nhel = (int)h->good.size();
+  const int ncol = h->desc->ncol;
+  const int npar = h->desc->npar;
+  // scratch: per-helicity sums [nhel][nevt], later the flow weights of an event
+  // chunk [ncol][chunk]; the dual amplitudes of an event chunk [chunk][ncol][2]
+  const size_t row_doubles = (size_t)ncol * 2;
+  int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles));
+  chunk = std::min<int64_t>(std::max<int64_t>(64, (chunk / 64) * 64), nevt);
+  rc = ensure_partial(h, std::max<size_t>((size_t)nhel * nevt, (size_t)chunk * ncol));
+  if (rc) return rc;
+  rc = ensure_jamps(h, (size_t)chunk * row_doubles);
+  if (rc) return rc;
+  const double g = coupling(alpha_s);
+  // 1. per-helicity colour sums, one helicity per chunk
+  me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, 1, nhel, h->d_partial, nullptr, s};
+  hipError_t e = h->desc->launch(a);
+  if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
+  // 2. helicity draw and the summed |M|^2
+  const unsigned nb = (unsigned)((nevt + 255) / 256);
+  const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+  hipLaunchKernelGGL(select_hel_kernel, dim3(nb), dim3(256), 0, s, h->d_partial, nhel, nevt, h->d_hels,
+                     r_hel, scale, out_me2, (int*)sel_hel);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "helicity selection launch");
+  // 3. dual amplitudes of the drawn helicity of each event, in event chunks that
+  //    fit the staging buffer, and 4. the colour-flow draw (the per-helicity sums
+  //    are no longer needed: their buffer holds the flow weights)
+  for (int64_t off = 0; off < nevt; off += chunk) {
+    const int64_t n = std::min<int64_t>(chunk, nevt - off);
+    me::LaunchArgs b{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, 1, 1, 1, nullptr,
+                     h->d_jamps, s};
+    b.hel_of_event = (const int*)sel_hel + off;
+    e = h->desc->launch(b);
+    if (e != hipSuccess) return hip_fail(e, "dual-amplitude kernel launch");
+    hipLaunchKernelGGL(select_col_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_jamps,
+                       ncol, n, r_col + off, h->d_partial, (int*)sel_col + off);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "colour selection launch");
+  }
   return ME_OK;
 }
 

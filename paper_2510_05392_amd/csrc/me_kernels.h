@@ -44,20 +44,26 @@ __device__ __forceinline__ void helicity_signs(int h, int* lam) {
 // or, persistently, from an atomic work counter: every wave takes items until
 // the counter passes nitems, so every wave reaches the exit.  Outputs depend
 // only on the item, never on which wave ran it (bit-reproducible).
+// Optional per-event inputs: alphas[e] replaces the fixed coupling by
+// sqrt(4 pi alphas[e]) (running alpha_s), and hel_of_event[e] replaces the
+// helicity list by one helicity per event (nhel = hel_per_chunk = 1).
 template <class P>
 __device__ __forceinline__ void run_item(const double* __restrict__ mom, int64_t nevt, double g,
                                          double mt, const int* __restrict__ hels, int nhel,
                                          int hel_per_chunk, int64_t e, int c,
                                          double* __restrict__ partial,
-                                         double* __restrict__ jamp_out) {
+                                         double* __restrict__ jamp_out,
+                                         const double* __restrict__ alphas = nullptr,
+                                         const int* __restrict__ hel_of_event = nullptr) {
   double p[P::NPAR][4];
   load_momenta<P>(mom, e, p);
+  if (alphas) g = sqrt(4.0 * 3.14159265358979323846 * alphas[e]);
   const int k0 = c * hel_per_chunk;
   const int k1 = min(nhel, k0 + hel_per_chunk);
   double acc = 0.0;
   for (int k = k0; k < k1; ++k) {
     int lam[P::NPAR];
-    helicity_signs<P>(hels[k], lam);
+    helicity_signs<P>(hel_of_event ? hel_of_event[e] : hels[k], lam);
     // Opaque copy of the momenta: keeps the compiler from hoisting the
     // helicity-independent parts of the diagram code out of this loop, which
     // would keep hundreds of intermediates alive across iterations.
@@ -100,16 +106,58 @@ __global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, 
                                                 int nhel, int hel_per_chunk, int ntiles, int nitems,
                                                 int* __restrict__ counter,
                                                 double* __restrict__ partial,
-                                                double* __restrict__ jamp_out) {
+                                                double* __restrict__ jamp_out,
+                                                const double* __restrict__ alphas,
+                                                const int* __restrict__ hel_of_event) {
   int item = counter ? next_item(counter) : (int)(blockIdx.x + (int64_t)ntiles * blockIdx.y);
   while (item < nitems) {
     const int tile = item % ntiles;
     const int c = item / ntiles;
     const int64_t e = (int64_t)tile * 64 + threadIdx.x;
-    if (e < nevt) run_item<P>(mom, nevt, g, mt, hels, nhel, hel_per_chunk, e, c, partial, jamp_out);
+    if (e < nevt)
+      run_item<P>(mom, nevt, g, mt, hels, nhel, hel_per_chunk, e, c, partial, jamp_out, alphas,
+                  hel_of_event);
     if (!counter) break;
     item = next_item(counter);
   }
+}
+
+// Multi-process batch: one persistent grid serves every segment.  The
+// segment of an item is found by a wave-uniform scan; the segment record is
+// then copied out of the kernel arguments with static indices only.
+template <class... Ps>
+__device__ __forceinline__ void run_batch_item(const BatchSeg& s, int64_t e, int k) {
+  int i = 0;
+  ((s.proc == i++ ? run_item<Ps>(s.mom, s.nevt, s.g, s.mt, s.hels, s.nhel, 1, e, k, s.partial, nullptr)
+                  : (void)0),
+   ...);
+}
+
+template <class... Ps>
+__global__ void __launch_bounds__(64) batch_kernel(BatchArgs a) {
+  int item = next_item(a.counter);
+  while (item < a.nitems) {
+    int si = 0;
+#pragma unroll
+    for (int i = 1; i < kBatchMaxSeg; ++i)
+      if (i < a.nseg && item >= a.seg[i].item0) si = i;
+    BatchSeg s = a.seg[0];
+#pragma unroll
+    for (int i = 1; i < kBatchMaxSeg; ++i)
+      if (i == si) s = a.seg[i];
+    const int local = item - s.item0;
+    const int tile = local % s.ntiles;
+    const int k = local / s.ntiles;
+    const int64_t e = (int64_t)tile * 64 + threadIdx.x;
+    if (e < s.nevt) run_batch_item<Ps...>(s, e, k);
+    item = next_item(a.counter);
+  }
+}
+
+template <class... Ps>
+hipError_t launch_batch(const BatchArgs& a, int waves, hipStream_t stream) {
+  hipLaunchKernelGGL((batch_kernel<Ps...>), dim3((unsigned)waves), dim3(64), 0, stream, a);
+  return hipGetLastError();
 }
 
 template <class P>
@@ -118,7 +166,8 @@ hipError_t launch(const LaunchArgs& a) {
   const int nitems = ntiles * a.nchunk;
   const dim3 grid = a.counter ? dim3((unsigned)a.waves) : dim3((unsigned)ntiles, (unsigned)a.nchunk);
   hipLaunchKernelGGL(me_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt, a.hels,
-                     a.nhel, a.hel_per_chunk, ntiles, nitems, a.counter, a.out, a.jamp_out);
+                     a.nhel, a.hel_per_chunk, ntiles, nitems, a.counter, a.out, a.jamp_out, a.alphas,
+                     a.hel_of_event);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ struct LaunchArgs {
   hipStream_t stream;
   int* counter = nullptr;  // device work counter (zeroed before the launch) for a persistent grid
   int waves = 0;           // persistent grid size (wavefronts) when counter is set
+  const double* alphas = nullptr;   // device, per-event alpha_s [nevt], or nullptr (use g)
+  const int* hel_of_event = nullptr;  // device, one helicity index per event [nevt], or nullptr
 };
 
 using Launcher = hipError_t (*)(const LaunchArgs&);
@@ -36,6 +38,34 @@ struct ColourArgs {
 };
 
 using ColourLauncher = hipError_t (*)(const ColourArgs&);
+
+// One process segment of a multi-process batch: its events, coupling, good
+// helicities and the per-helicity partial sums [nhel][nevt] it writes.
+constexpr int kBatchMaxSeg = 8;
+
+struct BatchSeg {
+  const double* mom;    // device, [nevt][npar][4]
+  int64_t nevt;
+  double g;
+  double mt;
+  const int* hels;      // device, good helicities
+  int nhel;
+  int ntiles;           // (nevt + 63) / 64
+  int item0;            // first work item of the segment
+  int proc;             // index of the process in the batch kernel's process list
+  double* partial;      // device, [nhel][nevt]
+};
+
+// Work items (segment, 64-event tile, helicity) are numbered segment by segment;
+// waves take them from an atomic counter (zeroed before the launch).
+struct BatchArgs {
+  BatchSeg seg[kBatchMaxSeg];
+  int nseg;
+  int nitems;
+  int* counter;
+};
+
+using BatchLauncher = hipError_t (*)(const BatchArgs&, int waves, hipStream_t);
 
 struct ProcessDesc {
   const char* name;
