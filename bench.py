@@ -195,7 +195,8 @@ def main():
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS, 'traffic': None,
                      'flops_per_event_helicity': f_unit,
-                     'kernel': f'me_kernel<{process}> (+ reduce_chunks_kernel, <0.1%)'},
+                     'kernel': (f'team_kernel<{process}_team>' if tuned and tuned.get('executor') == 1
+                                else f'me_kernel<{process}>') + ' (+ reduce_chunks_kernel, <0.1%)'},
     }
     if mixed is not None:
         line['mixed'] = mixed

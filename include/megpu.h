@@ -52,6 +52,12 @@ extern "C" {
                            significant bits is split hi + lo as well) */
 
 /* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
+/* Executors of the FP64 path (me_set_executor) */
+#define ME_EXEC_LANE 0  /* one lane per (event, helicity): generated straight-line code, registers */
+#define ME_EXEC_TEAM 1  /* one team of 32 lanes per (event, helicity): generated step program,
+                           currents staged in LDS (the matrix-core colour-sum modes always use
+                           ME_EXEC_LANE for their diagram kernel) */
+
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 
 typedef struct me_ctx* me_handle;
@@ -142,9 +148,15 @@ int me_set_colorsum_mode(me_handle h, int mode);
  * the configuration beyond rounding order of the helicity sum. */
 int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves);
 
-/* Autotuner: times a fixed set of launch configurations on these events (writing
- * out_me2, synchronising the stream) and keeps the fastest; best[4] (host, may be
- * NULL) receives (persistent, waves_per_simd, hel_per_item, target_waves). */
+/* Executor of the FP64 colour-sum mode (ME_EXEC_LANE or ME_EXEC_TEAM); both give
+ * the same |M|^2 up to rounding order.  The team executor uses the helicity
+ * chunking of the grid path (target_waves of me_set_launch). */
+int me_set_executor(me_handle h, int executor);
+
+/* Autotuner: times a fixed set of launch configurations (and, in ME_CS_FP64 mode,
+ * both executors) on these events (writing out_me2, synchronising the stream)
+ * and keeps the fastest; best[5] (host, may be NULL) receives (persistent,
+ * waves_per_simd, hel_per_item, target_waves, executor). */
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
 

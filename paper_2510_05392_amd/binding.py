@@ -22,11 +22,13 @@ ME_ESTATE = -4
 ME_CS_FP64 = 0
 ME_CS_FP16X2 = 1
 ME_CS_BF16X2 = 2
+ME_EXEC_LANE = 0
+ME_EXEC_TEAM = 1
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
-           'me_compute_alphas', 'me_select',
+           'me_compute_alphas', 'me_select', 'me_set_executor',
            'me_finalize',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
@@ -78,6 +80,7 @@ def load(path=LIB_PATH):
     lib.me_compute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                      ctypes.POINTER(i64), ctypes.c_double, ctypes.POINTER(vp), vp]
     lib.me_compute_alphas.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.me_set_executor.argtypes = [vp, ctypes.c_int]
     lib.me_select.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.me_finalize.argtypes = [vp]
     fp, dbl = ctypes.POINTER(ctypes.c_float), ctypes.c_double
@@ -192,9 +195,13 @@ class MatrixElement:
         _check(load().me_set_launch(self._h, persistent, waves_per_simd, hel_per_item, target_waves))
 
     def me_autotune(self, momenta, nevt, alpha_s, out, stream=None):
-        best = (ctypes.c_int32 * 4)()
+        best = (ctypes.c_int32 * 5)()
         _check(load().me_autotune(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream), best))
-        return dict(zip(('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves'), list(best)))
+        return dict(zip(('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves', 'executor'),
+                        list(best)))
+
+    def me_set_executor(self, executor):
+        _check(load().me_set_executor(self._h, int(executor)))
 
     def me_set_colorsum_mode(self, mode):
         _check(load().me_set_colorsum_mode(self._h, int(mode)))

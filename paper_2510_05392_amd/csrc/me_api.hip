@@ -125,6 +125,7 @@ struct me_ctx {
   int waves_per_simd = 1;     // persistent grid size per SIMD
   int hel_per_item = 0;       // helicities per work item (0: all)
   int target_waves = 4096;    // grid path: waves to aim for (helicity chunks fill the rest)
+  int executor = ME_EXEC_LANE;  // FP64 path: one lane per (event, helicity), or a team of lanes
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
   // captured launch sequence of the last (momenta, out, nevt, alpha_s)
@@ -521,7 +522,7 @@ int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
   if (h->params.colorsum_mode == ME_CS_FP64) {
     size_t rows;
-    if (h->persistent) {
+    if (h->persistent && h->executor == ME_EXEC_LANE) {
       const int hpi = h->hel_per_item > 0 ? std::min(h->hel_per_item, nhel) : nhel;
       rows = (size_t)((nhel + hpi - 1) / hpi);
     } else {
@@ -543,6 +544,24 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
             hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
+  if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_TEAM) {
+    // one workgroup (one wavefront) per two events; helicity chunks fill the grid
+    const int64_t blocks = (nevt + 1) / 2;
+    int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (h->target_waves + blocks - 1) / blocks));
+    const int hpc = (nhel + nchunk - 1) / nchunk;
+    nchunk = (nhel + hpc - 1) / hpc;
+    me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
+                     h->d_partial, nullptr, s};
+    a.alphas = alphas;
+    hipError_t e = h->desc->team(a);
+    if (e != hipSuccess) return hip_fail(e, "team kernel launch");
+    const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
+                       h->d_partial, nchunk, nevt, scale, out_me2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    return ME_OK;
+  }
   if (h->params.colorsum_mode == ME_CS_FP64) {
     int nchunk, hpc;
     if (h->persistent) {
@@ -816,12 +835,14 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
     if (rc) return rc;
   }
-  struct Cand { int p, w, hpi, tw; };
-  std::vector<Cand> cands = {{0, 1, 0, 1024}, {0, 1, 0, 4096}, {0, 1, 0, 16384},
-                             {1, 1, 0, 0},    {1, 1, 8, 0},    {1, 2, 8, 0},
-                             {1, 1, 1, 0},    {1, 2, 1, 0}};
+  struct Cand { int p, w, hpi, tw, x; };
+  std::vector<Cand> cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0},
+                             {1, 1, 0, 0, 0},    {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},
+                             {1, 1, 1, 0, 0},    {1, 2, 1, 0, 0}};
+  if (h->params.colorsum_mode == ME_CS_FP64)
+    for (int tw : {1024, 8192, 65536}) cands.push_back({0, 1, 0, tw, 1});
   const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
-            save_tw = h->target_waves, save_graph = h->params.use_graph;
+            save_tw = h->target_waves, save_graph = h->params.use_graph, save_x = h->executor;
   h->params.use_graph = 0;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -833,6 +854,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     h->waves_per_simd = cands[i].w;
     h->hel_per_item = cands[i].hpi;
     h->target_waves = cands[i].tw > 0 ? cands[i].tw : save_tw;
+    h->executor = cands[i].x;
     rc = prepare(h, nevt);
     if (rc == ME_OK) rc = enqueue(h, momenta, nevt, alpha_s, out_me2, s);   // warm-up
     if (rc) break;
@@ -856,18 +878,30 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     h->waves_per_simd = save_w;
     h->hel_per_item = save_hpi;
     h->target_waves = save_tw;
+    h->executor = save_x;
     return rc ? rc : fail(ME_EHIP, "autotune found no configuration");
   }
   h->persistent = cands[best_i].p;
   h->waves_per_simd = cands[best_i].w;
   h->hel_per_item = cands[best_i].hpi;
   h->target_waves = cands[best_i].tw > 0 ? cands[best_i].tw : save_tw;
+  h->executor = cands[best_i].x;
   if (best) {
     best[0] = h->persistent;
     best[1] = h->waves_per_simd;
     best[2] = h->hel_per_item;
     best[3] = h->target_waves;
+    best[4] = h->executor;
   }
+  return ME_OK;
+}
+
+int me_set_executor(me_handle h, int executor) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM) return fail(ME_EINVAL, "unknown executor");
+  h->executor = executor;
+  drop_graph(h);
   return ME_OK;
 }
 

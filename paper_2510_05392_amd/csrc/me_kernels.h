@@ -14,6 +14,7 @@
 
 #include "me_device.h"
 #include "me_process.h"
+#include "me_team.h"
 #include "colour_mfma.h"
 
 namespace me {
@@ -185,8 +186,9 @@ hipError_t launch_colour(const ColourArgs& a) {
 
 template <class P>
 const ProcessDesc* describe() {
-  static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,      P::NHEL,    P::IDEN,
-                                P::CF_DEN, P::NDIAG, P::cf_int(), &launch<P>, &launch_colour<P>};
+  static const ProcessDesc d = {P::NAME,   P::NPAR,    P::NCOL,    P::NHEL,          P::IDEN,
+                                P::CF_DEN, P::NDIAG,   P::cf_int(), &launch<P>, &launch_colour<P>,
+                                &launch_team<typename P::Team>};
   return &d;
 }
 

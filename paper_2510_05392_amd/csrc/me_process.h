@@ -73,6 +73,7 @@ struct ProcessDesc {
   const int* cf_int;          // host, [ncol][ncol]
   Launcher launch;            // partial colour sums per helicity chunk, or dual amplitudes
   ColourLauncher colour;      // matrix-core colour sum of stored dual amplitudes
+  Launcher team;              // team executor: partial colour sums per helicity chunk
 };
 
 }  // namespace me

@@ -181,13 +181,12 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 }
 
 __global__ void cast_weights_kernel(const float* __restrict__ w, int out, int in, int kin, int outp,
-                                    __bf16* __restrict__ w16, __bf16* __restrict__ w16t) {
+                                    __bf16* __restrict__ w16) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (int64_t)outp * kin) return;
   const int o = (int)(k / kin), i = (int)(k % kin);
   const float x = (o < out && i < in) ? w[(int64_t)o * in + i] : 0.0f;
   w16[(int64_t)o * kin + i] = to_bf16(x);
-  w16t[(int64_t)i * outp + o] = to_bf16(x);
 }
 
 __global__ void copy_col_kernel(const float* __restrict__ z, int64_t ld, int64_t n, float* __restrict__ y) {
@@ -270,7 +269,7 @@ struct me_sur_ctx {
   int nfeat, width, depth, kin0;       // kin0: padded input width
   std::vector<int> in, out, kin, outp; // per linear layer: sizes and padded sizes
   std::vector<float*> w, b, gw, gb, mw, vw, mb, vb;
-  std::vector<__bf16*> w16, w16t;
+  std::vector<__bf16*> w16;         // BF16 weights [outp][kin], zero padded
   float* mean = nullptr;
   float* inv_std = nullptr;
   int step = 0;
@@ -307,7 +306,7 @@ void sfree(me_sur_ctx* c) {
   };
   for (auto v : {&c->w, &c->b, &c->gw, &c->gb, &c->mw, &c->vw, &c->mb, &c->vb, &c->z})
     for (float* p : *v) f(p);
-  for (auto v : {&c->w16, &c->w16t, &c->h})
+  for (auto v : {&c->w16, &c->h})
     for (__bf16* p : *v) f(p);
   f(c->mean);
   f(c->inv_std);
@@ -364,7 +363,7 @@ int refresh_bf16(me_sur_ctx* c, hipStream_t s) {
   for (size_t l = 0; l < c->in.size(); ++l) {
     const int64_t n = (int64_t)c->outp[l] * c->kin[l];
     hipLaunchKernelGGL(cast_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c->w[l],
-                       c->out[l], c->in[l], c->kin[l], c->outp[l], c->w16[l], c->w16t[l]);
+                       c->out[l], c->in[l], c->kin[l], c->outp[l], c->w16[l]);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ME_OK : shipfail(e, "weight cast");
@@ -421,7 +420,7 @@ int me_sur_init(const me_sur_params* p, me_surrogate* out) {
       hw[k] = (float)((2.0 * u - 1.0) * bound);
     }
     float *w, *b, *gw, *gb, *mw, *vw, *mb, *vb;
-    __bf16 *w16, *w16t;
+    __bf16* w16;
     e = dalloc(&w, nw);
     if (e == hipSuccess) e = dalloc(&b, c->out[l]);
     if (e == hipSuccess) e = dalloc(&gw, nw);
@@ -431,7 +430,6 @@ int me_sur_init(const me_sur_params* p, me_surrogate* out) {
     if (e == hipSuccess) e = dalloc(&mb, c->out[l]);
     if (e == hipSuccess) e = dalloc(&vb, c->out[l]);
     if (e == hipSuccess) e = dalloc(&w16, (size_t)c->outp[l] * c->kin[l]);
-    if (e == hipSuccess) e = dalloc(&w16t, (size_t)c->outp[l] * c->kin[l]);
     if (e != hipSuccess) break;
     c->w.push_back(w);
     c->b.push_back(b);
@@ -442,7 +440,6 @@ int me_sur_init(const me_sur_params* p, me_surrogate* out) {
     c->mb.push_back(mb);
     c->vb.push_back(vb);
     c->w16.push_back(w16);
-    c->w16t.push_back(w16t);
     e = hipMemcpy(w, hw.data(), nw * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b, hb.data(), hb.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(mw, 0, nw * 4);
@@ -609,7 +606,8 @@ int me_sur_grads(me_surrogate s, const uint16_t* feat, const float* target, int6
     if (l == 0) break;
     // dH[b][i] = sum_o dZ[b][o] W[o][i], then dZ_{l-1} = dH * silu'(Z_{l-1})
     const int64_t ldn = s->outp[l - 1];
-    e = gemm(s->dzh, ld, 1, s->w16t[l], s->outp[l], 1, nb, s->in[l], s->out[l], nullptr, s->dh, ldn, nullptr,
+    // B[k = o][j = i] = W[o][i] = w16[o * kin + i]
+    e = gemm(s->dzh, ld, 1, s->w16[l], s->kin[l], 1, nb, s->in[l], s->out[l], nullptr, s->dh, ldn, nullptr,
              0, false, st);
     if (e != hipSuccess) return shipfail(e, "input-gradient gemm");
     const int64_t tot = nb * ldn;

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import math
 
+from . import team as team_gen
 from .colour import colour_matrix
 from .topology import Plan
 
@@ -259,12 +260,15 @@ def generate(name):
     iden = 4 * 64 * math.factorial(npar - 4)
     em = Emitter(name, plan)
     body = em.amplitudes()
+    team_src, _ = team_gen.emit(name, plan)
     out = []
     out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
                f"{len(plan.pieces)} colour-structure pieces,")
     out.append(f"// {len(plan.order)} currents, {ncol} colour flows.  Do not edit.")
     out.append("#pragma once")
     out.append('#include "me_device.h"')
+    out.append('#include "me_team.h"')
+    out.append(team_src.rstrip('\n'))
     out.append("namespace me {")
     flat = ', '.join(str(cf[i][j]) for i in range(ncol) for j in range(ncol))
     out.append(f"static const int CF_INT_{name}[{ncol * ncol}] = {{{flat}}};")
@@ -277,6 +281,7 @@ def generate(name):
     out.append(f"  static constexpr int CF_DEN = {den};")
     out.append(f"  static constexpr int NDIAG = {plan.ndiagrams};")
     out.append(f"  static const int* cf_int() {{ return CF_INT_{name}; }}")
+    out.append(f"  using Team = {name}_team;")
     out.append("  static __device__ __forceinline__ void amplitudes(const double (*p)[4], const int* lam, "
                "double g, double mt, cx* jamp) {")
     out.extend('  ' + l for l in body)

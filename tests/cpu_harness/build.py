@@ -20,7 +20,8 @@ def build(name, opt='-O1'):
         with open(hdr, 'w') as f:
             f.write(src)
     lib = os.path.join(OUT, f'harness_{name}.so')
-    deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(HERE, 'harness.cpp')]
+    deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(CSRC, 'me_team.h'),
+            os.path.join(HERE, 'harness.cpp')]
     if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
         cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE),
                '-I', CSRC, f'-DPROCESS_HEADER="{hdr}"', f'-DPROCNAME={name}',
@@ -49,4 +50,16 @@ class Harness:
                               jam.ctypes.data_as(dp) if want_jamps else None)
         if want_jamps:
             return meh, jam[..., 0] + 1j * jam[..., 1]
+        return meh
+
+    def team_eval(self, mom, g, mt, hels):
+        """Per-helicity colour sums from the serial emulation of the team executor."""
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        meh = np.zeros((len(hels), nevt))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.harness_team_eval(mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
+                                   ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
         return meh

@@ -68,8 +68,13 @@ def test_surrogate_forward_and_gradients_vs_cpu(binding):
     loss = torch.zeros(1, dtype=torch.float32, device='cuda')
     sur.me_sur_grads(feat, tg, nb, loss)
     torch.cuda.synchronize()
-    # CPU FP64 reference on the same BF16-rounded inputs and weights
-    x = _bf16((raw - mean) / std)
+    # the GPU features (BF16) against the FP64 ones, except the constant (g1, g2)
+    # column whose normalised value is rounding noise amplified by 1 / std
+    xg = feat.view(torch.bfloat16).float().cpu().numpy().astype(np.float64)[:, :nfeat]
+    xc = (raw - mean) / std
+    assert np.all(np.abs(xg[:, 1:] - xc[:, 1:]) <= 2.0 ** -7 * np.abs(xc[:, 1:]) + 1e-3)
+    # CPU FP64 reference of the network on the same BF16 inputs and weights
+    x = xg
     pb = [(_bf16(w), b) for w, b in params]
     yref, _ = S.forward(pb, x)
     ygpu = y.cpu().numpy()

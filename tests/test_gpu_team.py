@@ -1,0 +1,92 @@
+"""Team executor (one team of lanes per (event, helicity), currents in LDS)
+vs the oracle and vs the one-lane-per-(event, helicity) executor.
+
+Same FP64 arithmetic per routine; only the rounding order of the colour-flow
+accumulation and of the colour sum differ, so the two executors agree to
+~1e-13 relative and both meet the 1e-12 bar against the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_05392_amd import rambo
+from test_gpu_parity import AS, NPAR, _golden, _say, assert_parity
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2510_05392_amd import binding as b
+    b.load()
+    return b
+
+
+def _run(binding, name, mom, executor, target_waves=4096, alphas=None):
+    m = binding.MatrixElement(name)
+    m.me_set_launch(0, 1, 0, target_waves)
+    m.me_set_executor(executor)
+    d = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
+    out = torch.empty(len(mom), dtype=torch.float64, device='cuda')
+    if alphas is None:
+        m.me_compute(d, len(mom), AS, out)
+    else:
+        m.me_compute_alphas(d, len(mom), torch.from_numpy(alphas).cuda(), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize('name,nevt,seed', [('gg_ttx', 257, 1001), ('gg_ttxg', 133, 22), ('gg_ttxgg', 67, 23),
+                                            ('gg_ttxg', 1, 5), ('gg_ttxgg', 3, 6)])
+def test_team_vs_oracle_and_lane(binding, name, nevt, seed):
+    _say(f'case team {name} nevt={nevt}')
+    npar = NPAR[name]
+    mom = rambo.generate(npar, nevt, seed)
+    team = _run(binding, name, mom, binding.ME_EXEC_TEAM)
+    lane = _run(binding, name, mom, binding.ME_EXEC_LANE)
+    rel = np.abs(team / lane - 1)
+    _say(f'  team vs lane max rel {rel.max():.2e}')
+    assert rel.max() < 1e-13
+    assert_parity(team, mom, npar)
+
+
+def test_team_ggttggg_golden(binding):
+    _say('case team ggttggg golden 197 events')
+    g = _golden('gg_ttxggg_seed1003_first197.npz')
+    mom = rambo.generate(7, 197, 1003)
+    team = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_TEAM)
+    assert_parity(team, mom, 7, me64=g['me'], me_ext=g['me_ext'])
+
+
+@pytest.mark.parametrize('tw', [64, 1 << 20])
+def test_team_helicity_chunking(binding, tw):
+    # one chunk with every helicity, or one helicity per chunk: same result up to rounding order
+    _say(f'case team chunking target_waves={tw}')
+    mom = rambo.generate(6, 100, 24)
+    a = _run(binding, 'gg_ttxgg', mom, binding.ME_EXEC_TEAM, target_waves=tw)
+    b = _run(binding, 'gg_ttxgg', mom, binding.ME_EXEC_LANE)
+    assert np.max(np.abs(a / b - 1)) < 1e-13
+
+
+def test_team_deterministic_and_alphas(binding):
+    _say('case team determinism and running alpha_s')
+    mom = rambo.generate(6, 130, 25)
+    a = _run(binding, 'gg_ttxgg', mom, binding.ME_EXEC_TEAM)
+    b = _run(binding, 'gg_ttxgg', mom, binding.ME_EXEC_TEAM)
+    assert np.array_equal(a, b)
+    alphas = np.random.default_rng(2).uniform(0.08, 0.2, 130)
+    c = _run(binding, 'gg_ttxgg', mom, binding.ME_EXEC_TEAM, alphas=alphas)
+    assert np.allclose(c, a * (alphas / AS) ** 4, rtol=1e-12)
+
+
+def test_team_full_size_ggttggg_sampled(binding):
+    # the benchmark workload in the team executor, sampled events against the oracle
+    _say('case team full size ggttggg 262144')
+    mom = rambo.generate(7, 262144, 1003)
+    team = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_TEAM)
+    assert np.all(np.isfinite(team)) and np.all(team > 0)
+    g = _golden('gg_ttxggg_seed1003_n262144_sampled.npz')
+    idx = g['index']
+    assert_parity(team[idx], mom[idx], 7, me64=g['me'], me_ext=g['me_ext'])
