@@ -23,9 +23,9 @@ OBJ = os.path.join(ROOT, '_build', 'obj')
 INCLUDE = os.path.join(ROOT, 'include')
 LIB = os.path.join(HERE, 'libmegpu.so')
 
-PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg']
+PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg', 'gg_ttxgggg']
 # headers the generated process units include
-PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h']
+PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h', 'me_team.h']
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
@@ -67,18 +67,25 @@ def generate_sources(procs, build_dir):
     reg.append(f'static const int kNumProcesses = {len(procs)};')
     reg.append('// one persistent kernel over all of them (multi-process batches)')
     reg.append('hipError_t launch_batch_all(const BatchArgs& a, int waves, hipStream_t stream);')
+    # the batch kernel covers the leading processes that have one-lane code
+    lane = []
+    for n in procs:
+        if codegen.PROCESS_NPAR[n] > codegen.LANE_MAX_NPAR:
+            break
+        lane.append(n)
+    reg.append(f'static const int kNumBatchProcesses = {len(lane)};')
     batch = ['// Multi-process batch kernel over the processes of this library (generated).']
-    batch += [f'#include "{n}.inc"' for n in procs]
+    batch += [f'#include "{n}.inc"' for n in lane]
     batch += ['#include "me_kernels.h"', 'namespace me {',
               'hipError_t launch_batch_all(const BatchArgs& a, int waves, hipStream_t stream) {',
-              '  return launch_batch<' + ', '.join(f'me::{n}' for n in procs) + '>(a, waves, stream);',
+              '  return launch_batch<' + ', '.join(f'me::{n}' for n in lane) + '>(a, waves, stream);',
               '}', '}']
     batchfile = os.path.join(build_dir, 'batch.hip')
     _write_if_changed(batchfile, '\n'.join(batch) + '\n')
     regfile = os.path.join(build_dir, 'registry.inc')
     _write_if_changed(regfile, '\n'.join(reg) + '\n')
     units.insert(0, (batchfile, os.path.join(build_dir, 'batch.o'),
-                     [os.path.join(GEN, f'{n}.inc') for n in procs] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
+                     [os.path.join(GEN, f'{n}.inc') for n in lane] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
                   [regfile, os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_process.h'),
                    os.path.join(CSRC, 'me_error.h')]))

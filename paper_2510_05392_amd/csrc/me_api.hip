@@ -334,11 +334,14 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   if (p) prm = *p;
   if (!(prm.mt > 0.0)) return fail(ME_EINVAL, "mt must be positive");
   if (!valid_mode(prm.colorsum_mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
+  if (!desc->launch && prm.colorsum_mode != ME_CS_FP64)
+    return fail(ME_EINVAL, std::string(process) + " has only the team executor (ME_CS_FP64)");
   me_ctx* c = new (std::nothrow) me_ctx;
   if (!c) return fail(ME_ENOMEM, "host allocation failed");
   c->desc = desc;
   c->proc_index = proc_index;
   c->params = prm;
+  if (!desc->launch) c->executor = ME_EXEC_TEAM;
   c->good.resize(desc->nhel);
   for (int k = 0; k < desc->nhel; ++k) c->good[k] = k;
   hipError_t e = hipMalloc(&c->d_hels, desc->nhel * sizeof(int));
@@ -450,7 +453,7 @@ int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double al
   // one helicity per chunk: the per-chunk partial sums are the per-helicity sums
   me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out,
                    nullptr, s};
-  hipError_t e = h->desc->launch(a);
+  hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
   if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
   const int64_t n = nevt * nh;
   hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, 1,
@@ -467,6 +470,7 @@ int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   if (nevt < 0 || nh < 0 || nh > h->desc->nhel) return fail(ME_EINVAL, "bad sizes");
   if (nevt == 0 || nh == 0) return ME_OK;
   if (!momenta || !hels || !out) return fail(ME_EINVAL, "null pointer");
+  if (!h->desc->launch) return fail(ME_EINVAL, "dual amplitudes need the one-lane executor of the process");
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
@@ -681,6 +685,8 @@ int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* mo
       if (hs[j] == hs[i]) return fail(ME_EINVAL, "a handle may appear only once in a batch");
     if (nevts[i] < 0 || nevts[i] > (int64_t)64 * 0x7fffff) return fail(ME_EINVAL, "bad nevt");
     if (nevts[i] > 0 && (!momenta[i] || !outs[i])) return fail(ME_EINVAL, "null pointer");
+    if (hs[i]->proc_index >= me::kNumBatchProcesses)
+      return fail(ME_EINVAL, std::string(hs[i]->desc->name) + " is not in the batch kernel");
   }
   // segments with events, heaviest process first so that the tail of the
   // persistent grid runs the cheapest items
@@ -764,6 +770,7 @@ int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, 
     return fail(ME_EINVAL, "null pointer");
   if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
   if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  if (!h->desc->launch) return fail(ME_EINVAL, "selection needs the one-lane executor of the process");
   hipStream_t s = (hipStream_t)stream;
   if (!h->filtered) {
     rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
@@ -836,9 +843,10 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     if (rc) return rc;
   }
   struct Cand { int p, w, hpi, tw, x; };
-  std::vector<Cand> cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0},
-                             {1, 1, 0, 0, 0},    {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},
-                             {1, 1, 1, 0, 0},    {1, 2, 1, 0, 0}};
+  std::vector<Cand> cands;
+  if (h->desc->launch)
+    cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0}, {1, 1, 0, 0, 0},
+             {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},    {1, 1, 1, 0, 0},     {1, 2, 1, 0, 0}};
   if (h->params.colorsum_mode == ME_CS_FP64)
     for (int tw : {1024, 8192, 65536}) cands.push_back({0, 1, 0, tw, 1});
   const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
@@ -900,6 +908,8 @@ int me_set_executor(me_handle h, int executor) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM) return fail(ME_EINVAL, "unknown executor");
+  if (executor == ME_EXEC_LANE && !h->desc->launch)
+    return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor");
   h->executor = executor;
   drop_graph(h);
   return ME_OK;
@@ -909,6 +919,8 @@ int me_set_colorsum_mode(me_handle h, int mode) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!valid_mode(mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
+  if (!h->desc->launch && mode != ME_CS_FP64)
+    return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor (ME_CS_FP64)");
   rc = build_tables(h, mode);
   if (rc) return rc;
   h->params.colorsum_mode = mode;

@@ -184,10 +184,17 @@ hipError_t launch_colour(const ColourArgs& a) {
   return hipGetLastError();
 }
 
+// Processes without the one-lane code (P::LANE false) have only the team executor.
 template <class P>
 const ProcessDesc* describe() {
-  static const ProcessDesc d = {P::NAME,   P::NPAR,    P::NCOL,    P::NHEL,          P::IDEN,
-                                P::CF_DEN, P::NDIAG,   P::cf_int(), &launch<P>, &launch_colour<P>,
+  Launcher lane = nullptr;
+  ColourLauncher colour = nullptr;
+  if constexpr (P::LANE) {
+    lane = &launch<P>;
+    colour = &launch_colour<P>;
+  }
+  static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,     P::NHEL, P::IDEN,
+                                P::CF_DEN, P::NDIAG, P::cf_int(), lane,    colour,
                                 &launch_team<typename P::Team>};
   return &d;
 }

@@ -11,13 +11,18 @@
 // on diagram groups); this executor exchanges them through LDS.
 //
 // Frame of a team (doubles, offsets generated per process):
-//   [0, MOFF)          object slots, 8 doubles (4 complex) each; at the end
-//                      of a frame the colour flows (2 doubles each) reuse it
-//   [MOFF, POFF)       table of signed momentum sums, 4 doubles each
+//   [0, JOFF)          object slots (4 complex each), TEAM_SLOT doubles apart:
+//                      an odd number of 8-byte words between slots spreads the
+//                      lanes' accesses over the LDS banks
+//   [JOFF, MOFF)       the colour flows J_i (complex), accumulated in place
+//   [MOFF, POFF)       table of signed momentum sums, TEAM_MSTRIDE doubles apart
 //   [POFF, AOFF)       the event's external momenta p_q, 4 doubles each
-//   [AOFF, FRAME)      amplitude buffer, one complex per lane of an amplitude step
-// Operand tables are uint16 [operand][T] per step; a momentum operand is a
-// table index with bit 15 meaning "negated".
+//   [AOFF, FRAME)      amplitude buffer: per lane of an amplitude step its
+//                      amplitude times +1, -1, +i, -i (4 complex)
+// Operands: one row of 8 uint16 per lane per step (one 16-byte load); a
+// momentum operand is an index into the momentum table with bit 15 meaning
+// "negated".  After an amplitude step every lane adds the amplitudes of its
+// flow records to the flows it owns in that step (no two lanes share a flow).
 //
 // Every step is a function of (frame, lane), so the same code runs on the
 // GPU (lanes in SIMT, __syncthreads between steps) and in a serial CPU
@@ -31,14 +36,17 @@ namespace me {
 
 enum TeamClass { TC_V3 = 0, TC_V4, TC_ROWV, TC_VCOL, TC_ROWP, TC_PCOL, TC_LINE, TC_AMP, TC_FLOWS };
 
+constexpr int TEAM_SLOT = 9;      // doubles between object slots
+constexpr int TEAM_MSTRIDE = 5;   // doubles between momentum-table entries
+
 __device__ __forceinline__ void team_load(const double* F, int slot, cx* v) {
-  const double* s = F + slot * 8;
+  const double* s = F + slot * TEAM_SLOT;
 #pragma unroll
   for (int u = 0; u < 4; ++u) v[u] = cx{s[2 * u], s[2 * u + 1]};
 }
 
 __device__ __forceinline__ void team_store(double* F, int slot, const cx* v) {
-  double* s = F + slot * 8;
+  double* s = F + slot * TEAM_SLOT;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     s[2 * u] = v[u].r;
@@ -47,7 +55,7 @@ __device__ __forceinline__ void team_store(double* F, int slot, const cx* v) {
 }
 
 __device__ __forceinline__ void team_mom(const double* F, int moff, int code, double* p) {
-  const double* s = F + moff + (code & 0x7fff) * 4;
+  const double* s = F + moff + (code & 0x7fff) * TEAM_MSTRIDE;
   const bool neg = (code & 0x8000) != 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) p[u] = neg ? -s[u] : s[u];
@@ -69,7 +77,7 @@ __device__ __forceinline__ void team_momenta(double* F, int moff, int poff, cons
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) F[moff + i * 4 + u] = s[u];
+    for (int u = 0; u < 4; ++u) F[moff + i * TEAM_MSTRIDE + u] = s[u];
   }
 }
 
@@ -90,33 +98,33 @@ __device__ __forceinline__ void team_external(double* F, int poff, int slot, int
   team_store(F, slot, w);
 }
 
-// One op of class C for lane t; tab points at the step's operand table.
+// One op of class C for one lane, operands o[0..7] of its row.
 template <int C>
-__device__ __forceinline__ void team_op(double* F, int moff, int aoff, const uint16_t* tab, int t, int T,
-                                        double g, double mt) {
+__device__ __forceinline__ void team_op(double* F, int moff, int aoff, const unsigned* o, int t, double g,
+                                        double mt) {
   cx a[4], b[4], out[4];
   if (C == TC_V3) {
     double pa[4], pb[4], pf[4];
-    team_load(F, tab[t], a);
-    team_mom(F, moff, tab[T + t], pa);
-    team_load(F, tab[2 * T + t], b);
-    team_mom(F, moff, tab[3 * T + t], pb);
-    team_mom(F, moff, tab[4 * T + t], pf);
+    team_load(F, o[0], a);
+    team_mom(F, moff, o[1], pa);
+    team_load(F, o[2], b);
+    team_mom(F, moff, o[3], pb);
+    team_mom(F, moff, o[4], pf);
     v3_open(a, pa, b, pb, -g / msq(pf), out);
-    team_store(F, tab[5 * T + t], out);
+    team_store(F, o[5], out);
   } else if (C == TC_V4) {
     // out = f (P0 (X0.Y0) - P1 (X1.Y1)), f = -g^2 / P^2
     cx x[4];
-    team_load(F, tab[T + t], x);
-    team_load(F, tab[2 * T + t], b);
+    team_load(F, o[1], x);
+    team_load(F, o[2], b);
     const cx d0 = vdot(x, b);
-    team_load(F, tab[4 * T + t], x);
-    team_load(F, tab[5 * T + t], b);
+    team_load(F, o[4], x);
+    team_load(F, o[5], b);
     const cx d1 = vdot(x, b);
-    team_load(F, tab[t], a);
-    team_load(F, tab[3 * T + t], b);
+    team_load(F, o[0], a);
+    team_load(F, o[3], b);
     double pf[4];
-    team_mom(F, moff, tab[6 * T + t], pf);
+    team_mom(F, moff, o[6], pf);
     const double f = -g * g / msq(pf);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -124,114 +132,109 @@ __device__ __forceinline__ void team_op(double* F, int moff, int aoff, const uin
       acc = acc - b[u] * d1;
       out[u] = f * acc;
     }
-    team_store(F, tab[7 * T + t], out);
+    team_store(F, o[7], out);
   } else if (C == TC_ROWV) {
-    team_load(F, tab[t], a);
-    team_load(F, tab[T + t], b);
+    team_load(F, o[0], a);
+    team_load(F, o[1], b);
     row_vertex(a, b, g, out);
-    team_store(F, tab[2 * T + t], out);
+    team_store(F, o[2], out);
   } else if (C == TC_VCOL) {
-    team_load(F, tab[t], a);
-    team_load(F, tab[T + t], b);
+    team_load(F, o[0], a);
+    team_load(F, o[1], b);
     vertex_col(a, b, g, out);
-    team_store(F, tab[2 * T + t], out);
+    team_store(F, o[2], out);
   } else if (C == TC_ROWP) {
     double q[4];
-    team_load(F, tab[t], a);
-    team_mom(F, moff, tab[T + t], q);
+    team_load(F, o[0], a);
+    team_mom(F, moff, o[1], q);
     row_prop(a, q, mt, out);
-    team_store(F, tab[2 * T + t], out);
+    team_store(F, o[2], out);
   } else if (C == TC_PCOL) {
     double q[4];
-    team_load(F, tab[t], a);
-    team_mom(F, moff, tab[T + t], q);
+    team_load(F, o[0], a);
+    team_mom(F, moff, o[1], q);
     prop_col(q, mt, a, out);
-    team_store(F, tab[2 * T + t], out);
+    team_store(F, o[2], out);
   } else if (C == TC_LINE) {
-    team_load(F, tab[t], a);
-    team_load(F, tab[T + t], b);
+    team_load(F, o[0], a);
+    team_load(F, o[1], b);
     line_current(a, b, g, out);
-    team_store(F, tab[2 * T + t], out);
+    team_store(F, o[2], out);
   } else if (C == TC_AMP) {
-    team_load(F, tab[t], a);
-    team_load(F, tab[T + t], b);
-    const cx v = tab[2 * T + t] ? vdot(a, b) : sdot(a, b);
-    F[aoff + 2 * t] = v.r;
-    F[aoff + 2 * t + 1] = v.i;
+    // the amplitude times +1, -1, +i and -i, so that a flow record only adds
+    team_load(F, o[0], a);
+    team_load(F, o[1], b);
+    const cx v = o[2] ? vdot(a, b) : sdot(a, b);
+    double* s = F + aoff + 8 * t;
+    s[0] = v.r;
+    s[1] = v.i;
+    s[2] = -v.r;
+    s[3] = -v.i;
+    s[4] = -v.i;
+    s[5] = v.r;
+    s[6] = v.i;
+    s[7] = -v.r;
   }
 }
 
-__device__ __forceinline__ void team_dispatch(int cls, double* F, int moff, int aoff, const uint16_t* tab,
-                                              int t, int T, double g, double mt) {
+__device__ __forceinline__ void team_dispatch(int cls, double* F, int moff, int aoff, const unsigned* o, int t,
+                                              double g, double mt) {
   switch (cls) {
-    case TC_V3: team_op<TC_V3>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_V4: team_op<TC_V4>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_ROWV: team_op<TC_ROWV>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_VCOL: team_op<TC_VCOL>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_ROWP: team_op<TC_ROWP>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_PCOL: team_op<TC_PCOL>(F, moff, aoff, tab, t, T, g, mt); break;
-    case TC_LINE: team_op<TC_LINE>(F, moff, aoff, tab, t, T, g, mt); break;
-    default: team_op<TC_AMP>(F, moff, aoff, tab, t, T, g, mt); break;
+    case TC_V3: team_op<TC_V3>(F, moff, aoff, o, t, g, mt); break;
+    case TC_V4: team_op<TC_V4>(F, moff, aoff, o, t, g, mt); break;
+    case TC_ROWV: team_op<TC_ROWV>(F, moff, aoff, o, t, g, mt); break;
+    case TC_VCOL: team_op<TC_VCOL>(F, moff, aoff, o, t, g, mt); break;
+    case TC_ROWP: team_op<TC_ROWP>(F, moff, aoff, o, t, g, mt); break;
+    case TC_PCOL: team_op<TC_PCOL>(F, moff, aoff, o, t, g, mt); break;
+    case TC_LINE: team_op<TC_LINE>(F, moff, aoff, o, t, g, mt); break;
+    default: team_op<TC_AMP>(F, moff, aoff, o, t, g, mt); break;
   }
 }
 
-// Colour-flow update of one lane: m entries (amplitude lane | coefficient << 6)
-// of the amplitude buffer added to the flow j, coefficient 0: +1, 1: -1, 2: +i, 3: -i.
-__device__ __forceinline__ void team_flows(const double* F, int aoff, const uint16_t* tab, int t, int T,
-                                           int m, cx& j) {
-  for (int i = 0; i < m; ++i) {
-    const unsigned w = tab[i * T + t];
-    if (w == 0xffffu) continue;
-    const int k = w & 63;
-    cx v{F[aoff + 2 * k], F[aoff + 2 * k + 1]};
-    if (w & 128) v = times_i(v);
-    j = (w & 64) ? j - v : j + v;
-  }
+// The 8 operands of lane t's row r of the operand table.
+__device__ __forceinline__ void team_row(const uint16_t* ops, uint32_t r, unsigned* o) {
+  const uint4 w = reinterpret_cast<const uint4*>(ops)[r];
+  o[0] = w.x & 0xffff;
+  o[1] = w.x >> 16;
+  o[2] = w.y & 0xffff;
+  o[3] = w.y >> 16;
+  o[4] = w.z & 0xffff;
+  o[5] = w.z >> 16;
+  o[6] = w.w & 0xffff;
+  o[7] = w.w >> 16;
 }
 
-// Program of a process: step headers in PROG (uint32): word 0 = class | n << 8,
-// word 1 = operand-table offset; a TC_FLOWS step is followed by NLOC pairs
-// (table offset, entries) for the local flows 0..NLOC-1.
-//
-// Runs one step for one lane: ops on lanes t < n; flow steps on every lane.
-// Returns the number of header words consumed.
-template <class X>
-__device__ __forceinline__ int team_step(const uint32_t* prog, double* F, int t, double g, double mt,
-                                         cx* jl) {
-  const uint32_t h = prog[0];
-  const int cls = h & 0xff;
-  const int n = h >> 8;
-  const uint16_t* tab = X::table();
-  if (cls == TC_FLOWS) {
-#pragma unroll
-    for (int L = 0; L < X::NLOC; ++L) {
-      const uint32_t off = prog[1 + 2 * L], m = prog[2 + 2 * L];
-      if (m) team_flows(F, X::AOFF, tab + off, t, X::T, (int)m, jl[L]);
-    }
-    return 1 + 2 * X::NLOC;
+// One flow record of a lane: entry 4 * k + c of the amplitude buffer (the
+// amplitude of lane k times +1, -1, +i, -i for c = 0..3) is added to the
+// running sum; on the last record of a flow the sum is added to that flow in LDS.
+__device__ __forceinline__ void team_flow_record(double* F, int aoff, int joff, uint32_t rec, cx& run) {
+  if (rec == 0xffffffffu) return;
+  const int k = rec & 255;
+  run = run + cx{F[aoff + 2 * k], F[aoff + 2 * k + 1]};
+  if (rec & (1u << 20)) {
+    double* j = F + joff + 2 * ((rec >> 8) & 0xfff);
+    j[0] += run.r;
+    j[1] += run.i;
+    run = cx{0.0, 0.0};
   }
-  if (t < n) team_dispatch(cls, F, X::MOFF, X::AOFF, tab + prog[1], t, X::T, g, mt);
-  return 2;
 }
 
 // Per-lane part of the colour sum: sum over the lane's rows i of
 // Re(conj(J_i) sum_j CF_int[i][j] J_j), with the flows already in F[0, 2 NCOL).
 template <class X>
-__device__ __forceinline__ double team_colour(const double* F, int t, const cx* jl) {
-  const int16_t* cf = X::colour_matrix();
+__device__ __forceinline__ double team_colour(const double* F, int t) {
+  const int32_t* cf = X::colour_matrix();
+  const double* J = F + X::JOFF;
   double part = 0.0;
-#pragma unroll
-  for (int L = 0; L < X::NLOC; ++L) {
-    const int i = L * X::T + t;
-    if (i < X::NCOL) {
-      double sr = 0.0, si = 0.0;
-      for (int j = 0; j < X::NCOL; ++j) {
-        const double c = (double)cf[j * X::NCOL + i];
-        sr += c * F[2 * j];
-        si += c * F[2 * j + 1];
-      }
-      part += jl[L].r * sr + jl[L].i * si;
+  for (int i = t; i < X::NCOL; i += X::T) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < X::NCOL; ++j) {
+      const double c = (double)cf[j * X::NCOL + i];
+      sr += c * J[2 * j];
+      si += c * J[2 * j + 1];
     }
+    part += J[2 * i] * sr + J[2 * i + 1] * si;
   }
   return part;
 }
@@ -269,28 +272,51 @@ __global__ void __launch_bounds__(64) team_kernel(const double* __restrict__ mom
   const int k0 = blockIdx.y * hel_per_chunk;
   const int k1 = min(nhel, k0 + hel_per_chunk);
   const uint32_t* prog = X::program();
+  const uint16_t* ops = X::ops();
+  const uint32_t* flows = X::flows();
   double acc = 0.0;
   for (int k = k0; k < k1; ++k) {
+    for (int i = t; i < 2 * X::NCOL; i += X::T) F[X::JOFF + i] = 0.0;
     X::externals(F, t, hels[k], mt);
     __syncthreads();
-    cx jl[X::NLOC];
-#pragma unroll
-    for (int L = 0; L < X::NLOC; ++L) jl[L] = cx{0.0, 0.0};
+    unsigned o[8];
+    team_row(ops, prog[1] * 1u + t, o);
     for (int w = 0; w < X::NPROGW;) {
-      w += team_step<X>(prog + w, F, t, gl, mt, jl);
-      __syncthreads();
-    }
-    // colour flows to LDS (the object slots are free now), then the quadratic form
+      const uint32_t h = prog[w];
+      const int cls = h & 0xff, n = h >> 8;
+      const int adv = cls == TC_AMP ? 4 : 2;
+      // operands of the next step are fetched while this one runs
+      unsigned nx[8];
+      if (w + adv < X::NPROGW) team_row(ops, prog[w + adv + 1] + t, nx);
+      if (cls == TC_AMP) {
+        // flow records in chunks of RCH, each chunk's loads issued together
+        constexpr int RCH = X::RMAX < 16 ? X::RMAX : 16;
+        const uint32_t foff = prog[w + 2], nr = prog[w + 3];
+        uint32_t rec[RCH];
 #pragma unroll
-    for (int L = 0; L < X::NLOC; ++L) {
-      const int i = L * X::T + t;
-      if (i < X::NCOL) {
-        F[2 * i] = jl[L].r;
-        F[2 * i + 1] = jl[L].i;
+        for (int q = 0; q < RCH; ++q) rec[q] = q < (int)nr ? flows[foff + (uint32_t)q * X::T + t] : ~0u;
+        if (t < n) team_op<TC_AMP>(F, X::MOFF, X::AOFF, o, t, gl, mt);
+        __syncthreads();
+        cx run{0.0, 0.0};
+        for (uint32_t q0 = 0; q0 < nr; q0 += RCH) {
+          if (q0 > 0) {
+#pragma unroll
+            for (int q = 0; q < RCH; ++q)
+              rec[q] = q0 + q < nr ? flows[foff + (q0 + q) * X::T + t] : ~0u;
+          }
+#pragma unroll
+          for (int q = 0; q < RCH; ++q)
+            if (q0 + q < nr) team_flow_record(F, X::AOFF, X::JOFF, rec[q], run);
+        }
+      } else if (t < n) {
+        team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, gl, mt);
       }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o[q] = nx[q];
+      w += adv;
     }
-    __syncthreads();
-    double part = team_colour<X>(F, t, jl);
+    double part = team_colour<X>(F, t);
 #pragma unroll
     for (int off = X::T / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
     acc += part;

@@ -251,6 +251,12 @@ def colour_sum_code(cf, ncol):
     return lines
 
 
+# Largest process that also gets the one-lane-per-(event, helicity) code; beyond
+# it the straight-line function would be too large to compile in reasonable
+# time, and only the team program is generated.
+LANE_MAX_NPAR = 7
+
+
 def generate(name):
     npar = PROCESS_NPAR[name]
     n = npar - 2
@@ -258,8 +264,8 @@ def generate(name):
     cf, den = colour_matrix(n)
     ncol = len(plan.basis)
     iden = 4 * 64 * math.factorial(npar - 4)
-    em = Emitter(name, plan)
-    body = em.amplitudes()
+    lane = npar <= LANE_MAX_NPAR
+    body = Emitter(name, plan).amplitudes() if lane else []
     team_src, _ = team_gen.emit(name, plan)
     out = []
     out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
@@ -282,13 +288,15 @@ def generate(name):
     out.append(f"  static constexpr int NDIAG = {plan.ndiagrams};")
     out.append(f"  static const int* cf_int() {{ return CF_INT_{name}; }}")
     out.append(f"  using Team = {name}_team;")
-    out.append("  static __device__ __forceinline__ void amplitudes(const double (*p)[4], const int* lam, "
-               "double g, double mt, cx* jamp) {")
-    out.extend('  ' + l for l in body)
-    out.append("  }")
-    out.append("  static __device__ __forceinline__ double colour_sum(const cx* jamp) {")
-    out.extend('  ' + l for l in colour_sum_code(cf, ncol))
-    out.append("  }")
+    out.append(f"  static constexpr bool LANE = {'true' if lane else 'false'};")
+    if lane:
+        out.append("  static __device__ __forceinline__ void amplitudes(const double (*p)[4], const int* lam, "
+                   "double g, double mt, cx* jamp) {")
+        out.extend('  ' + l for l in body)
+        out.append("  }")
+        out.append("  static __device__ __forceinline__ double colour_sum(const cx* jamp) {")
+        out.extend('  ' + l for l in colour_sum_code(cf, ncol))
+        out.append("  }")
     out.append("};")
     out.append("}  // namespace me")
     return '\n'.join(out) + '\n', plan, (cf, den)

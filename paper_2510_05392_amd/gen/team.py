@@ -30,12 +30,28 @@ the kernel that runs it is csrc/me_team.h.
 from __future__ import annotations
 
 import collections
+import heapq
 
 from .colour import colour_matrix
 from .topology import Plan
 
 T_DEFAULT = 32
+
+
+def team_width(n):
+    """Lanes per team: 64 (one team per wavefront) when the program has enough
+    parallel ops per step, else 32."""
+    return 64 if n >= 5 else 32
+
+
+def team_window(n):
+    """How far (in emission order) a step may reach ahead of its earliest op:
+    bounded for the largest programs, where it cuts the LDS frame by a quarter
+    at a few per cent of lane use."""
+    return 4096 if n >= 6 else None
 NONE = 0xFFFF
+SLOT = 9        # doubles between object slots in the LDS frame (must match me_team.h)
+MSTRIDE = 5     # doubles between momentum-table entries (must match me_team.h)
 
 
 def slot_particle(slot):
@@ -69,10 +85,11 @@ class TeamProgram:
     CLASSES = ('V3', 'V4', 'ROWV', 'VCOL', 'ROWP', 'PCOL', 'LINE', 'AMP')
     NOPER = {'V3': 6, 'V4': 8, 'ROWV': 3, 'VCOL': 3, 'ROWP': 3, 'PCOL': 3, 'LINE': 3, 'AMP': 3}
 
-    def __init__(self, name, plan: Plan, T=T_DEFAULT):
+    def __init__(self, name, plan: Plan, T=T_DEFAULT, window=None):
         self.name = name
         self.plan = plan
         self.T = T
+        self.window = window if window is not None else 1 << 30
         self.n = plan.n
         self.npar = self.n + 2
         self.ncol = len(plan.basis)
@@ -221,27 +238,29 @@ class TeamProgram:
             indeg[k] = len(ds)
             for d in ds:
                 users[d].append(k)
+        # per class a heap of ready ops by rank; each step takes the class whose
+        # earliest ready op comes first in the emission order
         ready = collections.defaultdict(list)
         for k in self.ops:
             if indeg[k] == 0:
-                ready[self.ops[k][0]].append(k)
+                heapq.heappush(ready[self.ops[k][0]], (rank[k], k))
         passes = []
         done = 0
         while done < len(self.ops):
-            cls = min(ready, key=lambda c: min(rank[k] for k in ready[c]))
-            lst = sorted(ready[cls], key=lambda k: rank[k])
-            batch, rest = lst[:self.T], lst[self.T:]
-            if rest:
-                ready[cls] = rest
-            else:
-                del ready[cls]
+            cls = min((c for c in ready if ready[c]), key=lambda c: ready[c][0][0])
+            heap = ready[cls]
+            # ops far ahead of the earliest ready one would stretch live ranges
+            limit = heap[0][0] + self.window
+            batch = []
+            while heap and len(batch) < self.T and heap[0][0] <= limit:
+                batch.append(heapq.heappop(heap)[1])
             passes.append((cls, batch))
             for k in batch:
                 done += 1
                 for u in users[k]:
                     indeg[u] -= 1
                     if indeg[u] == 0:
-                        ready[self.ops[u][0]].append(u)
+                        heapq.heappush(ready[self.ops[u][0]], (rank[u], u))
         self.passes = passes
 
     def _allocate(self):
@@ -280,56 +299,76 @@ class TeamProgram:
                     free.append(slot[k])
             free.sort(reverse=True)
         self.slot = slot
-        self.nslot = max(nslot, (2 * self.ncol + 7) // 8)   # the flows reuse the slot area
+        self.nslot = max(nslot, 1)
 
     # ------------------------------------------------------------ tables
     def tables(self):
-        """uint16 operand table, per-pass (class, count, offset), flow tables."""
-        T = self.T
-        tab = []
-        prog = []
-        for cls, batch in self.passes:
-            off = len(tab)
-            rows = []
-            for k in batch:
-                spec = self.ops[k][1]
-                if cls == 'AMP':
-                    a, b, metric = spec
-                    row = [self.slot[a], self.slot[b], metric]
-                else:
-                    row = [self.slot[x] if isinstance(x, tuple) else x for x in spec] + [self.slot[k]]
-                assert len(row) == self.NOPER[cls], (cls, row)
-                rows.append(row)
-            for j in range(self.NOPER[cls]):
-                for i in range(T):
-                    tab.append(rows[i][j] if i < len(rows) else 0)
-            entry = {'cls': cls, 'n': len(batch), 'off': off}
-            if cls == 'AMP':
-                entry['flows'] = self._flow_tables(batch, tab)
-            prog.append(entry)
-        return tab, prog
+        """Operand rows, flow words and step records.
 
-    def _flow_tables(self, batch, tab):
-        """Per local flow index L (flow L*T + t of lane t): entries (amp lane | coef << 6)."""
+        ops:   uint16, one row of 8 operands per lane per step (rows padded to T
+               per step, unused operands 0), so that a lane reads its operands
+               of a step with one 16-byte load;
+        flows: uint32 records per AMP step, laid out [record][lane] (see
+               _flow_records);
+        steps: (class, n, first row, record offset, records per lane).
+        """
         T = self.T
-        per = collections.defaultdict(list)    # (lane, L) -> entries
+        ops, flows, steps = [], [], []
+        nloc = (self.ncol + T - 1) // T
+        for cls, batch in self.passes:
+            row0 = len(ops) // 8
+            for i in range(T):
+                if i < len(batch):
+                    k = batch[i]
+                    spec = self.ops[k][1]
+                    if cls == 'AMP':
+                        a, b, metric = spec
+                        row = [self.slot[a], self.slot[b], metric]
+                    else:
+                        row = [self.slot[x] if isinstance(x, tuple) else x for x in spec] + [self.slot[k]]
+                    assert len(row) == self.NOPER[cls], (cls, row)
+                else:
+                    row = []
+                ops += row + [0] * (8 - len(row))
+            rec = {'cls': cls, 'n': len(batch), 'row': row0, 'foff': 0, 'mw': 0}
+            if cls == 'AMP':
+                rec['foff'], rec['mw'] = len(flows), self._flow_records(batch, flows)
+            steps.append(rec)
+        return ops, flows, steps
+
+    def _flow_records(self, batch, flows):
+        """Colour-flow records of one amplitude step; returns records per lane.
+
+        Every flow touched by the step is given to one lane (longest lists
+        first, to the least loaded lane), so no two lanes update one flow.  A
+        lane's records are sorted by flow: 4 * amp lane + coefficient (bits
+        0-7; coefficient 0: +1, 1: -1, 2: +i, 3: -i, the amplitude step stores
+        all four products), flow (bits 8-19), bit 20 set on the last record of
+        a flow (the lane then adds its running sum to the flow in LDS).
+        Padding records are 0xFFFFFFFF.
+        """
+        T = self.T
+        per_flow = collections.defaultdict(list)
         for i, akey in enumerate(batch):
             for k, c in self.amp_info[akey]:
                 code = {1: 0, -1: 1, 1j: 2, -1j: 3}[complex(round(c.real), round(c.imag))]
-                per[(k % T, k // T)].append(i | (code << 6))
-        out = []
-        nloc = (self.ncol + T - 1) // T
-        for L in range(nloc):
-            m = max((len(per[(t, L)]) for t in range(T)), default=0)
-            if m == 0:
-                continue
-            off = len(tab)
-            for j in range(m):
-                for t in range(T):
-                    lst = per[(t, L)]
-                    tab.append(lst[j] if j < len(lst) else NONE)
-            out.append((L, off, m))
-        return out
+                per_flow[k].append((i << 2) | code)
+        load = [0] * T
+        lanes = [[] for _ in range(T)]
+        free = [(0, t) for t in range(T)]
+        for k in sorted(per_flow, key=lambda k: (-len(per_flow[k]), k)):
+            _, t = heapq.heappop(free)
+            ents = per_flow[k]
+            for n, e in enumerate(ents):
+                lanes[t].append(e | (k << 8) | ((1 << 20) if n == len(ents) - 1 else 0))
+            load[t] += len(ents)
+            heapq.heappush(free, (load[t], t))
+        assert self.ncol < (1 << 12)
+        r = max(load)
+        for q in range(r):
+            for t in range(T):
+                flows.append(lanes[t][q] if q < len(lanes[t]) else 0xFFFFFFFF)
+        return r
 
     def stats(self):
         util = sum(len(b) for _, b in self.passes) / (self.T * len(self.passes))
@@ -340,54 +379,59 @@ class TeamProgram:
 CLASS_ID = {'V3': 0, 'V4': 1, 'ROWV': 2, 'VCOL': 3, 'ROWP': 4, 'PCOL': 5, 'LINE': 6, 'AMP': 7, 'FLOWS': 8}
 
 
-def emit(name, plan, T=T_DEFAULT):
+def emit(name, plan, T=None):
     """HIP source of struct me::<name>_team (the team program of the process)."""
-    prog = TeamProgram(name, plan, T)
-    tab, passes = prog.tables()
+    T = T or team_width(plan.n)
+    prog = TeamProgram(name, plan, T, team_window(plan.n))
+    ops, flows, steps = prog.tables()
     cf, den = colour_matrix(plan.n)
     ncol = prog.ncol
     npar = prog.npar
     nmom = len(prog.moms)
     nloc = (ncol + T - 1) // T
-    # frame layout (doubles): slots | momentum table | external momenta | amplitude buffer
-    moff = prog.nslot * 8
-    poff = moff + nmom * 4
+    # frame layout (doubles): slots (SLOT = 9 doubles apart, which spreads the
+    # lanes' accesses over the LDS banks) | colour flows | momentum table (5
+    # doubles apart) | external momenta | amplitude buffer
+    joff = prog.nslot * SLOT
+    moff = joff + 2 * ncol
+    poff = moff + nmom * MSTRIDE
     aoff = poff + npar * 4
-    frame = aoff + T * 2
+    frame = aoff + T * 8
     words = []
-    for p in passes:
-        words += [CLASS_ID[p['cls']] | (p['n'] << 8), p['off']]
-        if p['cls'] == 'AMP':
-            flows = {loc: (off, m) for loc, off, m in p['flows']}
-            words.append(CLASS_ID['FLOWS'])
-            for loc in range(nloc):
-                words += list(flows.get(loc, (0, 0)))
-    assert max(tab, default=0) <= 0xFFFF and len(tab) < 2 ** 32
+    for r in steps:
+        words += [CLASS_ID[r['cls']] | (r['n'] << 8), r['row']]
+        if r['cls'] == 'AMP':
+            words += [r['foff'], r['mw']]
+    fmaxw = max((r['mw'] for r in steps), default=1)
+    assert max(ops, default=0) <= 0xFFFF
     L = []
     st = prog.stats()
     L.append(f"// Team program of {name}: {st['ops']} ops in {st['passes']} steps of up to {T} lanes "
              f"(lane use {st['lane_util']:.2f}),")
     L.append(f"// {prog.nslot} object slots, {nmom} momentum sums; LDS frame {frame * 8} bytes.")
     L.append("namespace me {")
-    L.append(f"static __device__ const uint16_t TEAMTAB_{name}[{max(1, len(tab))}] = {{"
-             + ', '.join(str(v) for v in tab) + "};")
+    L.append(f"alignas(16) static __device__ const uint16_t TEAMOPS_{name}[{max(8, len(ops))}] = {{"
+             + ', '.join(str(v) for v in ops) + "};")
+    L.append(f"static __device__ const uint32_t TEAMFLOW_{name}[{max(1, len(flows))}] = {{"
+             + ', '.join(f'{v}u' for v in flows) + "};")
     L.append(f"static __device__ const uint32_t TEAMPROG_{name}[{len(words)}] = {{"
              + ', '.join(str(v) for v in words) + "};")
     masks = sorted(prog.moms.items(), key=lambda kv: kv[1])
     L.append(f"static __device__ const uint16_t TEAMMOM_{name}[{nmom}] = {{"
              + ', '.join(str(m) for m, _ in masks) + "};")
     flat = ', '.join(str(cf[j][i]) for j in range(ncol) for i in range(ncol))
-    L.append(f"static __device__ const int16_t TEAMCF_{name}[{ncol * ncol}] = {{{flat}}};")
+    L.append(f"static __device__ const int32_t TEAMCF_{name}[{ncol * ncol}] = {{{flat}}};")
     L.append(f"struct {name}_team {{")
     L.append(f'  static constexpr const char* NAME = "{name}";')
-    for k, v in (('T', T), ('NPAR', npar), ('NCOL', ncol), ('NLOC', nloc), ('NMOM', nmom), ('MOFF', moff),
-                 ('POFF', poff), ('AOFF', aoff), ('FRAME', frame), ('NPROGW', len(words)),
-                 ('NEXT', len(prog.ext))):
+    for k, v in (('T', T), ('NPAR', npar), ('NCOL', ncol), ('NLOC', nloc), ('NMOM', nmom), ('JOFF', joff),
+                 ('MOFF', moff), ('POFF', poff), ('AOFF', aoff), ('FRAME', frame), ('NPROGW', len(words)),
+                 ('NEXT', len(prog.ext)), ('RMAX', fmaxw)):
         L.append(f"  static constexpr int {k} = {v};")
-    L.append(f"  static __device__ __forceinline__ const uint16_t* table() {{ return TEAMTAB_{name}; }}")
+    L.append(f"  static __device__ __forceinline__ const uint16_t* ops() {{ return TEAMOPS_{name}; }}")
+    L.append(f"  static __device__ __forceinline__ const uint32_t* flows() {{ return TEAMFLOW_{name}; }}")
     L.append(f"  static __device__ __forceinline__ const uint32_t* program() {{ return TEAMPROG_{name}; }}")
     L.append(f"  static __device__ __forceinline__ const uint16_t* momentum_masks() {{ return TEAMMOM_{name}; }}")
-    L.append(f"  static __device__ __forceinline__ const int16_t* colour_matrix() {{ return TEAMCF_{name}; }}")
+    L.append(f"  static __device__ __forceinline__ const int32_t* colour_matrix() {{ return TEAMCF_{name}; }}")
     L.append("  // external states: lane t < NEXT computes external state t of the frame")
     L.append("  static __device__ __forceinline__ void externals(double* F, int t, int hel, double mt) {")
     L.append("    switch (t) {")

@@ -478,6 +478,14 @@ class Plan:
         retires after its last consumer); the order with the smallest peak over
         a few alphas is kept.  The order only affects register pressure.
         """
+        groups = self.colour_groups()
+        if len(groups) > 2000:
+            # the list scheduler is quadratic in the number of groups; large
+            # processes (which only get the team program, where the order sets
+            # the LDS frame size, not registers) take the groups in the order
+            # of their earliest current in the plan
+            pos = {k: i for i, k in enumerate(self.order)}
+            return sorted(groups, key=lambda g: min(pos[o] for _, a in g[1] for o in a[1:]))
         best = None
         for a in alphas:
             order = self._schedule(a)

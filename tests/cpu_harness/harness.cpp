@@ -5,10 +5,11 @@ namespace me { using PROC = me::PROCNAME; }
 
 extern "C" int harness_ncol() { return me::PROC::NCOL; }
 
-extern "C" void harness_eval(const double* mom, int nevt, double g, double mt, const int* hels,
-                             int nh, double* me_h /*[nh][nevt]*/, double* jamp_out /*[nh][nevt][NCOL][2]*/) {
+template <class P>
+void lane_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h,
+               double* jamp_out) {
   using namespace me;
-  constexpr int NPAR = PROC::NPAR, NCOL = PROC::NCOL;
+  constexpr int NPAR = P::NPAR, NCOL = P::NCOL;
   for (int e = 0; e < nevt; ++e) {
     double p[NPAR][4];
     for (int q = 0; q < NPAR; ++q)
@@ -18,8 +19,8 @@ extern "C" void harness_eval(const double* mom, int nevt, double g, double mt, c
       for (int q = 0; q < NPAR; ++q) lam[q] = (hels[k] >> (NPAR - 1 - q)) & 1 ? 1 : -1;
       cx jamp[NCOL];
       for (int c = 0; c < NCOL; ++c) jamp[c] = cx{0.0, 0.0};
-      PROC::amplitudes(p, lam, g, mt, jamp);
-      me_h[k * nevt + e] = PROC::colour_sum(jamp) / PROC::CF_DEN;
+      P::amplitudes(p, lam, g, mt, jamp);
+      me_h[k * nevt + e] = P::colour_sum(jamp) / P::CF_DEN;
       if (jamp_out)
         for (int c = 0; c < NCOL; ++c) {
           jamp_out[((k * nevt + e) * NCOL + c) * 2] = jamp[c].r;
@@ -29,6 +30,17 @@ extern "C" void harness_eval(const double* mom, int nevt, double g, double mt, c
   }
 }
 
+template <class P>
+void lane_dispatch(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h,
+                   double* jamp_out) {
+  if constexpr (P::LANE) lane_eval<P>(mom, nevt, g, mt, hels, nh, me_h, jamp_out);
+}
+
+extern "C" void harness_eval(const double* mom, int nevt, double g, double mt, const int* hels,
+                             int nh, double* me_h /*[nh][nevt]*/, double* jamp_out /*[nh][nevt][NCOL][2]*/) {
+  lane_dispatch<me::PROC>(mom, nevt, g, mt, hels, nh, me_h, jamp_out);
+}
+
 // Serial emulation of the team executor: every step runs for all lanes of
 // the team before the next one starts (the GPU separates steps by barriers).
 extern "C" void harness_team_eval(const double* mom, int nevt, double g, double mt, const int* hels,
@@ -36,31 +48,35 @@ extern "C" void harness_team_eval(const double* mom, int nevt, double g, double 
   using namespace me;
   using X = PROC::Team;
   static double F[X::FRAME];
+  const uint32_t* prog = X::program();
   for (int e = 0; e < nevt; ++e) {
     for (int i = 0; i < X::NPAR * 4; ++i) F[X::POFF + i] = mom[e * X::NPAR * 4 + i];
     for (int t = 0; t < X::T; ++t)
       team_momenta<X::NPAR>(F, X::MOFF, X::POFF, X::momentum_masks(), X::NMOM, t, X::T);
     for (int k = 0; k < nh; ++k) {
+      for (int i = 0; i < 2 * X::NCOL; ++i) F[X::JOFF + i] = 0.0;
       for (int t = 0; t < X::T; ++t) X::externals(F, t, hels[k], mt);
-      static cx jl[X::T][X::NLOC];
-      for (int t = 0; t < X::T; ++t)
-        for (int L = 0; L < X::NLOC; ++L) jl[t][L] = cx{0.0, 0.0};
-      const uint32_t* prog = X::program();
       for (int w = 0; w < X::NPROGW;) {
-        int adv = 0;
-        for (int t = 0; t < X::T; ++t) adv = team_step<X>(prog + w, F, t, g, mt, jl[t]);
-        w += adv;
-      }
-      for (int t = 0; t < X::T; ++t)
-        for (int L = 0; L < X::NLOC; ++L) {
-          const int i = L * X::T + t;
-          if (i < X::NCOL) {
-            F[2 * i] = jl[t][L].r;
-            F[2 * i + 1] = jl[t][L].i;
-          }
+        const int cls = prog[w] & 0xff, n = prog[w] >> 8;
+        unsigned o[8];
+        for (int t = 0; t < n; ++t) {
+          team_row(X::ops(), prog[w + 1] + t, o);
+          team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, g, mt);
         }
+        if (cls == TC_AMP) {
+          const uint32_t foff = prog[w + 2], nr = prog[w + 3];
+          for (int t = 0; t < X::T; ++t) {
+            cx run{0.0, 0.0};
+            for (uint32_t q = 0; q < nr; ++q)
+              team_flow_record(F, X::AOFF, X::JOFF, X::flows()[foff + q * X::T + t], run);
+          }
+          w += 4;
+        } else {
+          w += 2;
+        }
+      }
       double part = 0.0;
-      for (int t = 0; t < X::T; ++t) part += team_colour<X>(F, t, jl[t]);
+      for (int t = 0; t < X::T; ++t) part += team_colour<X>(F, t);
       me_h[k * nevt + e] = part / PROC::CF_DEN;
     }
   }

@@ -8,3 +8,6 @@
 #define __host__
 #define __forceinline__ inline
 using std::sqrt;
+struct uint4 {
+  unsigned x, y, z, w;
+};

@@ -3,7 +3,7 @@
 Calls only the oracle (and the seeded input generator): no value here comes
 from the HIP path.  Run from the repository root:
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py [ggttggg] [ggttgggg]
 """
 import os
 import sys
@@ -26,7 +26,7 @@ def values(proc, mom):
             me.matrix_element(proc, mom.astype(np.longdouble), AS).astype(np.float64))
 
 
-def main():
+def ggttggg():
     proc = me.process(7)
     # g g -> t tbar g g g: three 64-event tiles and a ragged tail
     mom = rambo.generate(7, 197, 1003)
@@ -41,5 +41,20 @@ def main():
                         momenta=full[idx], me=m64, me_ext=mext)
 
 
+def ggttgggg():
+    # g g -> t tbar g g g g, the 32768-event workload: 24 events spread over it
+    proc = me.process(8)
+    full = rambo.generate(8, 32768, 1005)
+    idx = np.unique(np.concatenate([np.arange(3), np.linspace(3, 32767, 21).astype(int)]))
+    m64, mext = values(proc, full[idx])
+    np.savez_compressed(os.path.join(HERE, 'gg_ttxgggg_seed1005_n32768_sampled.npz'), index=idx,
+                        momenta=full[idx], me=m64, me_ext=mext)
+
+
+def main(which):
+    for name in which or ('ggttggg', 'ggttgggg'):
+        {'ggttggg': ggttggg, 'ggttgggg': ggttgggg}[name]()
+
+
 if __name__ == '__main__':
-    main()
+    main(sys.argv[1:])

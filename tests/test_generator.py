@@ -83,3 +83,52 @@ def test_generated_code_on_host_vs_oracle(name, npar, nevt, opt, hels):
     ph = np.where(ok, num / np.where(ok, den, 1), 1)
     dev = np.abs(jam - ph[..., None] * jo).max(axis=(0, 2))
     assert np.all(dev <= 1e-12 * jscale)
+
+
+@pytest.mark.parametrize('name,npar,nevt,opt,hels', [
+    ('gg_ttx', 4, 16, '-O1', None), ('gg_ttxg', 5, 8, '-O1', None),
+    ('gg_ttxgg', 6, 4, '-O1', None), ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127))])
+def test_team_program_on_host_vs_oracle(name, npar, nevt, opt, hels):
+    # serial emulation of the team executor (every step for all lanes, then the
+    # next step) with the same device routines as the GPU
+    h = harness.build(name, opt)
+    mom = rambo.generate(npar, nevt, 6)
+    hels = list(range(2 ** npar)) if hels is None else list(hels)
+    meh = h.team_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels)
+    ref = ome.me_helicities(ome.process(npar), mom, AS, hels)
+    assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
+
+
+def test_team_program_slots_and_schedule():
+    # every op runs once, after its operands, and no slot is overwritten while live
+    from paper_2510_05392_amd.gen import team
+    for n in (3, 4):
+        p = team.TeamProgram('x', topology.Plan(n))
+        step_of = {}
+        for si, (cls, batch) in enumerate(p.passes):
+            assert 0 < len(batch) <= p.T and len({p.ops[k][0] for k in batch}) == 1
+            for k in batch:
+                assert k not in step_of
+                step_of[k] = si
+        assert set(step_of) == set(p.ops)
+        for k, si in step_of.items():
+            for d in p.deps(k):
+                assert d not in step_of or step_of[d] < si
+        # live ranges of objects sharing a slot do not overlap
+        last = {}
+        for k, si in step_of.items():
+            for d in p.deps(k):
+                last[d] = max(last.get(d, -1), si)
+        ranges = {}
+        for key, *_ in p.ext:
+            ranges[key] = (-1, last.get(key, -1))
+        for k, si in step_of.items():
+            if p.ops[k][0] != 'AMP':
+                ranges[k] = (si, last.get(k, si))
+        by_slot = {}
+        for k, (a, b) in ranges.items():
+            by_slot.setdefault(p.slot[k], []).append((a, b))
+        for s, rs in by_slot.items():
+            rs.sort()
+            for (a0, b0), (a1, b1) in zip(rs, rs[1:]):
+                assert a1 > b0, (s, rs)
