@@ -22,6 +22,14 @@ sys.path.insert(0, HERE)
 
 FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/clk (FMA = 2)
 
+# HBM bytes per launch of the FP64 diagram kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# scaled by the same counters on a plain 2 GiB copy (x2.0 and x1.0), keyed by the workload and
+# launch configuration (persistent, waves/SIMD, helicities/item, target waves, executor); the
+# numbers and the commands are in the named profile and hold only for the kernel they were taken on.
+MEASURED_TRAFFIC = {
+    ('gg_ttxggg', 262144, (1, 1, 1, 4096, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
+}
+
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
 SEED = {'gg_ttx': 1001, 'gg_ttxg': 1004, 'gg_ttxgg': 1002, 'gg_ttxggg': 1003, 'gg_ttxgggg': 1005}
 
@@ -126,6 +134,9 @@ def main():
     ap.add_argument('--autotune', action=argparse.BooleanOptionalAction, default=True,
                     help='pick the FP64 launch configuration with the library autotuner first')
     ap.add_argument('--no-graph', action='store_true', help='do not replay me_compute from a hipGraph')
+    ap.add_argument('--launch', default=None,
+                    help='fixed FP64 launch "persistent,waves_per_simd,hel_per_item,target_waves,executor" '
+                         'instead of autotuning (profiling runs)')
     ap.add_argument('--surrogate', action=argparse.BooleanOptionalAction, default=True,
                     help='also measure mixed precision + surrogate two-stage unweighting')
     ap.add_argument('--sur-train', type=int, default=131072)
@@ -154,7 +165,13 @@ def main():
         out = torch.empty(nevt, dtype=torch.float64, device=dev)
         m = binding.MatrixElement(process, colorsum_mode=mode, use_graph=not args.no_graph)
         tuned = None
-        if args.autotune and mode == binding.ME_CS_FP64:
+        if args.launch and mode == binding.ME_CS_FP64:
+            p_, w_, h_, t_, x_ = (int(v) for v in args.launch.split(','))
+            m.me_set_launch(p_, w_, h_, t_)
+            m.me_set_executor(x_)
+            tuned = {'persistent': p_, 'waves_per_simd': w_, 'hel_per_item': h_, 'target_waves': t_,
+                     'executor': x_}
+        elif args.autotune and mode == binding.ME_CS_FP64:
             nt = min(nevt, 65536)
             print(f'# bench autotune on {nt} events', file=sys.stderr, flush=True)
             tuned = m.me_autotune(dmom[:nt], nt, args.alpha_s, out[:nt], stream)
@@ -191,6 +208,11 @@ def main():
         except binding.MeError as exc:
             mixed = {'skipped': str(exc)}
 
+    traffic = None
+    if tuned:
+        key = (process, nevt, tuple(tuned[k] for k in ('persistent', 'waves_per_simd', 'hel_per_item',
+                                                          'target_waves', 'executor')))
+        traffic = MEASURED_TRAFFIC.get(key)
     f_unit = flops.per_event_helicity(process)
     step_flops = f_unit * nhel * nevt
     achieved = step_flops / (ms * 1e-3) / 1e12
@@ -204,7 +226,9 @@ def main():
                    'good_helicities': nhel, 'parallelism': 'single GPU', 'launch': tuned,
                    'hipgraph': not args.no_graph},
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
-                     'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS, 'traffic': None,
+                     'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS,
+                     'traffic': traffic[0] if traffic else None,
+                     'traffic_source': traffic[1] if traffic else None,
                      'flops_per_event_helicity': f_unit,
                      'kernel': (f'team_kernel<{process}_team>' if tuned and tuned.get('executor') == 1
                                 else f'me_kernel<{process}>') + ' (+ reduce_chunks_kernel, <0.1%)'},

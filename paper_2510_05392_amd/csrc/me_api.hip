@@ -549,8 +549,9 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
   if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_TEAM) {
-    // one workgroup (one wavefront) per two events; helicity chunks fill the grid
-    const int64_t blocks = (nevt + 1) / 2;
+    // one workgroup (one wavefront) per 64 / T events; helicity chunks fill the grid
+    const int64_t per = h->desc->team_events_per_block;
+    const int64_t blocks = (nevt + per - 1) / per;
     int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (h->target_waves + blocks - 1) / blocks));
     const int hpc = (nhel + nchunk - 1) / nchunk;
     nchunk = (nhel + hpc - 1) / hpc;
@@ -848,7 +849,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0}, {1, 1, 0, 0, 0},
              {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},    {1, 1, 1, 0, 0},     {1, 2, 1, 0, 0}};
   if (h->params.colorsum_mode == ME_CS_FP64)
-    for (int tw : {1024, 8192, 65536}) cands.push_back({0, 1, 0, tw, 1});
+    for (int tw : {1024, 262144, 1048576}) cands.push_back({0, 1, 0, tw, 1});
   const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
             save_tw = h->target_waves, save_graph = h->params.use_graph, save_x = h->executor;
   h->params.use_graph = 0;

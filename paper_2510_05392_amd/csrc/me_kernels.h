@@ -195,7 +195,7 @@ const ProcessDesc* describe() {
   }
   static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,     P::NHEL, P::IDEN,
                                 P::CF_DEN, P::NDIAG, P::cf_int(), lane,    colour,
-                                &launch_team<typename P::Team>};
+                                &launch_team<typename P::Team>, 64 / P::Team::T};
   return &d;
 }
 

@@ -74,6 +74,7 @@ struct ProcessDesc {
   Launcher launch;            // partial colour sums per helicity chunk, or dual amplitudes
   ColourLauncher colour;      // matrix-core colour sum of stored dual amplitudes
   Launcher team;              // team executor: partial colour sums per helicity chunk
+  int team_events_per_block;  // events per workgroup of the team executor (64 / lanes per team)
 };
 
 }  // namespace me

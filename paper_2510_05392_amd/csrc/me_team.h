@@ -11,9 +11,10 @@
 // on diagram groups); this executor exchanges them through LDS.
 //
 // Frame of a team (doubles, offsets generated per process):
-//   [0, JOFF)          object slots (4 complex each), TEAM_SLOT doubles apart:
-//                      an odd number of 8-byte words between slots spreads the
-//                      lanes' accesses over the LDS banks
+//   [0, JOFF)          object slots (4 complex each), X::SLOT doubles apart: 9
+//                      (an odd number of 8-byte words spreads the lanes'
+//                      accesses over the LDS banks), or 8 when that lets one
+//                      more workgroup fit in the CU's LDS
 //   [JOFF, MOFF)       the colour flows J_i (complex), accumulated in place
 //   [MOFF, POFF)       table of signed momentum sums, TEAM_MSTRIDE doubles apart
 //   [POFF, AOFF)       the event's external momenta p_q, 4 doubles each
@@ -36,17 +37,16 @@ namespace me {
 
 enum TeamClass { TC_V3 = 0, TC_V4, TC_ROWV, TC_VCOL, TC_ROWP, TC_PCOL, TC_LINE, TC_AMP, TC_FLOWS };
 
-constexpr int TEAM_SLOT = 9;      // doubles between object slots
 constexpr int TEAM_MSTRIDE = 5;   // doubles between momentum-table entries
 
-__device__ __forceinline__ void team_load(const double* F, int slot, cx* v) {
-  const double* s = F + slot * TEAM_SLOT;
+__device__ __forceinline__ void team_load(const double* F, int slot, cx* v, int ss) {
+  const double* s = F + slot * ss;
 #pragma unroll
   for (int u = 0; u < 4; ++u) v[u] = cx{s[2 * u], s[2 * u + 1]};
 }
 
-__device__ __forceinline__ void team_store(double* F, int slot, const cx* v) {
-  double* s = F + slot * TEAM_SLOT;
+__device__ __forceinline__ void team_store(double* F, int slot, const cx* v, int ss) {
+  double* s = F + slot * ss;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     s[2 * u] = v[u].r;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void team_momenta(double* F, int moff, int poff, cons
 }
 
 // External state of particle Q (KIND 0: ubar, 1: v, 2: gluon) into `slot`.
-template <int KIND, int Q, int OUTGOING, int NPAR>
+template <int KIND, int Q, int OUTGOING, int NPAR, int SS>
 __device__ __forceinline__ void team_external(double* F, int poff, int slot, int hel, double mt) {
   double p[4];
 #pragma unroll
@@ -95,34 +95,34 @@ __device__ __forceinline__ void team_external(double* F, int poff, int slot, int
     ext_v(p, lam, mt, w);
   else
     ext_gluon(p, lam, OUTGOING != 0, w);
-  team_store(F, slot, w);
+  team_store(F, slot, w, SS);
 }
 
 // One op of class C for one lane, operands o[0..7] of its row.
 template <int C>
 __device__ __forceinline__ void team_op(double* F, int moff, int aoff, const unsigned* o, int t, double g,
-                                        double mt) {
+                                        double mt, int ss) {
   cx a[4], b[4], out[4];
   if (C == TC_V3) {
     double pa[4], pb[4], pf[4];
-    team_load(F, o[0], a);
+    team_load(F, o[0], a, ss);
     team_mom(F, moff, o[1], pa);
-    team_load(F, o[2], b);
+    team_load(F, o[2], b, ss);
     team_mom(F, moff, o[3], pb);
     team_mom(F, moff, o[4], pf);
     v3_open(a, pa, b, pb, -g / msq(pf), out);
-    team_store(F, o[5], out);
+    team_store(F, o[5], out, ss);
   } else if (C == TC_V4) {
     // out = f (P0 (X0.Y0) - P1 (X1.Y1)), f = -g^2 / P^2
     cx x[4];
-    team_load(F, o[1], x);
-    team_load(F, o[2], b);
+    team_load(F, o[1], x, ss);
+    team_load(F, o[2], b, ss);
     const cx d0 = vdot(x, b);
-    team_load(F, o[4], x);
-    team_load(F, o[5], b);
+    team_load(F, o[4], x, ss);
+    team_load(F, o[5], b, ss);
     const cx d1 = vdot(x, b);
-    team_load(F, o[0], a);
-    team_load(F, o[3], b);
+    team_load(F, o[0], a, ss);
+    team_load(F, o[3], b, ss);
     double pf[4];
     team_mom(F, moff, o[6], pf);
     const double f = -g * g / msq(pf);
@@ -132,38 +132,38 @@ __device__ __forceinline__ void team_op(double* F, int moff, int aoff, const uns
       acc = acc - b[u] * d1;
       out[u] = f * acc;
     }
-    team_store(F, o[7], out);
+    team_store(F, o[7], out, ss);
   } else if (C == TC_ROWV) {
-    team_load(F, o[0], a);
-    team_load(F, o[1], b);
+    team_load(F, o[0], a, ss);
+    team_load(F, o[1], b, ss);
     row_vertex(a, b, g, out);
-    team_store(F, o[2], out);
+    team_store(F, o[2], out, ss);
   } else if (C == TC_VCOL) {
-    team_load(F, o[0], a);
-    team_load(F, o[1], b);
+    team_load(F, o[0], a, ss);
+    team_load(F, o[1], b, ss);
     vertex_col(a, b, g, out);
-    team_store(F, o[2], out);
+    team_store(F, o[2], out, ss);
   } else if (C == TC_ROWP) {
     double q[4];
-    team_load(F, o[0], a);
+    team_load(F, o[0], a, ss);
     team_mom(F, moff, o[1], q);
     row_prop(a, q, mt, out);
-    team_store(F, o[2], out);
+    team_store(F, o[2], out, ss);
   } else if (C == TC_PCOL) {
     double q[4];
-    team_load(F, o[0], a);
+    team_load(F, o[0], a, ss);
     team_mom(F, moff, o[1], q);
     prop_col(q, mt, a, out);
-    team_store(F, o[2], out);
+    team_store(F, o[2], out, ss);
   } else if (C == TC_LINE) {
-    team_load(F, o[0], a);
-    team_load(F, o[1], b);
+    team_load(F, o[0], a, ss);
+    team_load(F, o[1], b, ss);
     line_current(a, b, g, out);
-    team_store(F, o[2], out);
+    team_store(F, o[2], out, ss);
   } else if (C == TC_AMP) {
     // the amplitude times +1, -1, +i and -i, so that a flow record only adds
-    team_load(F, o[0], a);
-    team_load(F, o[1], b);
+    team_load(F, o[0], a, ss);
+    team_load(F, o[1], b, ss);
     const cx v = o[2] ? vdot(a, b) : sdot(a, b);
     double* s = F + aoff + 8 * t;
     s[0] = v.r;
@@ -178,16 +178,16 @@ __device__ __forceinline__ void team_op(double* F, int moff, int aoff, const uns
 }
 
 __device__ __forceinline__ void team_dispatch(int cls, double* F, int moff, int aoff, const unsigned* o, int t,
-                                              double g, double mt) {
+                                              double g, double mt, int ss) {
   switch (cls) {
-    case TC_V3: team_op<TC_V3>(F, moff, aoff, o, t, g, mt); break;
-    case TC_V4: team_op<TC_V4>(F, moff, aoff, o, t, g, mt); break;
-    case TC_ROWV: team_op<TC_ROWV>(F, moff, aoff, o, t, g, mt); break;
-    case TC_VCOL: team_op<TC_VCOL>(F, moff, aoff, o, t, g, mt); break;
-    case TC_ROWP: team_op<TC_ROWP>(F, moff, aoff, o, t, g, mt); break;
-    case TC_PCOL: team_op<TC_PCOL>(F, moff, aoff, o, t, g, mt); break;
-    case TC_LINE: team_op<TC_LINE>(F, moff, aoff, o, t, g, mt); break;
-    default: team_op<TC_AMP>(F, moff, aoff, o, t, g, mt); break;
+    case TC_V3: team_op<TC_V3>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_V4: team_op<TC_V4>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_ROWV: team_op<TC_ROWV>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_VCOL: team_op<TC_VCOL>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_ROWP: team_op<TC_ROWP>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_PCOL: team_op<TC_PCOL>(F, moff, aoff, o, t, g, mt, ss); break;
+    case TC_LINE: team_op<TC_LINE>(F, moff, aoff, o, t, g, mt, ss); break;
+    default: team_op<TC_AMP>(F, moff, aoff, o, t, g, mt, ss); break;
   }
 }
 
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(64) team_kernel(const double* __restrict__ mom
         uint32_t rec[RCH];
 #pragma unroll
         for (int q = 0; q < RCH; ++q) rec[q] = q < (int)nr ? flows[foff + (uint32_t)q * X::T + t] : ~0u;
-        if (t < n) team_op<TC_AMP>(F, X::MOFF, X::AOFF, o, t, gl, mt);
+        if (t < n) team_op<TC_AMP>(F, X::MOFF, X::AOFF, o, t, gl, mt, X::SLOT);
         __syncthreads();
         cx run{0.0, 0.0};
         for (uint32_t q0 = 0; q0 < nr; q0 += RCH) {
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(64) team_kernel(const double* __restrict__ mom
             if (q0 + q < nr) team_flow_record(F, X::AOFF, X::JOFF, rec[q], run);
         }
       } else if (t < n) {
-        team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, gl, mt);
+        team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, gl, mt, X::SLOT);
       }
       __syncthreads();
 #pragma unroll

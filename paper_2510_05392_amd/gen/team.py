@@ -50,8 +50,8 @@ def team_window(n):
     at a few per cent of lane use."""
     return 4096 if n >= 6 else None
 NONE = 0xFFFF
-SLOT = 9        # doubles between object slots in the LDS frame (must match me_team.h)
 MSTRIDE = 5     # doubles between momentum-table entries (must match me_team.h)
+LDS_BYTES = 160 * 1024   # LDS of one compute unit
 
 
 def slot_particle(slot):
@@ -389,14 +389,21 @@ def emit(name, plan, T=None):
     npar = prog.npar
     nmom = len(prog.moms)
     nloc = (ncol + T - 1) // T
-    # frame layout (doubles): slots (SLOT = 9 doubles apart, which spreads the
-    # lanes' accesses over the LDS banks) | colour flows | momentum table (5
-    # doubles apart) | external momenta | amplitude buffer
-    joff = prog.nslot * SLOT
-    moff = joff + 2 * ncol
-    poff = moff + nmom * MSTRIDE
-    aoff = poff + npar * 4
-    frame = aoff + T * 8
+    # frame layout (doubles): slots SLOT doubles apart | colour flows | momentum
+    # table (MSTRIDE doubles apart) | external momenta | amplitude buffer.  SLOT is
+    # 9 (an odd number of 8-byte words spreads the lanes over the LDS banks),
+    # or 8 when that lets one more workgroup fit in a compute unit's LDS.
+    def layout(slot):
+        joff = prog.nslot * slot
+        moff = joff + 2 * ncol
+        poff = moff + nmom * MSTRIDE
+        aoff = poff + npar * 4
+        return joff, moff, poff, aoff, aoff + T * 8
+
+    teams = 64 // T
+    per_cu = {sl: LDS_BYTES // (teams * 8 * layout(sl)[4]) for sl in (9, 8)}
+    slot = 8 if per_cu[8] > per_cu[9] else 9
+    joff, moff, poff, aoff, frame = layout(slot)
     words = []
     for r in steps:
         words += [CLASS_ID[r['cls']] | (r['n'] << 8), r['row']]
@@ -423,7 +430,8 @@ def emit(name, plan, T=None):
     L.append(f"static __device__ const int32_t TEAMCF_{name}[{ncol * ncol}] = {{{flat}}};")
     L.append(f"struct {name}_team {{")
     L.append(f'  static constexpr const char* NAME = "{name}";')
-    for k, v in (('T', T), ('NPAR', npar), ('NCOL', ncol), ('NLOC', nloc), ('NMOM', nmom), ('JOFF', joff),
+    for k, v in (('T', T), ('SLOT', slot), ('NPAR', npar), ('NCOL', ncol), ('NLOC', nloc), ('NMOM', nmom),
+                 ('JOFF', joff),
                  ('MOFF', moff), ('POFF', poff), ('AOFF', aoff), ('FRAME', frame), ('NPROGW', len(words)),
                  ('NEXT', len(prog.ext)), ('RMAX', fmaxw)):
         L.append(f"  static constexpr int {k} = {v};")
@@ -437,7 +445,7 @@ def emit(name, plan, T=None):
     L.append("    switch (t) {")
     for i, (key, kind, q, outgoing) in enumerate(prog.ext):
         kid = {'U': 0, 'V': 1, 'G': 2}[kind]
-        L.append(f"      case {i}: team_external<{kid}, {q}, {outgoing}, NPAR>(F, POFF, {prog.slot[key]}, hel, mt); "
+        L.append(f"      case {i}: team_external<{kid}, {q}, {outgoing}, NPAR, SLOT>(F, POFF, {prog.slot[key]}, hel, mt); "
                  "break;")
     L.append("      default: break;")
     L.append("    }")

@@ -61,7 +61,7 @@ extern "C" void harness_team_eval(const double* mom, int nevt, double g, double 
         unsigned o[8];
         for (int t = 0; t < n; ++t) {
           team_row(X::ops(), prog[w + 1] + t, o);
-          team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, g, mt);
+          team_dispatch(cls, F, X::MOFF, X::AOFF, o, t, g, mt, X::SLOT);
         }
         if (cls == TC_AMP) {
           const uint32_t foff = prog[w + 2], nr = prog[w + 3];
