@@ -23,11 +23,12 @@ sys.path.insert(0, HERE)
 FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/clk (FMA = 2)
 
 # HBM bytes per launch of the FP64 diagram kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
-# scaled by the same counters on a plain 2 GiB copy (x2.0 and x1.0), keyed by the workload and
-# launch configuration (persistent, waves/SIMD, helicities/item, target waves, executor); the
-# numbers and the commands are in the named profile and hold only for the kernel they were taken on.
+# scaled by the same counters on a plain 2 GiB copy (x2.0 and x1.0), keyed by the workload and the
+# launch configuration that fixes the work items (persistent, helicities/item, executor; the
+# persistent grid's size does not change what an item reads and writes); the numbers and the
+# commands are in the named profile and hold only for the kernel they were taken on.
 MEASURED_TRAFFIC = {
-    ('gg_ttxggg', 262144, (1, 1, 1, 4096, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
+    ('gg_ttxggg', 262144, (1, 1, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
@@ -210,8 +211,7 @@ def main():
 
     traffic = None
     if tuned:
-        key = (process, nevt, tuple(tuned[k] for k in ('persistent', 'waves_per_simd', 'hel_per_item',
-                                                          'target_waves', 'executor')))
+        key = (process, nevt, tuple(tuned[k] for k in ('persistent', 'hel_per_item', 'executor')))
         traffic = MEASURED_TRAFFIC.get(key)
     f_unit = flops.per_event_helicity(process)
     step_flops = f_unit * nhel * nevt

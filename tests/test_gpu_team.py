@@ -95,9 +95,11 @@ def test_team_full_size_ggttggg_sampled(binding):
 def test_team_only_process_ggttgggg(binding):
     # g g -> t tbar g g g g (15495 diagrams, 720 colour flows) has only the team
     # program; the stored oracle values cover 24 events of its 32768-event workload
-    _say('case team ggttgggg golden 24 events')
+    _say('case team ggttgggg full size 32768, 24 sampled events against the oracle')
     g = _golden('gg_ttxgggg_seed1005_n32768_sampled.npz')
-    mom = g['momenta']
+    full = rambo.generate(8, 32768, 1005)
+    idx = g['index']
+    assert np.array_equal(full[idx], g['momenta'])
     m = binding.MatrixElement('gg_ttxgggg')
     assert m.ncolor == 720 and m.ndiag == 15495
     with pytest.raises(binding.MeError):
@@ -106,8 +108,9 @@ def test_team_only_process_ggttgggg(binding):
         m.me_set_colorsum_mode(binding.ME_CS_FP16X2)
     with pytest.raises(binding.MeError):
         binding.MatrixElement('gg_ttxgggg', colorsum_mode=binding.ME_CS_FP16X2)
-    out = m.compute(torch.from_numpy(np.ascontiguousarray(mom)).cuda(), AS)
+    out = m.compute(torch.from_numpy(full).cuda(), AS)
     torch.cuda.synchronize()
     gpu = out.cpu().numpy()
     assert len(m.me_good_helicities()) == 256
-    assert_parity(gpu, mom, 8, me64=g['me'], me_ext=g['me_ext'])
+    assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
+    assert_parity(gpu[idx], full[idx], 8, me64=g['me'], me_ext=g['me_ext'])
