@@ -93,9 +93,9 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del train
-    val = torch.from_numpy(rambo.generate(npar, 32768, 2003)).cuda()
+    val = torch.from_numpy(rambo.generate(npar, min(32768, args.sur_cal), 2003)).cuda()
     err = pipe.log_error(val)
-    calm, calw = rambo.generate(npar, 65536, 2005, return_weights=True)
+    calm, calw = rambo.generate(npar, args.sur_cal, 2005, return_weights=True)
     dcal, dcw = torch.from_numpy(calm).cuda(), torch.from_numpy(calw).cuda()
     what_max, x_max = pipe.calibrate(dcal, dcw, quantile=0.99)
     w_max = float(torch.quantile(pipe.exact(dcal) * dcw, 0.99))
@@ -117,7 +117,8 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo):
             'unweighting_efficiency': two['accepted'] / nevt,
             'one_stage_efficiency': one['accepted'] / nevt,
             'rms_log_error': float(np.sqrt(np.mean(err ** 2))), 'train_events': args.sur_train,
-            'maxima': '0.99 quantiles of a 65536-event calibration sample (events above: residual weights > 1)',
+            'maxima': f'0.99 quantiles of a {args.sur_cal}-event calibration sample '
+                      '(events above: residual weights > 1)',
             'train_epochs': args.sur_epochs, 'train_seconds': t_train, 'final_mse': hist[-1],
             'stated_err': 'exact path split FP16 <= 1e-5 relative per event; unweighted sample unbiased'}
 
@@ -142,6 +143,7 @@ def main():
                     help='also measure mixed precision + surrogate two-stage unweighting')
     ap.add_argument('--sur-train', type=int, default=131072)
     ap.add_argument('--sur-epochs', type=int, default=12)
+    ap.add_argument('--sur-cal', type=int, default=65536, help='calibration events for the maxima')
     ap.add_argument('--cpu-budget', type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:

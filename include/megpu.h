@@ -46,18 +46,22 @@ extern "C" {
 /* colour-sum arithmetic */
 #define ME_CS_FP64 0    /* FP64 triangular quadratic form on the vector ALUs, fused with the diagrams */
 #define ME_CS_FP16X2 1  /* matrix cores: amplitudes split hi + lo in FP16 (rows scaled by a power
-                           of two), integer colour matrix exact in FP16, FP32 accumulation,
+                           of two), integer colour matrix exact in FP16 (entries with more than
+                           11 significant bits split in two exact parts), FP32 accumulation,
                            final row dot products in FP64 */
-#define ME_CS_BF16X2 2  /* as ME_CS_FP16X2 in BF16 (no scaling; a colour matrix with more than 8
-                           significant bits is split hi + lo as well) */
+#define ME_CS_BF16X2 2  /* as ME_CS_FP16X2 in BF16 (no scaling; entries with more than 8
+                           significant bits are split the same way) */
 
-/* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 /* Executors of the FP64 path (me_set_executor) */
 #define ME_EXEC_LANE 0  /* one lane per (event, helicity): generated straight-line code, registers */
-#define ME_EXEC_TEAM 1  /* one team of 32 lanes per (event, helicity): generated step program,
-                           currents staged in LDS (the matrix-core colour-sum modes always use
-                           ME_EXEC_LANE for their diagram kernel) */
+#define ME_EXEC_TEAM 1  /* one team of 32 or 64 lanes per (event, helicity): generated step
+                           program, currents staged in LDS.  The matrix-core colour-sum modes use
+                           the one-lane diagram kernel when the process has one (all but
+                           gg_ttxgggg), else the team program.  gg_ttxgggg has only the team
+                           program: ME_EXEC_LANE, me_select and me_compute_batch return ME_EINVAL
+                           for it. */
 
+/* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 
 typedef struct me_ctx* me_handle;
@@ -73,9 +77,11 @@ typedef struct {
 /* Fill *p with the defaults. */
 int me_params_default(me_params* p);
 
-/* Create a handle for `process`; p may be NULL for the defaults.  Allocates
- * small device tables; the helicity filter runs on the first me_compute call
- * unless me_filter_helicities was called first. */
+/* Create a handle for `process` ("gg_ttx", "gg_ttxg", "gg_ttxgg", "gg_ttxggg",
+ * "gg_ttxgggg": g g -> t tbar + 0..4 gluons); p may be NULL for the defaults.
+ * Allocates small device tables; the helicity filter runs on the first
+ * me_compute call unless me_filter_helicities was called first.  Unknown
+ * process or mode: ME_EINVAL. */
 int me_init(const char* process, const me_params* p, me_handle* out);
 
 /* out_me2[i] = helicity- and colour-summed, initial-state averaged |M|^2 of

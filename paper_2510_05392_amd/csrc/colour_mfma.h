@@ -8,7 +8,8 @@
 // real parts, then the imaginary parts) as the N = 32 dimension; the colour index
 // is both M (blocks of 32) and K (steps of 16).  The integer colour matrix is the
 // A operand (zero padded); it is exact in the input format (FP16 holds 11
-// significant bits, BF16 8: a BF16 matrix that needs more is split into hi + lo).
+// significant bits, BF16 8: a matrix that needs more is split into hi + lo, both
+// exact, and applied twice).
 // FP16 rows are first scaled by an exact power of two so that max |X| is in
 // [1, 2); the scale is undone on the FP64 result.
 //
@@ -91,6 +92,41 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
     }
   }
 
+  double s = 0.0;
+  if constexpr (MB > 8) {
+    // many colour flows: one M block of accumulators at a time (the row is re-read
+    // from cache for every block instead of keeping MB x 16 accumulators live)
+    for (int mb = 0; mb < MB; ++mb) {
+      f32x16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      for (int kk = 0; kk < KS; ++kk) {
+        vec bh, bl;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int c = 16 * kk + 8 * half + t;
+          const double v = (c < NCOL && valid) ? x[2 * c] * scale : 0.0;
+          const elem hi = (elem)v;
+          bh[t] = hi;
+          bl[t] = (elem)(v - (double)hi);
+        }
+        const int idx = ((32 * mb + j) * KP + 16 * kk + 8 * half) / 8;
+        const vec a = cf_hi[idx];
+        acc = T::mfma(a, bh, acc);
+        acc = T::mfma(a, bl, acc);
+        if (cf_lo) {
+          const vec a2 = cf_lo[idx];
+          acc = T::mfma(a2, bh, acc);
+          acc = T::mfma(a2, bl, acc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
+        if (i < NCOL && valid) s += x[2 * i] * (double)acc[v];
+      }
+    }
+  } else {
   f32x16 acc[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -123,7 +159,6 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
   }
 
   // row dot products in FP64: sum_i X[j][i] D[i][j]
-  double s = 0.0;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -131,6 +166,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
       const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
       if (i < NCOL && valid) s += x[2 * i] * (double)acc[mb][v];
     }
+  }
   s += __shfl_xor(s, 32);   // the two halves of the M rows
   s += __shfl_xor(s, 16);   // real + imaginary parts
   if (l < 16 && valid) out[row] = s * unscale * inv_den;

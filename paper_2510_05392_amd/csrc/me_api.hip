@@ -250,12 +250,12 @@ bool bf16_bits(int v, uint16_t* out) {
   return true;
 }
 
-// value of the top 8 significant bits of v (so that v - hi has the rest)
-int bf16_high_part(int v) {
+// value of the top `bits` significant bits of v (so that v - hi has the rest)
+int high_part(int v, int bits) {
   unsigned a = (unsigned)(v < 0 ? -v : v);
   if (a == 0) return 0;
   const int e = 31 - __builtin_clz(a);
-  if (e >= 8) a &= ~((1u << (e - 7)) - 1);
+  if (e >= bits) a &= ~((1u << (e - bits + 1)) - 1);
   return v < 0 ? -(int)a : (int)a;
 }
 
@@ -277,10 +277,15 @@ int build_tables(me_ctx* c, int mode) {
     for (int k = 0; k < n; ++k) {
       const int v = c->desc->cf_int[i * n + k];
       uint16_t bh = 0, bl = 0;
+      // entries with more significant bits than the format holds (11 for FP16,
+      // 8 for BF16) are split into two exact parts and the matrix is applied twice
       if (mode == ME_CS_FP16X2) {
-        if (!half_bits(v, &bh)) return fail(ME_EINVAL, "colour matrix is not exact in FP16");
+        const int vh = high_part(v, 11);
+        if (!half_bits(vh, &bh) || !half_bits(v - vh, &bl))
+          return fail(ME_EINVAL, "colour matrix is not exact in two FP16 parts");
+        if (v != vh) split = true;
       } else {
-        const int vh = bf16_high_part(v);
+        const int vh = high_part(v, 8);
         if (!bf16_bits(vh, &bh) || !bf16_bits(v - vh, &bl))
           return fail(ME_EINVAL, "colour matrix is not exact in two BF16 parts");
         if (v != vh) split = true;
@@ -334,8 +339,6 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   if (p) prm = *p;
   if (!(prm.mt > 0.0)) return fail(ME_EINVAL, "mt must be positive");
   if (!valid_mode(prm.colorsum_mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
-  if (!desc->launch && prm.colorsum_mode != ME_CS_FP64)
-    return fail(ME_EINVAL, std::string(process) + " has only the team executor (ME_CS_FP64)");
   me_ctx* c = new (std::nothrow) me_ctx;
   if (!c) return fail(ME_ENOMEM, "host allocation failed");
   c->desc = desc;
@@ -470,13 +473,12 @@ int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   if (nevt < 0 || nh < 0 || nh > h->desc->nhel) return fail(ME_EINVAL, "bad sizes");
   if (nevt == 0 || nh == 0) return ME_OK;
   if (!momenta || !hels || !out) return fail(ME_EINVAL, "null pointer");
-  if (!h->desc->launch) return fail(ME_EINVAL, "dual amplitudes need the one-lane executor of the process");
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
   me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, nullptr,
                    out, s};
-  hipError_t e = h->desc->launch(a);
+  hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
   if (e != hipSuccess) return hip_fail(e, "jamp kernel launch");
   return ME_OK;
 }
@@ -609,7 +611,8 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     me::LaunchArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, 1, nhel,
                      nullptr, h->d_jamps, s};
     a.alphas = alphas ? alphas + off : nullptr;
-    hipError_t e = h->desc->launch(a);
+    // the diagram kernel of the process: one-lane code, else the team program
+    hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
     if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
     me::ColourArgs ca{h->d_jamps, n * nhel, fmt, h->d_cf_hi, h->d_cf_lo,
                       1.0 / h->desc->cf_den, h->d_partial, s};
@@ -920,8 +923,6 @@ int me_set_colorsum_mode(me_handle h, int mode) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!valid_mode(mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
-  if (!h->desc->launch && mode != ME_CS_FP64)
-    return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor (ME_CS_FP64)");
   rc = build_tables(h, mode);
   if (rc) return rc;
   h->params.colorsum_mode = mode;

@@ -184,15 +184,13 @@ hipError_t launch_colour(const ColourArgs& a) {
   return hipGetLastError();
 }
 
-// Processes without the one-lane code (P::LANE false) have only the team executor.
+// Processes without the one-lane code (P::LANE false) have only the team executor
+// (which also feeds the matrix-core colour sum).
 template <class P>
 const ProcessDesc* describe() {
   Launcher lane = nullptr;
-  ColourLauncher colour = nullptr;
-  if constexpr (P::LANE) {
-    lane = &launch<P>;
-    colour = &launch_colour<P>;
-  }
+  ColourLauncher colour = &launch_colour<P>;
+  if constexpr (P::LANE) lane = &launch<P>;
   static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,     P::NHEL, P::IDEN,
                                 P::CF_DEN, P::NDIAG, P::cf_int(), lane,    colour,
                                 &launch_team<typename P::Team>, 64 / P::Team::T};

@@ -248,14 +248,17 @@ namespace me {
 
 // Kernel: a workgroup is one wavefront holding 64 / T teams; team r of block
 // (x, y) evaluates event x * (64 / T) + r over helicity chunk y and writes
-// its partial sum sum_h sum_ij CF_int Re(conj(J_i) J_j) to partial[y][e].
+// its partial sum sum_h sum_ij CF_int Re(conj(J_i) J_j) to partial[y][e], or,
+// with jamp_out set (one helicity per chunk), the colour flows of (helicity k,
+// event e) to jamp_out[k * nevt + e][NCOL][2] for a matrix-core colour sum.
 // Teams past the last event compute a copy of it and write nothing (every
 // lane must reach every __syncthreads of the block).
 template <class X>
 __global__ void __launch_bounds__(64) team_kernel(const double* __restrict__ mom, int64_t nevt, double g,
                                                   double mt, const int* __restrict__ hels, int nhel,
                                                   int hel_per_chunk, double* __restrict__ partial,
-                                                  const double* __restrict__ alphas) {
+                                                  const double* __restrict__ alphas,
+                                                  double* __restrict__ jamp_out) {
   extern __shared__ double lds[];
   constexpr int TEAMS = 64 / X::T;
   const int team = threadIdx.x / X::T;
@@ -316,13 +319,21 @@ __global__ void __launch_bounds__(64) team_kernel(const double* __restrict__ mom
       for (int q = 0; q < 8; ++q) o[q] = nx[q];
       w += adv;
     }
-    double part = team_colour<X>(F, t);
+    if (jamp_out) {
+      // one helicity per chunk: the flows of (helicity k, event e) go to row k * nevt + e
+      if (valid) {
+        double* dst = jamp_out + ((int64_t)k * nevt + e) * (2 * X::NCOL);
+        for (int i = t; i < 2 * X::NCOL; i += X::T) dst[i] = F[X::JOFF + i];
+      }
+    } else {
+      double part = team_colour<X>(F, t);
 #pragma unroll
-    for (int off = X::T / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    acc += part;
+      for (int off = X::T / 2; off > 0; off >>= 1) part += __shfl_xor(part, off);
+      acc += part;
+    }
     __syncthreads();
   }
-  if (valid && t == 0) partial[(int64_t)blockIdx.y * nevt + e] = acc;
+  if (!jamp_out && valid && t == 0) partial[(int64_t)blockIdx.y * nevt + e] = acc;
 }
 
 template <class X>
@@ -336,7 +347,7 @@ hipError_t launch_team(const LaunchArgs& a) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(team_kernel<X>, dim3(nb, (unsigned)a.nchunk), dim3(64), bytes, a.stream, a.mom, a.nevt,
-                     a.g, a.mt, a.hels, a.nhel, a.hel_per_chunk, a.out, a.alphas);
+                     a.g, a.mt, a.hels, a.nhel, a.hel_per_chunk, a.out, a.alphas, a.jamp_out);
   return hipGetLastError();
 }
 

@@ -68,3 +68,30 @@ def test_host_only_entry_points(libpath):
     assert lib.me_compute(None, None, 1, 0.118, None, None) == binding.ME_EINVAL
     bogus = ctypes.c_void_p(0x1000)
     assert lib.me_compute(bogus, None, 1, 0.118, None, None) == binding.ME_ESTATE
+
+
+def test_host_validation_of_batch_select_and_executor(libpath):
+    # these entry points check their arguments on the host before any device call
+    from paper_2510_05392_amd import binding
+    lib = ctypes.CDLL(libpath)
+    lib.me_last_error.restype = ctypes.c_char_p
+    vp = ctypes.c_void_p
+    lib.me_compute_batch.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
+    assert lib.me_compute_batch(0, None, None, None, 0.118, None, None) == binding.ME_EINVAL
+    assert lib.me_compute_batch(9, None, None, None, 0.118, None, None) == binding.ME_EINVAL
+    assert lib.me_compute_batch(1, None, None, None, 0.118, None, None) == binding.ME_EINVAL
+    hs = (vp * 1)(0x1000)
+    ms = (vp * 1)(None)
+    ns = (ctypes.c_int64 * 1)(8)
+    os_ = (vp * 1)(None)
+    assert lib.me_compute_batch(1, hs, ms, ns, 0.118, os_, None) == binding.ME_ESTATE
+    assert lib.me_compute_batch(1, hs, ms, ns, -1.0, os_, None) == binding.ME_EINVAL
+    lib.me_select.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+    assert lib.me_select(None, None, 4, 0.118, None, None, None, None, None, None) == binding.ME_EINVAL
+    lib.me_compute_alphas.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    assert lib.me_compute_alphas(vp(0x1000), None, 4, None, None, None) == binding.ME_ESTATE
+    lib.me_set_executor.argtypes = [vp, ctypes.c_int]
+    assert lib.me_set_executor(None, 1) == binding.ME_EINVAL
+    assert lib.me_set_executor(vp(0x1000), 1) == binding.ME_ESTATE
+    lib.me_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    assert lib.me_set_launch(None, 1, 1, 1, 1) == binding.ME_EINVAL

@@ -104,13 +104,47 @@ def test_team_only_process_ggttgggg(binding):
     assert m.ncolor == 720 and m.ndiag == 15495
     with pytest.raises(binding.MeError):
         m.me_set_executor(binding.ME_EXEC_LANE)
-    with pytest.raises(binding.MeError):
-        m.me_set_colorsum_mode(binding.ME_CS_FP16X2)
-    with pytest.raises(binding.MeError):
-        binding.MatrixElement('gg_ttxgggg', colorsum_mode=binding.ME_CS_FP16X2)
     out = m.compute(torch.from_numpy(full).cuda(), AS)
     torch.cuda.synchronize()
     gpu = out.cpu().numpy()
     assert len(m.me_good_helicities()) == 256
     assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
     assert_parity(gpu[idx], full[idx], 8, me64=g['me'], me_ext=g['me_ext'])
+
+
+def test_ggttgggg_mixed_colour_sum(binding):
+    # team program writing the 720 colour flows, split-FP16 colour sum on the
+    # matrix cores (the integer colour matrix, entries up to 32768, is exact in FP16)
+    _say('case ggttgggg split-FP16 colour sum, 24 sampled events')
+    g = _golden('gg_ttxgggg_seed1005_n32768_sampled.npz')
+    mom = g['momenta']
+    m = binding.MatrixElement('gg_ttxgggg', colorsum_mode=binding.ME_CS_FP16X2)
+    out = m.compute(torch.from_numpy(np.ascontiguousarray(mom)).cuda(), AS)
+    torch.cuda.synchronize()
+    rel = np.abs(out.cpu().numpy() / g['me_ext'] - 1)
+    _say(f'  max rel err {rel.max():.3e}')
+    assert rel.max() < 1e-5
+
+
+def test_team_graph_replay_matches_eager(binding):
+    # the captured launch sequence of the team executor, replayed with new
+    # buffer contents and eager work in between, equals eager evaluation
+    _say('case team graph replay gg_ttxgg')
+    mom = rambo.generate(6, 130, 51)
+    mom2 = rambo.generate(6, 130, 52)
+    eager = binding.MatrixElement('gg_ttxgg')
+    eager.me_set_executor(binding.ME_EXEC_TEAM)
+    graph = binding.MatrixElement('gg_ttxgg', use_graph=True)
+    graph.me_set_executor(binding.ME_EXEC_TEAM)
+    d = torch.from_numpy(mom).cuda()
+    out = torch.empty(130, dtype=torch.float64, device='cuda')
+    ref = eager.compute(d, AS).cpu().numpy()
+    ref2 = eager.compute(torch.from_numpy(mom2).cuda(), AS).cpu().numpy()
+    s = torch.cuda.current_stream()
+    for rep in range(4):
+        d.copy_(torch.from_numpy(mom if rep % 2 == 0 else mom2))
+        torch.cuda.synchronize()
+        graph.me_compute(d, 130, AS, out, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref if rep % 2 == 0 else ref2), rep
+        _ = eager.compute(d, AS)
