@@ -123,6 +123,37 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo):
             'stated_err': 'exact path split FP16 <= 1e-5 relative per event; unweighted sample unbiased'}
 
 
+def batch_leg(args, binding, rambo):
+    """Uneven multi-process batch (8192 gg->ttg + 65536 gg->ttgg + 16384 gg->ttggg) in one
+    persistent launch, against the three processes' own me_compute calls in sequence."""
+    import torch
+    names = ['gg_ttxg', 'gg_ttxgg', 'gg_ttxggg']
+    sizes = [8192, 65536, 16384]
+    moms = [torch.from_numpy(rambo.generate(NPAR[n], k, SEED[n])).cuda() for n, k in zip(names, sizes)]
+    outs = [torch.empty(k, dtype=torch.float64, device='cuda') for k in sizes]
+    hs = [binding.MatrixElement(n) for n in names]
+    single = [binding.MatrixElement(n) for n in names]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps
+
+    t_batch = timed(lambda: binding.me_compute_batch(hs, moms, sizes, args.alpha_s, outs, stream))
+    t_seq = timed(lambda: [m.me_compute(d, k, args.alpha_s, o, stream)
+                           for m, d, k, o in zip(single, moms, sizes, outs)])
+    n = sum(sizes)
+    return {'segments': dict(zip(names, sizes)), 'ms_one_launch': t_batch, 'ms_three_launches': t_seq,
+            'value': n / (t_batch * 1e-3), 'unit': 'ME evals/s (all segments)'}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -145,6 +176,8 @@ def main():
     ap.add_argument('--sur-epochs', type=int, default=12)
     ap.add_argument('--sur-cal', type=int, default=65536, help='calibration events for the maxima')
     ap.add_argument('--cpu-budget', type=float, default=20.0)
+    ap.add_argument('--batch', action='store_true',
+                    help='also time the uneven multi-process batch in one persistent launch')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py runs on one GPU only (got --gpus {args.gpus}): events are independent, '
@@ -239,6 +272,9 @@ def main():
         line['mixed'] = mixed
     if args.surrogate:
         line['surrogate'] = surrogate_leg(args, process, nevt, mom, dmom, binding, rambo)
+    if args.batch:
+        print('# bench uneven batch', file=sys.stderr, flush=True)
+        line['uneven_batch'] = batch_leg(args, binding, rambo)
     if not args.no_cpu_baseline:
         print('# bench cpu baseline (oracle)', file=sys.stderr, flush=True)
         line['cpu_baseline'] = cpu_baseline(process, mom, args.alpha_s, args.cpu_budget)

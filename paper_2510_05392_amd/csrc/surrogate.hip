@@ -149,13 +149,24 @@ __global__ void silu_back_kernel(const float* __restrict__ dh, const float* __re
 }
 
 // db[j] = sum_b dZ[b][j], fixed order
-__global__ void bias_grad_kernel(const float* __restrict__ dz, int64_t nb, int64_t ld, int n,
-                                 float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// db[j] = sum_b dz[b][j]: a workgroup of 64 x 16 threads per 64 columns; thread
+// (x, y) sums rows y, y + 16, ... of column x (coalesced across x), then the 16
+// partial sums of a column are added in a fixed order (deterministic).
+__global__ void __launch_bounds__(1024) bias_grad_kernel(const float* __restrict__ dz, int64_t nb, int64_t ld,
+                                                         int n, float* __restrict__ db) {
+  __shared__ float part[16][64];
+  const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + x;
   float s = 0.0f;
-  for (int64_t b = 0; b < nb; ++b) s += dz[b * ld + j];
-  db[j] = s;
+  if (j < n)
+    for (int64_t b = y; b < nb; b += 16) s += dz[b * ld + j];
+  part[y][x] = s;
+  __syncthreads();
+  if (y == 0 && j < n) {
+    float t = 0.0f;
+    for (int k = 0; k < 16; ++k) t += part[k][x];
+    db[j] = t;
+  }
 }
 
 __global__ void sum_kernel(const float* __restrict__ x, int n, float* __restrict__ out) {
@@ -601,8 +612,8 @@ int me_sur_grads(me_surrogate s, const uint16_t* feat, const float* target, int6
     e = gemm(s->dzh, 1, ld, s->h[l], s->kin[l], 1, s->out[l], s->in[l], nb, nullptr, s->gw[l], s->in[l],
              nullptr, 0, false, st);
     if (e != hipSuccess) return shipfail(e, "weight-gradient gemm");
-    hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)((s->out[l] + 63) / 64)), dim3(64), 0, st, s->dzf, nb,
-                       ld, s->out[l], s->gb[l]);
+    hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)((s->out[l] + 63) / 64)), dim3(1024), 0, st, s->dzf,
+                       nb, ld, s->out[l], s->gb[l]);
     if (l == 0) break;
     // dH[b][i] = sum_o dZ[b][o] W[o][i], then dZ_{l-1} = dH * silu'(Z_{l-1})
     const int64_t ldn = s->outp[l - 1];
