@@ -265,8 +265,10 @@ def main():
                      'traffic': traffic[0] if traffic else None,
                      'traffic_source': traffic[1] if traffic else None,
                      'flops_per_event_helicity': f_unit,
-                     'kernel': (f'team_kernel<{process}_team>' if tuned and tuned.get('executor') == 1
-                                else f'me_kernel<{process}>') + ' (+ reduce_chunks_kernel, <0.1%)'},
+                     'kernel': {1: f'team_kernel<{process}_team>',
+                                2: f'sums_kernel<{process}> + assemble_kernel<{process}>'}.get(
+                                    (tuned or {}).get('executor', 0), f'me_kernel<{process}>')
+                               + ' (+ reduce_chunks_kernel, <0.1%)'},
     }
     if mixed is not None:
         line['mixed'] = mixed

@@ -61,8 +61,16 @@ extern "C" {
                            program: ME_EXEC_LANE, me_select and me_compute_batch return ME_EINVAL
                            for it. */
 
+#define ME_EXEC_SPLIT 2 /* two kernels per event chunk: one lane per (event, helicity) stores the
+                           sums of its colour groups (no colour flows kept in registers), then
+                           one lane per (event, helicity) forms the flows from them and the FP64
+                           colour form; the group sums of a chunk use at most
+                           ME_SPLIT_SCRATCH_BYTES of library-owned device memory */
+
 /* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
+/* device scratch of the split executor's colour-group sums */
+#define ME_SPLIT_SCRATCH_BYTES (8ull << 30)
 
 typedef struct me_ctx* me_handle;
 
@@ -154,8 +162,8 @@ int me_set_colorsum_mode(me_handle h, int mode);
  * the configuration beyond rounding order of the helicity sum. */
 int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves);
 
-/* Executor of the FP64 colour-sum mode (ME_EXEC_LANE or ME_EXEC_TEAM); both give
- * the same |M|^2 up to rounding order.  The team executor uses the helicity
+/* Executor of the FP64 colour-sum mode (ME_EXEC_LANE, ME_EXEC_TEAM or
+ * ME_EXEC_SPLIT); all give the same |M|^2 up to rounding order.  The team executor uses the helicity
  * chunking of the grid path (target_waves of me_set_launch). */
 int me_set_executor(me_handle h, int executor);
 

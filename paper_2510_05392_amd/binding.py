@@ -24,6 +24,7 @@ ME_CS_FP16X2 = 1
 ME_CS_BF16X2 = 2
 ME_EXEC_LANE = 0
 ME_EXEC_TEAM = 1
+ME_EXEC_SPLIT = 2
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',

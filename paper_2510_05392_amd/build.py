@@ -53,9 +53,26 @@ def generate_sources(procs, build_dir):
         src, _, _ = codegen.generate(name)
         inc = os.path.join(GEN, f'{name}.inc')
         _write_if_changed(inc, src)
-        unit = (f'// Kernels and descriptor of process {name} (generated).\n'
-                f'#include "{name}.inc"\n#include "me_kernels.h"\n'
-                f'namespace me {{\nconst ProcessDesc* process_{name}() {{ return describe<me::{name}>(); }}\n}}\n')
+        lane = codegen.PROCESS_NPAR[name] <= codegen.LANE_MAX_NPAR
+        if lane:
+            unit = (f'// Kernels and descriptor of process {name} (generated).\n'
+                    f'#include "{name}.inc"\n#include "me_kernels.h"\n'
+                    f'namespace me {{\nhipError_t split_{name}(const SplitArgs& a);\n'
+                    f'const ProcessDesc* process_{name}() {{ return describe<me::{name}>(&split_{name}); }}\n}}\n')
+            # the split executor's kernels compile in parallel in a unit of their own
+            split = (f'// Split-executor kernels of process {name} (generated).\n'
+                     f'#include "{name}.inc"\n#include "me_kernels.h"\n'
+                     f'namespace me {{\nhipError_t split_{name}(const SplitArgs& a) '
+                     f'{{ return launch_split<me::{name}>(a); }}\n}}\n')
+            spath = os.path.join(GEN, f'split_{name}.hip')
+            _write_if_changed(spath, split)
+            units.append((spath, os.path.join(OBJ, f'split_{name}.o'),
+                          [inc] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
+        else:
+            unit = (f'// Kernels and descriptor of process {name} (generated).\n'
+                    f'#include "{name}.inc"\n#include "me_kernels.h"\n'
+                    f'namespace me {{\nconst ProcessDesc* process_{name}() '
+                    f'{{ return describe<me::{name}>(nullptr); }}\n}}\n')
         path = os.path.join(GEN, f'proc_{name}.hip')
         _write_if_changed(path, unit)
         units.append((path, os.path.join(OBJ, f'proc_{name}.o'),
@@ -124,7 +141,7 @@ def build(procs=None, jobs=None, verbose=True, lib=LIB, force=False):
     os.makedirs(OBJ, exist_ok=True)
     units = generate_sources(procs, build_dir)
     # the largest units first: the batch kernel and the process with most diagrams
-    units.sort(key=lambda u: (not u[0].endswith('batch.hip'), -len(os.path.basename(u[0]))))
+    units.sort(key=lambda u: (not u[0].endswith('batch.hip'), 'ggg' not in u[0], -len(os.path.basename(u[0]))))
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

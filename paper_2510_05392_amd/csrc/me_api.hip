@@ -117,6 +117,8 @@ struct me_ctx {
   size_t partial_cap = 0;     // doubles
   double* d_jamps = nullptr;  // staged dual amplitudes (matrix-core colour-sum modes)
   size_t jamps_cap = 0;       // doubles
+  double* d_sums = nullptr;   // colour-group sums of the split executor
+  size_t sums_cap = 0;        // doubles
   void* d_cf_hi = nullptr;    // colour matrix in the MFMA input format
   void* d_cf_lo = nullptr;    // its low half when the matrix is split (BF16)
   bool filtered = false;
@@ -204,6 +206,21 @@ int ensure_jamps(me_ctx* c, size_t n) {
   if (n <= c->jamps_cap) return ME_OK;
   drop_graph(c);
   return ensure_buffer(&c->d_jamps, &c->jamps_cap, n, "jamps");
+}
+
+int ensure_sums(me_ctx* c, size_t n) {
+  if (n <= c->sums_cap) return ME_OK;
+  drop_graph(c);
+  return ensure_buffer(&c->d_sums, &c->sums_cap, n, "group sums");
+}
+
+// Events per chunk of the split executor: the group sums of a chunk (2 NGROUP
+// doubles per row, nhel rows per event) fill at most ME_SPLIT_SCRATCH_BYTES.
+int64_t split_chunk(const me_ctx* h, int64_t nevt) {
+  const size_t per_event = sizeof(double) * 2 * (size_t)h->desc->ngroup * h->good.size();
+  int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
+  chunk = std::max<int64_t>(64, (chunk / 64) * 64);
+  return std::min<int64_t>(chunk, nevt);
 }
 
 int ensure_buffer(double** buf, size_t* cap, size_t n, const char* what) {
@@ -398,6 +415,7 @@ int me_finalize(me_handle h) {
   hipError_t e2 = hipFree(h->d_scratch_hels);
   hipError_t e3 = h->d_partial ? hipFree(h->d_partial) : hipSuccess;
   if (h->d_jamps) (void)hipFree(h->d_jamps);
+  if (h->d_sums) (void)hipFree(h->d_sums);
   if (h->d_counter) (void)hipFree(h->d_counter);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
@@ -526,6 +544,12 @@ namespace {
 // Size the scratch of one me_compute call (outside any capture).
 int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
+  if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_SPLIT) {
+    const int64_t chunk = split_chunk(h, nevt);
+    int rc = ensure_sums(h, (size_t)chunk * nhel * 2 * h->desc->ngroup);
+    if (rc) return rc;
+    return ensure_partial(h, (size_t)chunk * nhel);
+  }
   if (h->params.colorsum_mode == ME_CS_FP64) {
     size_t rows;
     if (h->persistent && h->executor == ME_EXEC_LANE) {
@@ -550,6 +574,25 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
             hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
+  if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_SPLIT) {
+    // event chunks: group sums of every (helicity, event) row, then flows and the
+    // colour form per row, then the fixed-order helicity sum of the chunk
+    const int64_t chunk = split_chunk(h, nevt);
+    const int npar = h->desc->npar;
+    const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    for (int64_t off = 0; off < nevt; off += chunk) {
+      const int64_t n = std::min<int64_t>(chunk, nevt - off);
+      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, h->d_partial,
+                      alphas ? alphas + off : nullptr, s};
+      hipError_t e = h->desc->split(a);
+      if (e != hipSuccess) return hip_fail(e, "split kernels launch");
+      hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                         h->d_partial, nhel, n, scale, out_me2 + off);
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    }
+    return ME_OK;
+  }
   if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_TEAM) {
     // one workgroup (one wavefront) per 64 / T events; helicity chunks fill the grid
     const int64_t per = h->desc->team_events_per_block;
@@ -851,8 +894,10 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   if (h->desc->launch)
     cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0}, {1, 1, 0, 0, 0},
              {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},    {1, 1, 1, 0, 0},     {1, 2, 1, 0, 0}};
-  if (h->params.colorsum_mode == ME_CS_FP64)
+  if (h->params.colorsum_mode == ME_CS_FP64) {
     for (int tw : {1024, 262144, 1048576}) cands.push_back({0, 1, 0, tw, 1});
+    if (h->desc->split) cands.push_back({0, 1, 0, 4096, ME_EXEC_SPLIT});
+  }
   const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
             save_tw = h->target_waves, save_graph = h->params.use_graph, save_x = h->executor;
   h->params.use_graph = 0;
@@ -911,8 +956,9 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
 int me_set_executor(me_handle h, int executor) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM) return fail(ME_EINVAL, "unknown executor");
-  if (executor == ME_EXEC_LANE && !h->desc->launch)
+  if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM && executor != ME_EXEC_SPLIT)
+    return fail(ME_EINVAL, "unknown executor");
+  if ((executor == ME_EXEC_LANE && !h->desc->launch) || (executor == ME_EXEC_SPLIT && !h->desc->split))
     return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor");
   h->executor = executor;
   drop_graph(h);

@@ -184,16 +184,66 @@ hipError_t launch_colour(const ColourArgs& a) {
   return hipGetLastError();
 }
 
-// Processes without the one-lane code (P::LANE false) have only the team executor
-// (which also feeds the matrix-core colour sum).
+// Split executor.  sums_kernel: one lane per row (event e, helicity k) of the
+// chunk stores the colour-group sums of its diagrams (no colour flows are kept
+// live, which is what makes the diagram code fit the register file far
+// better); assemble_kernel: one lane per row forms the flows from the group
+// sums and the FP64 colour form.
 template <class P>
-const ProcessDesc* describe() {
+__global__ void __launch_bounds__(64) sums_kernel(const double* __restrict__ mom, int64_t n, double g, double mt,
+                                                  const int* __restrict__ hels, int nhel, double* __restrict__ sums,
+                                                  const double* __restrict__ alphas) {
+  const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (e >= n) return;
+  double p[P::NPAR][4];
+  load_momenta<P>(mom, e, p);
+  if (alphas) g = sqrt(4.0 * 3.14159265358979323846 * alphas[e]);
+  int lam[P::NPAR];
+  helicity_signs<P>(hels[k], lam);
+  const int64_t rows = n * nhel;
+  P::group_sums(p, lam, g, mt, sums + (int64_t)k * n + e, rows);
+}
+
+template <class P>
+__global__ void __launch_bounds__(64) assemble_kernel(const double* __restrict__ sums, int64_t rows,
+                                                      double* __restrict__ partial) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= rows) return;
+  cx jamp[P::NCOL];
+#pragma unroll
+  for (int i = 0; i < P::NCOL; ++i) jamp[i] = cx{0.0, 0.0};
+  P::flows_from_sums(sums + r, rows, jamp);
+  partial[r] = P::colour_sum(jamp);
+}
+
+template <class P>
+hipError_t launch_split(const SplitArgs& a) {
+  const int64_t rows = a.n * a.nhel;
+  hipLaunchKernelGGL(sums_kernel<P>, dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0, a.stream,
+                     a.mom, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(assemble_kernel<P>, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, a.stream, a.sums, rows,
+                     a.partial);
+  return hipGetLastError();
+}
+
+// Processes without the one-lane code (P::LANE false) have only the team executor
+// (which also feeds the matrix-core colour sum).  The split launcher is compiled in
+// a translation unit of its own and passed in.
+template <class P>
+const ProcessDesc* describe(SplitLauncher split) {
   Launcher lane = nullptr;
   ColourLauncher colour = &launch_colour<P>;
-  if constexpr (P::LANE) lane = &launch<P>;
+  int ngroup = 0;
+  if constexpr (P::LANE) {
+    lane = &launch<P>;
+    ngroup = P::NGROUP;
+  }
   static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,     P::NHEL, P::IDEN,
                                 P::CF_DEN, P::NDIAG, P::cf_int(), lane,    colour,
-                                &launch_team<typename P::Team>, 64 / P::Team::T};
+                                &launch_team<typename P::Team>, 64 / P::Team::T, split, ngroup};
   return &d;
 }
 

@@ -67,6 +67,25 @@ struct BatchArgs {
 
 using BatchLauncher = hipError_t (*)(const BatchArgs&, int waves, hipStream_t);
 
+// Split evaluation of an event chunk (all nhel helicities of n events, rows
+// row = k * n + e): one kernel stores the colour-group sums of every row to
+// sums[2 NGROUP][rows], a second forms the colour flows from them and the
+// colour sum sum_ij CF_int Re(conj(J_i) J_j) into partial[rows].
+struct SplitArgs {
+  const double* mom;     // device, [n][npar][4] (the chunk's events)
+  int64_t n;
+  double g;
+  double mt;
+  const int* hels;       // device, good helicities
+  int nhel;
+  double* sums;          // device, [2 * NGROUP][nhel * n]
+  double* partial;       // device, [nhel][n]
+  const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
+  hipStream_t stream;
+};
+
+using SplitLauncher = hipError_t (*)(const SplitArgs&);
+
 struct ProcessDesc {
   const char* name;
   int npar, ncol, nhel, iden, cf_den, ndiag;
@@ -75,6 +94,8 @@ struct ProcessDesc {
   ColourLauncher colour;      // matrix-core colour sum of stored dual amplitudes
   Launcher team;              // team executor: partial colour sums per helicity chunk
   int team_events_per_block;  // events per workgroup of the team executor (64 / lanes per team)
+  SplitLauncher split;        // split executor (group sums, then flows + colour sum), or nullptr
+  int ngroup;                 // colour groups (group sums per row of the split executor)
 };
 
 }  // namespace me

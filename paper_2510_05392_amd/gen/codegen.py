@@ -198,9 +198,12 @@ class Emitter:
             return '-', f"times_i({expr})"
         raise ValueError(c)
 
-    def amplitudes(self):
+    def amplitudes(self, split=False):
         """Pieces sharing one colour vector (up to a unit factor) are summed first,
-        then the sum is added once to each of its colour flows."""
+        then the sum is added once to each of its colour flows.  With split set the
+        sum of group gi is stored to sout[2 gi sstride] (real) and
+        sout[(2 gi + 1) sstride] (imaginary) instead, and the flows are formed by
+        flows_from_sums() in a second kernel."""
         done = set()
 
         def need(key):
@@ -226,11 +229,27 @@ class Emitter:
                     self.lines.append(head + f"{acc} = a; }}")
                 else:
                     self.lines.append(head + f"{acc} = {acc} {sign} {term}; }}")
+            if split:
+                self.lines.append(f"  sout[{2 * gi} * sstride] = {acc}.r; sout[{2 * gi + 1} * sstride] = {acc}.i;")
+                continue
             # distribute the group sum over its colour flows
             for k, rel in key:
                 sign, term = self._scaled(acc, rel * first_lead)
                 self.lines.append(f"  jamp[{k}] = jamp[{k}] {sign} {term};")
         return self.lines
+
+    def flows_from_sums(self):
+        """J_k = sum over groups of (unit coefficient) x group sum, the group sums read
+        from s[2 gi sstride], s[(2 gi + 1) sstride] in the order amplitudes() stores them."""
+        lines = []
+        for gi, (key, members) in enumerate(self.plan.scheduled_groups()):
+            first_lead = members[0][0]
+            lines.append(f"  {{ const cx s{gi}{{s[{2 * gi} * sstride], s[{2 * gi + 1} * sstride]}};")
+            for k, rel in key:
+                sign, term = self._scaled(f"s{gi}", rel * first_lead)
+                lines.append(f"    jamp[{k}] = jamp[{k}] {sign} {term};")
+            lines.append("  }")
+        return lines
 
 
 def colour_sum_code(cf, ncol):
@@ -266,6 +285,9 @@ def generate(name):
     iden = 4 * 64 * math.factorial(npar - 4)
     lane = npar <= LANE_MAX_NPAR
     body = Emitter(name, plan).amplitudes() if lane else []
+    sums = Emitter(name, plan).amplitudes(split=True) if lane else []
+    assemble = Emitter(name, plan).flows_from_sums() if lane else []
+    ngroup = len(plan.scheduled_groups())
     team_src, _ = team_gen.emit(name, plan)
     out = []
     out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
@@ -296,6 +318,16 @@ def generate(name):
         out.append("  }")
         out.append("  static __device__ __forceinline__ double colour_sum(const cx* jamp) {")
         out.extend('  ' + l for l in colour_sum_code(cf, ncol))
+        out.append("  }")
+        out.append("  // split evaluation: colour-group sums of one (event, helicity), stride sstride")
+        out.append(f"  static constexpr int NGROUP = {ngroup};")
+        out.append("  static __device__ __forceinline__ void group_sums(const double (*p)[4], const int* lam, "
+                   "double g, double mt, double* sout, int64_t sstride) {")
+        out.extend('  ' + l for l in sums)
+        out.append("  }")
+        out.append("  static __device__ __forceinline__ void flows_from_sums(const double* s, int64_t sstride, "
+                   "cx* jamp) {")
+        out.extend('  ' + l for l in assemble)
         out.append("  }")
     out.append("};")
     out.append("}  // namespace me")

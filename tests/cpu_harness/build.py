@@ -63,3 +63,15 @@ class Harness:
                                    ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                    ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
         return meh
+
+    def split_eval(self, mom, g, mt, hels):
+        """Per-helicity colour sums from the split evaluation (group sums, then flows)."""
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        meh = np.zeros((len(hels), nevt))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.lib.harness_split_eval(mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
+                                    ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
+        return meh

@@ -30,6 +30,39 @@ void lane_eval(const double* mom, int nevt, double g, double mt, const int* hels
   }
 }
 
+// Split evaluation: group sums of each (event, helicity) row, then the flows
+// from the sums and the colour form, exactly as the two GPU kernels do.
+template <class P>
+void split_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h) {
+  using namespace me;
+  constexpr int NPAR = P::NPAR, NCOL = P::NCOL;
+  static double sums[2 * P::NGROUP];
+  for (int e = 0; e < nevt; ++e) {
+    double p[NPAR][4];
+    for (int q = 0; q < NPAR; ++q)
+      for (int u = 0; u < 4; ++u) p[q][u] = mom[(e * NPAR + q) * 4 + u];
+    for (int k = 0; k < nh; ++k) {
+      int lam[NPAR];
+      for (int q = 0; q < NPAR; ++q) lam[q] = (hels[k] >> (NPAR - 1 - q)) & 1 ? 1 : -1;
+      P::group_sums(p, lam, g, mt, sums, 1);
+      cx jamp[NCOL];
+      for (int c = 0; c < NCOL; ++c) jamp[c] = cx{0.0, 0.0};
+      P::flows_from_sums(sums, 1, jamp);
+      me_h[k * nevt + e] = P::colour_sum(jamp) / P::CF_DEN;
+    }
+  }
+}
+
+template <class P>
+void split_dispatch(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h) {
+  if constexpr (P::LANE) split_eval<P>(mom, nevt, g, mt, hels, nh, me_h);
+}
+
+extern "C" void harness_split_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh,
+                                   double* me_h) {
+  split_dispatch<me::PROC>(mom, nevt, g, mt, hels, nh, me_h);
+}
+
 template <class P>
 void lane_dispatch(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h,
                    double* jamp_out) {

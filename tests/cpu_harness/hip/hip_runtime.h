@@ -4,6 +4,7 @@
 // without a GPU.  Never used by the product library.
 #pragma once
 #include <cmath>
+#include <cstdint>
 #define __device__
 #define __host__
 #define __forceinline__ inline

@@ -132,3 +132,17 @@ def test_team_program_slots_and_schedule():
             rs.sort()
             for (a0, b0), (a1, b1) in zip(rs, rs[1:]):
                 assert a1 > b0, (s, rs)
+
+
+@pytest.mark.parametrize('name,npar,nevt,opt,hels', [
+    ('gg_ttx', 4, 16, '-O1', None), ('gg_ttxg', 5, 8, '-O1', None),
+    ('gg_ttxgg', 6, 4, '-O1', None), ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127))])
+def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels):
+    # colour-group sums stored per row, then the flows formed from them (the two
+    # kernels of the split executor), compiled for the host
+    h = harness.build(name, opt)
+    mom = rambo.generate(npar, nevt, 7)
+    hels = list(range(2 ** npar)) if hels is None else list(hels)
+    meh = h.split_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels)
+    ref = ome.me_helicities(ome.process(npar), mom, AS, hels)
+    assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
