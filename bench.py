@@ -22,13 +22,15 @@ sys.path.insert(0, HERE)
 
 FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/clk (FMA = 2)
 
-# HBM bytes per launch of the FP64 diagram kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
-# scaled by the same counters on a plain 2 GiB copy (x2.0 and x1.0), keyed by the workload and the
-# launch configuration that fixes the work items (persistent, helicities/item, executor; the
-# persistent grid's size does not change what an item reads and writes); the numbers and the
-# commands are in the named profile and hold only for the kernel they were taken on.
+# HBM bytes per launch of the FP64 diagram kernel (averaged over its launches in one call, like
+# the kernel time), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by the same counters on a
+# plain 2 GiB copy (x2.0 and x1.0), keyed by the workload and the launch configuration that fixes
+# the work items (persistent, helicities/item, executor; the persistent grid's size does not change
+# what an item reads and writes); the numbers and the commands are in the named profile and hold
+# only for the kernel they were taken on.
 MEASURED_TRAFFIC = {
     ('gg_ttxggg', 262144, (1, 1, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
+    ('gg_ttxggg', 262144, (0, 0, 2)): (6.999e10, 'profiles/sums_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
@@ -218,24 +220,48 @@ def main():
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
+        # the timed region: eager calls with every kernel bracketed by events on the
+        # stream it runs on (per-kernel durations for the roofline); the same steps
+        # replayed from the captured graph are timed after it
+        timing = mode == binding.ME_CS_FP64
+        if timing:
+            m.me_set_kernel_timing(True)
         print(f'# bench timing {args.steps} steps', file=sys.stderr, flush=True)
         start.record(stream)
         for _ in range(args.steps):
             m.me_compute(dmom, nevt, args.alpha_s, out, stream)
         stop.record(stream)
         torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        ktimes = None
+        if timing:
+            ktimes = m.me_kernel_times()
+            m.me_set_kernel_timing(False)
         res = out.cpu().numpy()
         if not np.all(np.isfinite(res)):
             print('non-finite matrix elements', file=sys.stderr)
             sys.exit(1)
-        return start.elapsed_time(stop) / args.steps, res, len(m.me_good_helicities()), tuned
+        graph_ms = None
+        if timing and not args.no_graph:
+            m.me_compute(dmom, nevt, args.alpha_s, out, stream)   # graph (captured in the warmup) warm
+            torch.cuda.synchronize()
+            start.record(stream)
+            for _ in range(args.steps):
+                m.me_compute(dmom, nevt, args.alpha_s, out, stream)
+            stop.record(stream)
+            torch.cuda.synchronize()
+            graph_ms = start.elapsed_time(stop) / args.steps
+            if not np.array_equal(out.cpu().numpy(), res):
+                print('graph replay differs from eager evaluation', file=sys.stderr)
+                sys.exit(1)
+        return ms, res, len(m.me_good_helicities()), tuned, ktimes, graph_ms
 
-    ms, res, nhel, tuned = run(binding.ME_CS_FP64)
+    ms, res, nhel, tuned, ktimes, graph_ms = run(binding.ME_CS_FP64)
     value = nevt / (ms * 1e-3)
     mixed = None
     if not args.fp64_only:
         try:
-            ms_m, res_m, _, _ = run(binding.ME_CS_FP16X2)
+            ms_m, res_m, _, _, _, _ = run(binding.ME_CS_FP16X2)
             rel = np.abs(res_m / res - 1)
             mixed = {'colorsum': 'split FP16 hi+lo on MFMA, FP32 accumulation, FP64 row dots',
                      'value': nevt / (ms_m * 1e-3), 'unit': 'ME evals/s', 'ms_per_step': ms_m,
@@ -248,9 +274,20 @@ def main():
     if tuned:
         key = (process, nevt, tuple(tuned[k] for k in ('persistent', 'hel_per_item', 'executor')))
         traffic = MEASURED_TRAFFIC.get(key)
-    f_unit = flops.per_event_helicity(process)
-    step_flops = f_unit * nhel * nevt
-    achieved = step_flops / (ms * 1e-3) / 1e12
+    executor = (tuned or {}).get('executor', 0)
+    kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>'}.get(executor,
+                                                                              f'me_kernel<{process}>')
+    # the dominant kernel is the diagram kernel; its algorithmic flops per (event, helicity)
+    f_unit = flops.diagram_kernel(process, executor)
+    tot_ms, launches = ktimes
+    kms = tot_ms[binding.ME_KT_DIAGRAM]
+    achieved = f_unit * nhel * nevt * args.steps / (kms * 1e-3) / 1e12
+    kernels = {name: {'ms_total': tot_ms[k], 'launches': launches[k],
+                      'ms_per_launch': tot_ms[k] / launches[k] if launches[k] else None}
+               for k, name in ((binding.ME_KT_DIAGRAM, kname),
+                               (binding.ME_KT_FLOWS, f'flows_kernel<{process}>'),
+                               (binding.ME_KT_COLOUR, 'colour_f64_kernel'),
+                               (binding.ME_KT_REDUCE, 'reduce_chunks_kernel')) if launches[k]}
     line = {
         'metric': 'ME evals/s', 'value': value, 'unit': 'ME evals/s', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': ms,
@@ -259,16 +296,16 @@ def main():
         'config': {'workload': f'{process} LO |M|^2, FP64 diagrams + FP64 colour sum', 'process': process,
                    'nevt': nevt, 'sqrt_s_GeV': 1500.0, 'mt_GeV': 173.0, 'alpha_s': args.alpha_s,
                    'good_helicities': nhel, 'parallelism': 'single GPU', 'launch': tuned,
-                   'hipgraph': not args.no_graph},
+                   'timed': 'eager calls, kernels bracketed by events',
+                   'graph_replay_ms_per_step': graph_ms},
         'roofline': {'bound': 'alu', 'achieved': achieved, 'peak': FP64_VALU_PEAK_TFLOPS,
                      'unit': 'TFLOP/s', 'frac': achieved / FP64_VALU_PEAK_TFLOPS,
                      'traffic': traffic[0] if traffic else None,
                      'traffic_source': traffic[1] if traffic else None,
-                     'flops_per_event_helicity': f_unit,
-                     'kernel': {1: f'team_kernel<{process}_team>',
-                                2: f'sums_kernel<{process}> + assemble_kernel<{process}>'}.get(
-                                    (tuned or {}).get('executor', 0), f'me_kernel<{process}>')
-                               + ' (+ reduce_chunks_kernel, <0.1%)'},
+                     'kernel': kname, 'flops_per_event_helicity': f_unit,
+                     'kernel_ms_per_launch': kms / launches[binding.ME_KT_DIAGRAM],
+                     'launches': launches[binding.ME_KT_DIAGRAM]},
+        'kernels': kernels,
     }
     if mixed is not None:
         line['mixed'] = mixed

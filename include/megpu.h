@@ -61,15 +61,16 @@ extern "C" {
                            program: ME_EXEC_LANE, me_select and me_compute_batch return ME_EINVAL
                            for it. */
 
-#define ME_EXEC_SPLIT 2 /* two kernels per event chunk: one lane per (event, helicity) stores the
-                           sums of its colour groups (no colour flows kept in registers), then
-                           one lane per (event, helicity) forms the flows from them and the FP64
-                           colour form; the group sums of a chunk use at most
+#define ME_EXEC_SPLIT 2 /* three kernels per event chunk: one lane per (event, helicity) stores the
+                           sums of its colour groups (no colour flows kept in registers); a
+                           workgroup per 64 (event, helicity) rows streams them through LDS into
+                           the colour flows; the FP64 colour form of every row on the matrix
+                           cores.  The group sums and flows of a chunk use at most
                            ME_SPLIT_SCRATCH_BYTES of library-owned device memory */
 
 /* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
-/* device scratch of the split executor's colour-group sums */
+/* device scratch of the split executor's colour-group sums and colour flows */
 #define ME_SPLIT_SCRATCH_BYTES (8ull << 30)
 
 typedef struct me_ctx* me_handle;
@@ -166,6 +167,23 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
  * ME_EXEC_SPLIT); all give the same |M|^2 up to rounding order.  The team executor uses the helicity
  * chunking of the grid path (target_waves of me_set_launch). */
 int me_set_executor(me_handle h, int executor);
+
+/* Per-kernel timing, for measurement.  While on, me_compute runs eagerly (no graph
+ * replay) and brackets every kernel it launches with events on the caller's stream,
+ * classed as ME_KT_DIAGRAM (me_kernel, team_kernel or sums_kernel: the diagrams of
+ * every (event, helicity)), ME_KT_FLOWS (flows_kernel), ME_KT_COLOUR (matrix-core
+ * colour form) and ME_KT_REDUCE (helicity sum).  me_kernel_times waits for the
+ * recorded events and returns, per class, the summed duration in ms and the number
+ * of launches since timing was switched on or last read (host arrays of
+ * ME_KT_KINDS entries), then starts a new count.  me_set_kernel_timing(h, 0) drops
+ * what was recorded. */
+#define ME_KT_DIAGRAM 0
+#define ME_KT_FLOWS 1
+#define ME_KT_COLOUR 2
+#define ME_KT_REDUCE 3
+#define ME_KT_KINDS 4
+int me_set_kernel_timing(me_handle h, int on);
+int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
 
 /* Autotuner: times a fixed set of launch configurations (and, in ME_CS_FP64 mode,
  * both executors) on these events (writing out_me2, synchronising the stream)

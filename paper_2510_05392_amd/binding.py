@@ -25,12 +25,15 @@ ME_CS_BF16X2 = 2
 ME_EXEC_LANE = 0
 ME_EXEC_TEAM = 1
 ME_EXEC_SPLIT = 2
+# per-kernel timing classes (me_kernel_times)
+ME_KT_DIAGRAM, ME_KT_FLOWS, ME_KT_COLOUR, ME_KT_REDUCE = 0, 1, 2, 3
+ME_KT_KINDS = 4
 
 EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
-           'me_compute_alphas', 'me_select', 'me_set_executor',
-           'me_finalize',
+           'me_compute_alphas', 'me_select', 'me_set_executor', 'me_set_kernel_timing',
+           'me_kernel_times', 'me_finalize',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
            'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
@@ -203,6 +206,16 @@ class MatrixElement:
 
     def me_set_executor(self, executor):
         _check(load().me_set_executor(self._h, int(executor)))
+
+    def me_set_kernel_timing(self, on):
+        _check(load().me_set_kernel_timing(self._h, int(bool(on))))
+
+    def me_kernel_times(self):
+        """(total ms, launches) per kernel class since timing was switched on or last read."""
+        ms = (ctypes.c_double * ME_KT_KINDS)()
+        n = (ctypes.c_int64 * ME_KT_KINDS)()
+        _check(load().me_kernel_times(self._h, ms, n))
+        return list(ms), list(n)
 
     def me_set_colorsum_mode(self, mode):
         _check(load().me_set_colorsum_mode(self._h, int(mode)))

@@ -172,4 +172,87 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
   if (l < 16 && valid) out[row] = s * unscale * inv_den;
 }
 
+// FP64 colour form on the matrix cores, for the split executor:
+//     out[row] = sum_ik CF[i][k] (A_i A_k + B_i B_k),   J = A + iB,
+// the integer colour matrix (exact in FP64), not yet divided by its denominator.
+// GEMM D = CF . X^T on v_mfma_f64_16x16x4_f64, X rows = the real and the imaginary
+// parts of 8 (event, helicity) rows per N tile; each wave does COLOUR_F64_TILES
+// tiles so that every CF operand it loads feeds that many products.
+// Layouts (16x16x4, wave64, checked on the device): A[i][k]: i = l % 16, k = l / 16;
+// B[k][j]: j = l % 16, k = l / 16; D[i][j] (accumulator v = 0..3): j = l % 16,
+// i = 4 v + l / 16.
+// jt: [2 NCOL][nrow] (row r: real part of flow c at jt[2c nrow + r], imaginary at
+// jt[(2c + 1) nrow + r]); cf: [16 MB][4 KS] FP64 zero padded, integers of magnitude
+// below 2^24 (exact in FP32: the workgroup keeps its copy in LDS as FP32, rows
+// padded by one entry against bank conflicts).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int COLOUR_F64_TILES = 2;
+constexpr int COLOUR_F64_GRID = 1024;   // workgroups (at most) of colour_f64_kernel
+
+template <int NCOL>
+__global__ void __launch_bounds__(256) colour_f64_kernel(const double* __restrict__ jt, int64_t nrow,
+                                                         const double* __restrict__ cf, double* __restrict__ out) {
+  constexpr int KS = (NCOL + 3) / 4;    // K steps
+  constexpr int KP = 4 * KS;            // padded row length of cf
+  constexpr int MB = (NCOL + 15) / 16;  // M blocks
+  constexpr int NT = COLOUR_F64_TILES;
+  constexpr int KPS = KP + 1;           // LDS row stride
+  __shared__ float cfs[16 * MB * KPS];
+  for (int i = threadIdx.x; i < 16 * MB * KP; i += 256) cfs[(i / KP) * KPS + i % KP] = (float)cf[i];
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  const int j = l & 15;                 // X row in the tile (N index); also A's row i
+  const int kq = l >> 4;                // K index within a step; D row group
+  const int part = j >> 3;              // 0 = real parts, 1 = imaginary parts
+  // the workgroup walks over tiles of 4 x 8 x NT rows, so that the matrix it loaded
+  // into LDS serves many tiles
+  const int64_t ntile = (nrow + 32 * NT - 1) / (32 * NT);
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t wave = tile * 4 + (threadIdx.x >> 6);
+    const double* x[NT];
+    bool valid[NT];
+    int64_t row[NT];
+  #pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      row[t] = (wave * NT + t) * 8 + (j & 7);
+      valid[t] = row[t] < nrow;
+      x[t] = jt + (int64_t)part * nrow + (valid[t] ? row[t] : 0);
+    }
+    f64x4 acc[NT][MB];
+  #pragma unroll
+    for (int t = 0; t < NT; ++t)
+  #pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + kq;
+      double b[NT];
+  #pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = (c < NCOL && valid[t]) ? x[t][(int64_t)(2 * c) * nrow] : 0.0;
+  #pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const double a = (double)cfs[(16 * mb + j) * KPS + c];
+  #pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t][mb], 0, 0, 0);
+      }
+    }
+  #pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      // row dot products sum_i X[j][i] D[i][j], then over the four lane groups and
+      // over the real and imaginary parts of the row
+      double s = 0.0;
+  #pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+  #pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * mb + 4 * v + kq;
+          if (i < NCOL && valid[t]) s += x[t][(int64_t)(2 * i) * nrow] * acc[t][mb][v];
+        }
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      s += __shfl_xor(s, 8);
+      if (l < 8 && valid[t]) out[row[t]] = s;
+    }
+  }
+}
+
 }  // namespace me

@@ -117,8 +117,15 @@ struct me_ctx {
   size_t partial_cap = 0;     // doubles
   double* d_jamps = nullptr;  // staged dual amplitudes (matrix-core colour-sum modes)
   size_t jamps_cap = 0;       // doubles
-  double* d_sums = nullptr;   // colour-group sums of the split executor
+  double* d_sums = nullptr;   // colour-group sums, then colour flows, of the split executor
   size_t sums_cap = 0;        // doubles
+  double* d_cf64 = nullptr;   // colour matrix for the split executor's FP64 matrix-core colour form
+  // per-kernel timing (me_set_kernel_timing): recorded (class, start, stop) events
+  bool timing = false;
+  struct Timed { int kind; hipEvent_t a, b; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_used;  // events recorded since the last read (each once)
+  std::vector<hipEvent_t> ev_pool;  // events free for reuse
   void* d_cf_hi = nullptr;    // colour matrix in the MFMA input format
   void* d_cf_lo = nullptr;    // its low half when the matrix is split (BF16)
   bool filtered = false;
@@ -214,10 +221,12 @@ int ensure_sums(me_ctx* c, size_t n) {
   return ensure_buffer(&c->d_sums, &c->sums_cap, n, "group sums");
 }
 
-// Events per chunk of the split executor: the group sums of a chunk (2 NGROUP
-// doubles per row, nhel rows per event) fill at most ME_SPLIT_SCRATCH_BYTES.
+// Events per chunk of the split executor: the group sums and the colour flows of a
+// chunk (2 NGROUP + 2 NCOL doubles per row, nhel rows per event) fill at most
+// ME_SPLIT_SCRATCH_BYTES.
 int64_t split_chunk(const me_ctx* h, int64_t nevt) {
-  const size_t per_event = sizeof(double) * 2 * (size_t)h->desc->ngroup * h->good.size();
+  const size_t per_event =
+      sizeof(double) * 2 * (size_t)(h->desc->ngroup + h->desc->ncol) * h->good.size();
   int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
   chunk = std::max<int64_t>(64, (chunk / 64) * 64);
   return std::min<int64_t>(chunk, nevt);
@@ -323,7 +332,69 @@ int build_tables(me_ctx* c, int mode) {
   return ME_OK;
 }
 
+// Integer colour matrix in FP64 for the split executor's matrix-core colour form:
+// [16 MB][4 KS] zero padded, MB = ceil(NCOL / 16), KS = ceil(NCOL / 4).
+int build_cf64(me_ctx* c) {
+  if (!c->desc->split) return ME_OK;
+  const int n = c->desc->ncol;
+  const int kp = ((n + 3) / 4) * 4, mp = ((n + 15) / 16) * 16;
+  std::vector<double> t((size_t)mp * kp, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const int v = c->desc->cf_int[i * n + k];
+      // the colour kernel holds the matrix in FP32
+      if (v >= (1 << 24) || v <= -(1 << 24)) return fail(ME_EINVAL, "colour matrix entry not exact in FP32");
+      t[(size_t)i * kp + k] = (double)v;
+    }
+  hipError_t e = hipMalloc(&c->d_cf64, t.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(c->d_cf64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (c->d_cf64) (void)hipFree(c->d_cf64);
+    c->d_cf64 = nullptr;
+    return hip_fail(e, "FP64 colour-matrix table");
+  }
+  return ME_OK;
+}
+
 bool valid_mode(int m) { return m == ME_CS_FP64 || m == ME_CS_FP16X2 || m == ME_CS_BF16X2; }
+
+// An event for per-kernel timing, recorded on s now (nullptr if none is available).
+hipEvent_t mark_event(me_ctx* h, hipStream_t s) {
+  hipEvent_t e = nullptr;
+  if (!h->ev_pool.empty()) {
+    e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  h->ev_used.push_back(e);
+  (void)hipEventRecord(e, s);
+  return e;
+}
+
+// Events around one kernel launch of class kind when timing is on: constructed
+// before the launch, done() after it.
+struct KernelMark {
+  me_ctx* h;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  KernelMark(me_ctx* h_, int kind_, hipStream_t s_) : h(h_), kind(kind_), s(s_) {
+    if (h->timing) a = mark_event(h, s);
+  }
+  void done() {
+    if (!a) return;
+    hipEvent_t b = mark_event(h, s);
+    if (b) h->timed.push_back({kind, a, b});
+    a = nullptr;
+  }
+};
+
+void release_timed(me_ctx* h) {
+  h->ev_pool.insert(h->ev_pool.end(), h->ev_used.begin(), h->ev_used.end());
+  h->ev_used.clear();
+  h->timed.clear();
+}
 
 }  // namespace
 
@@ -373,9 +444,11 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   }
   int rc = upload_good(c, nullptr);
   if (rc == ME_OK) rc = build_tables(c, prm.colorsum_mode);
+  if (rc == ME_OK) rc = build_cf64(c);
   if (rc != ME_OK) {
     (void)hipFree(c->d_hels);
     (void)hipFree(c->d_scratch_hels);
+    if (c->d_cf64) (void)hipFree(c->d_cf64);
     free_tables(c);
     delete c;
     return rc;
@@ -392,6 +465,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
     (void)hipFree(c->d_hels);
     (void)hipFree(c->d_scratch_hels);
     if (c->d_counter) (void)hipFree(c->d_counter);
+    if (c->d_cf64) (void)hipFree(c->d_cf64);
     free_tables(c);
     delete c;
     return fail(ME_ENOMEM, "work counter / capture stream");
@@ -416,6 +490,10 @@ int me_finalize(me_handle h) {
   hipError_t e3 = h->d_partial ? hipFree(h->d_partial) : hipSuccess;
   if (h->d_jamps) (void)hipFree(h->d_jamps);
   if (h->d_sums) (void)hipFree(h->d_sums);
+  if (h->d_cf64) (void)hipFree(h->d_cf64);
+  for (hipEvent_t e : h->ev_used) (void)hipEventSynchronize(e);
+  release_timed(h);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->d_counter) (void)hipFree(h->d_counter);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
@@ -546,7 +624,7 @@ int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
   if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_SPLIT) {
     const int64_t chunk = split_chunk(h, nevt);
-    int rc = ensure_sums(h, (size_t)chunk * nhel * 2 * h->desc->ngroup);
+    int rc = ensure_sums(h, (size_t)chunk * nhel * 2 * (h->desc->ngroup + h->desc->ncol));
     if (rc) return rc;
     return ensure_partial(h, (size_t)chunk * nhel);
   }
@@ -569,7 +647,8 @@ int prepare(me_ctx* h, int64_t nevt) {
 }
 
 // Enqueue the kernels of one me_compute call on stream s (capturable: no
-// allocation, no synchronisation, no memset).
+// allocation, no synchronisation, no memset; with per-kernel timing on it records
+// events and is not captured).
 int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
             hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
@@ -582,12 +661,26 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
     for (int64_t off = 0; off < nevt; off += chunk) {
       const int64_t n = std::min<int64_t>(chunk, nevt - off);
-      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, h->d_partial,
-                      alphas ? alphas + off : nullptr, s};
+      // flows after the group sums of a full chunk
+      double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
+      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
+                      h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}};
+      // with timing on, the launcher records a.ev[k] before kernel k (sums, flows,
+      // colour form) and a.ev[3] after the last; the events are marked here (taken
+      // from the pool) and re-recorded at their place in the launcher
+      if (h->timing)
+        for (auto& ev : a.ev) ev = mark_event(h, s);
       hipError_t e = h->desc->split(a);
+      if (h->timing && e == hipSuccess && a.ev[0] && a.ev[1] && a.ev[2] && a.ev[3]) {
+        h->timed.push_back({ME_KT_DIAGRAM, a.ev[0], a.ev[1]});
+        h->timed.push_back({ME_KT_FLOWS, a.ev[1], a.ev[2]});
+        h->timed.push_back({ME_KT_COLOUR, a.ev[2], a.ev[3]});
+      }
       if (e != hipSuccess) return hip_fail(e, "split kernels launch");
+      KernelMark km(h, ME_KT_REDUCE, s);
       hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                          h->d_partial, nhel, n, scale, out_me2 + off);
+      km.done();
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     }
@@ -603,11 +696,15 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
                      h->d_partial, nullptr, s};
     a.alphas = alphas;
+    KernelMark kd(h, ME_KT_DIAGRAM, s);
     hipError_t e = h->desc->team(a);
     if (e != hipSuccess) return hip_fail(e, "team kernel launch");
+    kd.done();
     const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    KernelMark kr(h, ME_KT_REDUCE, s);
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
                        h->d_partial, nchunk, nevt, scale, out_me2);
+    kr.done();
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     return ME_OK;
@@ -632,11 +729,15 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       a.counter = h->d_counter;
       a.waves = h->simds * h->waves_per_simd;
     }
+    KernelMark kd(h, ME_KT_DIAGRAM, s);
     hipError_t e = h->desc->launch(a);
     if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+    kd.done();
     const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+    KernelMark kr(h, ME_KT_REDUCE, s);
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s,
                        h->d_partial, nchunk, nevt, scale, out_me2);
+    kr.done();
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     return ME_OK;
@@ -655,14 +756,20 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
                      nullptr, h->d_jamps, s};
     a.alphas = alphas ? alphas + off : nullptr;
     // the diagram kernel of the process: one-lane code, else the team program
+    KernelMark kd(h, ME_KT_DIAGRAM, s);
     hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
     if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+    kd.done();
     me::ColourArgs ca{h->d_jamps, n * nhel, fmt, h->d_cf_hi, h->d_cf_lo,
                       1.0 / h->desc->cf_den, h->d_partial, s};
+    KernelMark kc(h, ME_KT_COLOUR, s);
     e = h->desc->colour(ca);
     if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+    kc.done();
+    KernelMark kr(h, ME_KT_REDUCE, s);
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        h->d_partial, nhel, n, 1.0 / h->desc->iden, out_me2 + off);
+    kr.done();
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
   }
@@ -687,7 +794,7 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   }
   rc = prepare(h, nevt);
   if (rc) return rc;
-  if (!h->params.use_graph) return enqueue(h, momenta, nevt, alpha_s, out_me2, s);
+  if (!h->params.use_graph || h->timing) return enqueue(h, momenta, nevt, alpha_s, out_me2, s);
   // replay the captured sequence when the call matches the captured one
   if (!(h->graph && h->g_mom == momenta && h->g_out == out_me2 && h->g_nevt == nevt &&
         h->g_alpha == alpha_s && h->g_mode == h->params.colorsum_mode)) {
@@ -900,7 +1007,9 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   }
   const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
             save_tw = h->target_waves, save_graph = h->params.use_graph, save_x = h->executor;
+  const bool save_timing = h->timing;
   h->params.use_graph = 0;
+  h->timing = false;   // the candidates' launches are not part of a timed measurement
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return fail(ME_EHIP, "hipEventCreate");
@@ -929,6 +1038,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   h->params.use_graph = save_graph;
+  h->timing = save_timing;
   drop_graph(h);
   if (rc || best_i < 0) {
     h->persistent = save_p;
@@ -962,6 +1072,44 @@ int me_set_executor(me_handle h, int executor) {
     return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor");
   h->executor = executor;
   drop_graph(h);
+  return ME_OK;
+}
+
+int me_set_kernel_timing(me_handle h, int on) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->timing && !on) {
+    // events still pending are waited for before they are reused
+    for (hipEvent_t e : h->ev_used) (void)hipEventSynchronize(e);
+    release_timed(h);
+  }
+  h->timing = on != 0;
+  return ME_OK;
+}
+
+int me_kernel_times(me_handle h, double* total_ms, int64_t* launches) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!total_ms || !launches) return fail(ME_EINVAL, "null pointer");
+  for (int k = 0; k < ME_KT_KINDS; ++k) {
+    total_ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipError_t err = hipSuccess;
+  for (const auto& t : h->timed) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) {
+      err = e;
+      continue;
+    }
+    total_ms[t.kind] += ms;
+    launches[t.kind] += 1;
+  }
+  for (hipEvent_t e : h->ev_used) (void)hipEventSynchronize(e);
+  release_timed(h);
+  if (err != hipSuccess) return hip_fail(err, "kernel timing events");
   return ME_OK;
 }
 

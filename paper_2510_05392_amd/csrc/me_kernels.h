@@ -184,15 +184,20 @@ hipError_t launch_colour(const ColourArgs& a) {
   return hipGetLastError();
 }
 
-// Split executor.  sums_kernel: one lane per row (event e, helicity k) of the
-// chunk stores the colour-group sums of its diagrams (no colour flows are kept
-// live, which is what makes the diagram code fit the register file far
-// better); assemble_kernel: one lane per row forms the flows from the group
-// sums and the FP64 colour form.
-template <class P>
-__global__ void __launch_bounds__(64) sums_kernel(const double* __restrict__ mom, int64_t n, double g, double mt,
-                                                  const int* __restrict__ hels, int nhel, double* __restrict__ sums,
-                                                  const double* __restrict__ alphas) {
+// Split executor, three kernel kinds per chunk of rows (row = k n + e for event e
+// and helicity k of the chunk):
+//  sums_kernel<P, K>: one lane per row stores the colour-group sums of its diagrams
+//    in part K of the groups (no colour flows are kept live, which is what makes
+//    the diagram code fit the register file far better; each part computes only
+//    the currents its groups need);
+//  flows_kernel: a workgroup of four waves per 64 rows streams the group sums
+//    through LDS in chunks of FCHUNK groups (each sum read from HBM once); wave w
+//    keeps its quarter of the colour flows in registers and writes them out;
+//  colour_f64_kernel: the colour form of every row on the FP64 matrix cores.
+template <class P, int K>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P::SUMS_WPE, P::SUMS_WPE)))
+sums_kernel(const double* __restrict__ mom, int64_t n, double g, double mt, const int* __restrict__ hels, int nhel,
+            double* __restrict__ sums, const double* __restrict__ alphas) {
   const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int k = blockIdx.y;
   if (e >= n) return;
@@ -202,31 +207,93 @@ __global__ void __launch_bounds__(64) sums_kernel(const double* __restrict__ mom
   int lam[P::NPAR];
   helicity_signs<P>(hels[k], lam);
   const int64_t rows = n * nhel;
-  P::group_sums(p, lam, g, mt, sums + (int64_t)k * n + e, rows);
+  P::template group_sums_part<K>(p, lam, g, mt, sums + (int64_t)k * n + e, rows);
 }
 
+// the group-sum kernels of parts K, K + 1, ..., NPART - 1, in order
+template <class P, int K = 0>
+hipError_t launch_sums(const SplitArgs& a) {
+  if constexpr (K == P::NPART) {
+    return hipSuccess;
+  } else {
+    hipLaunchKernelGGL((sums_kernel<P, K>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0,
+                       a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sums<P, K + 1>(a);
+  }
+}
+
+// sums: [2 NGROUP][rows]; jt: [2 NCOL][rows] (real, imaginary part of each flow).
 template <class P>
-__global__ void __launch_bounds__(64) assemble_kernel(const double* __restrict__ sums, int64_t rows,
-                                                      double* __restrict__ partial) {
-  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (r >= rows) return;
-  cx jamp[P::NCOL];
+__global__ void __launch_bounds__(256) flows_kernel(const double* __restrict__ sums, int64_t rows,
+                                                    double* __restrict__ jt) {
+  constexpr int CH = P::FCHUNK;
+  constexpr int NCH = (P::NGROUP + CH - 1) / CH;
+  constexpr int PER = CH / 2;   // doubles of a chunk (2 CH x 64) each of the 256 threads stages
+  static_assert(CH % 2 == 0, "chunk of group sums must split evenly over 256 threads");
+  __shared__ double buf[2][2 * CH * 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = r < rows;
+  double acc[2 * P::FPW];
 #pragma unroll
-  for (int i = 0; i < P::NCOL; ++i) jamp[i] = cx{0.0, 0.0};
-  P::flows_from_sums(sums + r, rows, jamp);
-  partial[r] = P::colour_sum(jamp);
+  for (int i = 0; i < 2 * P::FPW; ++i) acc[i] = 0.0;
+  double st[PER];
+  // thread (w, lane) stages rows w, w + 4, ... of the chunk's 2 CH sum rows
+  auto load = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = 2 * CH * c + w + 4 * i;
+      st[i] = (ok && q < 2 * P::NGROUP) ? sums[(int64_t)q * rows + r] : 0.0;
+    }
+  };
+  auto put = [&](int bi) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) buf[bi][(w + 4 * i) * 64 + lane] = st[i];
+  };
+  load(0);
+  put(0);
+  __syncthreads();
+  for (int c = 0; c < NCH; ++c) {
+    // the next chunk's loads are in flight while this chunk's updates run; one
+    // barrier per chunk suffices because a buffer is rewritten only after every
+    // wave has passed the barrier that ends its last use
+    if (c + 1 < NCH) load(c + 1);
+    P::flow_chunk(w, c, &buf[c & 1][lane], acc);
+    if (c + 1 < NCH) put((c + 1) & 1);
+    __syncthreads();
+  }
+  if (!ok) return;
+#pragma unroll
+  for (int lk = 0; lk < P::FPW; ++lk) {
+    const int k = w * P::FPW + lk;
+    if (k < P::NCOL) {
+      jt[(int64_t)(2 * k) * rows + r] = acc[2 * lk];
+      jt[(int64_t)(2 * k + 1) * rows + r] = acc[2 * lk + 1];
+    }
+  }
 }
 
 template <class P>
 hipError_t launch_split(const SplitArgs& a) {
   const int64_t rows = a.n * a.nhel;
-  hipLaunchKernelGGL(sums_kernel<P>, dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0, a.stream,
-                     a.mom, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
-  hipError_t e = hipGetLastError();
+  if (a.ev[0]) (void)hipEventRecord(a.ev[0], a.stream);
+  hipError_t e = launch_sums<P>(a);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(assemble_kernel<P>, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, a.stream, a.sums, rows,
-                     a.partial);
-  return hipGetLastError();
+  if (a.ev[1]) (void)hipEventRecord(a.ev[1], a.stream);
+  hipLaunchKernelGGL(flows_kernel<P>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, a.stream, a.sums, rows,
+                     a.jt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.ev[2]) (void)hipEventRecord(a.ev[2], a.stream);
+  constexpr int RPB = 4 * 8 * COLOUR_F64_TILES;   // rows per tile of the colour kernel
+  const int64_t tiles = (rows + RPB - 1) / RPB;
+  hipLaunchKernelGGL(colour_f64_kernel<P::NCOL>, dim3((unsigned)std::min<int64_t>(tiles, COLOUR_F64_GRID)),
+                     dim3(256), 0, a.stream, a.jt, rows, a.cf64, a.partial);
+  e = hipGetLastError();
+  if (e == hipSuccess && a.ev[3]) (void)hipEventRecord(a.ev[3], a.stream);
+  return e;
 }
 
 // Processes without the one-lane code (P::LANE false) have only the team executor

@@ -79,9 +79,12 @@ struct SplitArgs {
   const int* hels;       // device, good helicities
   int nhel;
   double* sums;          // device, [2 * NGROUP][nhel * n]
+  double* jt;            // device, [2 * NCOL][nhel * n] colour flows
+  const double* cf64;    // device, colour matrix for the FP64 matrix-core colour form
   double* partial;       // device, [nhel][n]
   const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
   hipStream_t stream;
+  hipEvent_t ev[4];      // recorded before the first, between, and after the last kernel, or nullptr
 };
 
 using SplitLauncher = hipError_t (*)(const SplitArgs&);

@@ -66,9 +66,38 @@ def colour_sum_flops(ncol):
     return 2 * ncol * ncol + 4 * ncol
 
 
-def per_event_helicity(name):
+def _plan(name):
     from .gen import codegen
     from .gen.topology import Plan
-    n = codegen.PROCESS_NPAR[name] - 2
-    plan = Plan(n)
+    return Plan(codegen.PROCESS_NPAR[name] - 2)
+
+
+def per_event_helicity(name):
+    plan = _plan(name)
     return plan_flops(plan) + colour_sum_flops(len(plan.basis))
+
+
+def flow_updates(plan):
+    """Colour-flow accumulations (one per (group, flow) pair) of a plan."""
+    return sum(len(key) for key, _ in plan.colour_groups())
+
+
+def diagram_kernel(name, executor):
+    """FP64 flops per (event, helicity) of the kernel that evaluates the diagrams:
+    everything for the one-lane and team executors (flows and colour form are fused
+    into it), the group sums alone for the split executor (executor 2), whose flows
+    and colour form run in kernels of their own."""
+    plan = _plan(name)
+    if executor == 2:
+        return plan_flops(plan) - ROUTINE['jamp'] * flow_updates(plan)
+    return plan_flops(plan) + colour_sum_flops(len(plan.basis))
+
+
+def split_bytes(name):
+    """Algorithmic HBM bytes per (event, helicity) row of the split executor's
+    kernels: the sums kernel writes 2 NGROUP doubles; the flows kernel reads them
+    and writes 2 NCOL doubles; the colour kernel reads the 2 NCOL doubles and writes
+    one partial sum."""
+    plan = _plan(name)
+    ngroup, ncol = len(plan.colour_groups()), len(plan.basis)
+    return {'sums': 8 * 2 * ngroup, 'flows': 8 * (2 * ngroup + 2 * ncol), 'colour': 8 * (2 * ncol + 1)}

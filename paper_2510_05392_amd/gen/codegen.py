@@ -10,6 +10,12 @@ The emitted header defines, for process <name>:
                                                         (triangular: off-diagonal terms
                                                         once, doubled), not yet / CF_DEN
   CF_INT[NCOL*NCOL] (host table)
+  __device__ void group_sums_part<K>(p, lam, g, mt, sout, sstride)
+                                                     -- split executor: the colour-group
+        sums of one (event, helicity) in part K of the groups, stored instead of
+        accumulated into flows
+  __device__ void flow_chunk(w, c, b, acc)           -- split executor: wave w's share of
+        the flow updates from chunk c of group sums staged in LDS
 
 Everything is straight-line code: the generator has already resolved the
 diagram structure, so the compiler sees fixed register operands.
@@ -198,12 +204,13 @@ class Emitter:
             return '-', f"times_i({expr})"
         raise ValueError(c)
 
-    def amplitudes(self, split=False):
+    def amplitudes(self, split=False, groups=None):
         """Pieces sharing one colour vector (up to a unit factor) are summed first,
         then the sum is added once to each of its colour flows.  With split set the
         sum of group gi is stored to sout[2 gi sstride] (real) and
         sout[(2 gi + 1) sstride] (imaginary) instead, and the flows are formed by
-        flows_from_sums() in a second kernel."""
+        flow_chunks() in a second kernel; groups (a range of group indices) then
+        restricts the code to those groups and the currents they need."""
         done = set()
 
         def need(key):
@@ -215,6 +222,8 @@ class Emitter:
             done.add(key)
 
         for gi, (key, members) in enumerate(self.plan.scheduled_groups()):
+            if groups is not None and gi not in groups:
+                continue
             first_lead = members[0][0]
             acc = f"s{gi}"
             for n_m, (lead, amp) in enumerate(members):
@@ -238,17 +247,42 @@ class Emitter:
                 self.lines.append(f"  jamp[{k}] = jamp[{k}] {sign} {term};")
         return self.lines
 
-    def flows_from_sums(self):
-        """J_k = sum over groups of (unit coefficient) x group sum, the group sums read
-        from s[2 gi sstride], s[(2 gi + 1) sstride] in the order amplitudes() stores them."""
-        lines = []
-        for gi, (key, members) in enumerate(self.plan.scheduled_groups()):
-            first_lead = members[0][0]
-            lines.append(f"  {{ const cx s{gi}{{s[{2 * gi} * sstride], s[{2 * gi + 1} * sstride]}};")
-            for k, rel in key:
-                sign, term = self._scaled(f"s{gi}", rel * first_lead)
-                lines.append(f"    jamp[{k}] = jamp[{k}] {sign} {term};")
-            lines.append("  }")
+    def flow_chunks(self, nwave, chunk):
+        """Flows formed from group sums staged through LDS, chunk by chunk: wave w of
+        the workgroup owns flows [w fpw, (w + 1) fpw) and keeps them in acc
+        (acc[2 lk] real, acc[2 lk + 1] imaginary part of local flow lk); chunk c holds
+        groups [c chunk, (c + 1) chunk) of the order amplitudes() stores them in, group
+        c chunk + gl at b[2 gl 64] (real) and b[(2 gl + 1) 64] (imaginary)."""
+        groups = self.plan.scheduled_groups()
+        fpw = -(-len(self.plan.basis) // nwave)
+        nch = -(-len(groups) // chunk)
+        lines = [f"  switch (w * {nch} + c) {{"]
+        for w in range(nwave):
+            for c in range(nch):
+                body = []
+                for gl, (key, members) in enumerate(groups[c * chunk:(c + 1) * chunk]):
+                    mine = [(k, rel) for k, rel in key if k // fpw == w]
+                    if not mine:
+                        continue
+                    first_lead = members[0][0]
+                    body.append(f"    {{ const double sr = b[{2 * gl * 64}], si = b[{(2 * gl + 1) * 64}];")
+                    for k, rel in mine:
+                        lk = k - w * fpw
+                        re_, im_ = _cx(rel * first_lead)
+                        if re_:
+                            op = '+' if re_ > 0 else '-'
+                            body.append(f"      acc[{2 * lk}] {op}= sr; acc[{2 * lk + 1}] {op}= si;")
+                        else:
+                            # (sr + i si) times +-i = -+si +- i sr
+                            op, nop = ('+', '-') if im_ > 0 else ('-', '+')
+                            body.append(f"      acc[{2 * lk}] {nop}= si; acc[{2 * lk + 1}] {op}= sr;")
+                    body.append("    }")
+                if body:
+                    lines.append(f"  case {w * nch + c}: {{")
+                    lines.extend(body)
+                    lines.append("    break; }")
+        lines.append("  default: break;")
+        lines.append("  }")
         return lines
 
 
@@ -270,13 +304,29 @@ def colour_sum_code(cf, ncol):
     return lines
 
 
+# Staged flow formation of the split executor: waves per workgroup (each owns a
+# contiguous quarter of the colour flows) and colour groups per LDS chunk.
+FLOW_WAVES = 4
+FLOW_CHUNK = 16
+
+# Split executor's group-sum kernels: the groups (in scheduled order) are cut into
+# SUMS_PARTS contiguous ranges, one kernel each, each computing only the currents
+# its groups need (currents shared between ranges are recomputed: fewer live
+# currents per kernel, less spill traffic); SUMS_WPE waves per SIMD for them.
+SUMS_PARTS = {}
+SUMS_WPE = {'gg_ttxggg': 2}
+
 # Largest process that also gets the one-lane-per-(event, helicity) code; beyond
 # it the straight-line function would be too large to compile in reasonable
 # time, and only the team program is generated.
 LANE_MAX_NPAR = 7
 
 
-def generate(name):
+def part_ranges(ngroup, nparts):
+    return [range(k * ngroup // nparts, (k + 1) * ngroup // nparts) for k in range(nparts)]
+
+
+def generate(name, sums_parts=None, sums_wpe=None):
     npar = PROCESS_NPAR[name]
     n = npar - 2
     plan = Plan(n)
@@ -285,9 +335,12 @@ def generate(name):
     iden = 4 * 64 * math.factorial(npar - 4)
     lane = npar <= LANE_MAX_NPAR
     body = Emitter(name, plan).amplitudes() if lane else []
-    sums = Emitter(name, plan).amplitudes(split=True) if lane else []
-    assemble = Emitter(name, plan).flows_from_sums() if lane else []
     ngroup = len(plan.scheduled_groups())
+    nparts = sums_parts or SUMS_PARTS.get(name, 1)
+    wpe = sums_wpe or SUMS_WPE.get(name, 1)
+    parts = [Emitter(name, plan).amplitudes(split=True, groups=r) for r in part_ranges(ngroup, nparts)] \
+        if lane else []
+    assemble = Emitter(name, plan).flow_chunks(FLOW_WAVES, FLOW_CHUNK) if lane else []
     team_src, _ = team_gen.emit(name, plan)
     out = []
     out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
@@ -321,12 +374,23 @@ def generate(name):
         out.append("  }")
         out.append("  // split evaluation: colour-group sums of one (event, helicity), stride sstride")
         out.append(f"  static constexpr int NGROUP = {ngroup};")
-        out.append("  static __device__ __forceinline__ void group_sums(const double (*p)[4], const int* lam, "
+        out.append(f"  static constexpr int NPART = {nparts};   // group-sum kernels")
+        out.append(f"  static constexpr int SUMS_WPE = {wpe};   // their waves per SIMD")
+        for k, lines in enumerate(parts):
+            out.append(f"  static __device__ __forceinline__ void group_sums_{k}(const double (*p)[4], const int* lam, "
+                       "double g, double mt, double* sout, int64_t sstride) {")
+            out.extend('  ' + l for l in lines)
+            out.append("  }")
+        out.append("  template <int K>")
+        out.append("  static __device__ __forceinline__ void group_sums_part(const double (*p)[4], const int* lam, "
                    "double g, double mt, double* sout, int64_t sstride) {")
-        out.extend('  ' + l for l in sums)
+        for k in range(nparts):
+            kw = 'if' if k == 0 else 'else if'
+            out.append(f"    {kw} constexpr (K == {k}) group_sums_{k}(p, lam, g, mt, sout, sstride);")
         out.append("  }")
-        out.append("  static __device__ __forceinline__ void flows_from_sums(const double* s, int64_t sstride, "
-                   "cx* jamp) {")
+        out.append(f"  static constexpr int FCHUNK = {FLOW_CHUNK};   // group sums per LDS chunk")
+        out.append(f"  static constexpr int FPW = {-(-ncol // FLOW_WAVES)};   // colour flows per wave")
+        out.append("  static __device__ __forceinline__ void flow_chunk(int w, int c, const double* b, double* acc) {")
         out.extend('  ' + l for l in assemble)
         out.append("  }")
     out.append("};")

@@ -11,15 +11,18 @@ CSRC = os.path.join(ROOT, 'paper_2510_05392_amd', 'csrc')
 OUT = os.path.join(ROOT, '_build', 'cpu_harness')
 
 
-def build(name, opt='-O1'):
+def build(name, opt='-O1', sums_parts=None):
+    """sums_parts: number of group-sum parts of the split executor (default: the
+    generator's choice for the process)."""
     from paper_2510_05392_amd.gen import codegen
     os.makedirs(OUT, exist_ok=True)
-    src, _, _ = codegen.generate(name)
-    hdr = os.path.join(OUT, f'{name}.inc')
+    src, _, _ = codegen.generate(name, sums_parts=sums_parts)
+    tag = f'{name}_p{sums_parts}' if sums_parts else name
+    hdr = os.path.join(OUT, f'{tag}.inc')
     if not os.path.exists(hdr) or open(hdr).read() != src:
         with open(hdr, 'w') as f:
             f.write(src)
-    lib = os.path.join(OUT, f'harness_{name}.so')
+    lib = os.path.join(OUT, f'harness_{tag}.so')
     deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(CSRC, 'me_team.h'),
             os.path.join(HERE, 'harness.cpp')]
     if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):

@@ -30,13 +30,24 @@ void lane_eval(const double* mom, int nevt, double g, double mt, const int* hels
   }
 }
 
-// Split evaluation: group sums of each (event, helicity) row, then the flows
-// from the sums and the colour form, exactly as the two GPU kernels do.
+template <class P, int K = 0>
+void sums_parts(const double (*p)[4], const int* lam, double g, double mt, double* sums) {
+  if constexpr (K < P::NPART) {
+    P::template group_sums_part<K>(p, lam, g, mt, sums, 1);
+    sums_parts<P, K + 1>(p, lam, g, mt, sums);
+  }
+}
+
+// Split evaluation: group sums of each (event, helicity) row (every part), then the flows
+// formed chunk by chunk from the sums staged as the LDS buffer holds them (this
+// row at lane 0), each wave's share of the flows separately, then the colour form.
 template <class P>
 void split_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h) {
   using namespace me;
-  constexpr int NPAR = P::NPAR, NCOL = P::NCOL;
+  constexpr int NPAR = P::NPAR, NCOL = P::NCOL, CH = P::FCHUNK, FPW = P::FPW;
+  constexpr int NCH = (P::NGROUP + CH - 1) / CH;
   static double sums[2 * P::NGROUP];
+  static double buf[2 * CH * 64];
   for (int e = 0; e < nevt; ++e) {
     double p[NPAR][4];
     for (int q = 0; q < NPAR; ++q)
@@ -44,10 +55,17 @@ void split_eval(const double* mom, int nevt, double g, double mt, const int* hel
     for (int k = 0; k < nh; ++k) {
       int lam[NPAR];
       for (int q = 0; q < NPAR; ++q) lam[q] = (hels[k] >> (NPAR - 1 - q)) & 1 ? 1 : -1;
-      P::group_sums(p, lam, g, mt, sums, 1);
+      sums_parts<P>(p, lam, g, mt, sums);
+      double acc[4][2 * FPW] = {};
+      for (int c = 0; c < NCH; ++c) {
+        for (int q = 0; q < 2 * CH; ++q) {
+          const int gq = 2 * CH * c + q;
+          buf[q * 64] = gq < 2 * P::NGROUP ? sums[gq] : 0.0;
+        }
+        for (int w = 0; w < 4; ++w) P::flow_chunk(w, c, buf, acc[w]);
+      }
       cx jamp[NCOL];
-      for (int c = 0; c < NCOL; ++c) jamp[c] = cx{0.0, 0.0};
-      P::flows_from_sums(sums, 1, jamp);
+      for (int c = 0; c < NCOL; ++c) jamp[c] = cx{acc[c / FPW][2 * (c % FPW)], acc[c / FPW][2 * (c % FPW) + 1]};
       me_h[k * nevt + e] = P::colour_sum(jamp) / P::CF_DEN;
     }
   }

@@ -88,3 +88,29 @@ def test_split_deterministic_alphas_and_graph(binding):
     assert np.allclose(c, a * (alphas / AS) ** 4, rtol=1e-12)
     with pytest.raises(binding.MeError):
         binding.MatrixElement('gg_ttxgggg').me_set_executor(binding.ME_EXEC_SPLIT)
+
+
+@pytest.mark.parametrize('executor,mode,expect', [(2, 0, [1, 1, 1, 1]), (0, 0, [1, 0, 0, 1]), (1, 0, [1, 0, 0, 1]),
+                                                  (0, 1, [1, 0, 1, 1])])
+def test_kernel_timing(binding, executor, mode, expect):
+    # per-kernel events: one launch per kernel class of a one-chunk call, durations
+    # positive, results equal to an untimed call (also on a graph handle, which runs
+    # eagerly while timing is on), counters reset on reading
+    _say(f'case kernel timing executor={executor} mode={mode}')
+    mom = rambo.generate(6, 130, 26)
+    d = torch.from_numpy(mom).cuda()
+    m = binding.MatrixElement('gg_ttxgg', colorsum_mode=mode, use_graph=True)
+    m.me_set_executor(executor)
+    ref = m.compute(d, AS).cpu().numpy()
+    m.me_set_kernel_timing(True)
+    got = m.compute(d, AS).cpu().numpy()
+    ms, n = m.me_kernel_times()
+    assert n == expect
+    assert all((t > 0) == (c > 0) for t, c in zip(ms, n))
+    assert np.array_equal(got, ref)
+    ms, n = m.me_kernel_times()
+    assert n == [0, 0, 0, 0]
+    m.compute(d, AS)
+    m.me_set_kernel_timing(False)
+    assert np.array_equal(m.compute(d, AS).cpu().numpy(), ref)
+    assert m.me_kernel_times()[1] == [0, 0, 0, 0]
