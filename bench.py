@@ -65,7 +65,7 @@ def cpu_baseline(process, mom, alpha_s, budget_s):
                       f'numpy FP64 oracle, {t_used:.1f} s'}
 
 
-def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo):
+def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None):
     """Mixed colour sum + surrogate two-stage unweighting of the same workload.
 
     The surrogate is trained on separate events labelled by the exact path;
@@ -89,6 +89,9 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo):
         exact_mode = binding.ME_CS_FP64
         pipe = SurrogatePipeline(process, width=256, depth=4, seed=11, alpha_s=args.alpha_s,
                                  colorsum_mode=exact_mode)
+    if executor is not None:
+        # the exact path on the executor the FP64 run was tuned to
+        pipe.me.me_set_executor(executor)
     train = torch.from_numpy(rambo.generate(npar, args.sur_train, 2001)).cuda()
     t0 = time.perf_counter()
     hist = pipe.fit(train, epochs=args.sur_epochs, batch=4096, lr=2e-3, lr_final=1e-4)
@@ -198,8 +201,9 @@ def main():
     dmom = torch.from_numpy(mom).to(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def run(mode):
-        """Time me_compute over the batch in one colour-sum mode; returns (ms/step, ME, nhel)."""
+    def run(mode, executor=None):
+        """Time me_compute over the batch in one colour-sum mode (on the given executor,
+        else the tuned or default one)."""
         out = torch.empty(nevt, dtype=torch.float64, device=dev)
         m = binding.MatrixElement(process, colorsum_mode=mode, use_graph=not args.no_graph)
         tuned = None
@@ -213,6 +217,8 @@ def main():
             nt = min(nevt, 65536)
             print(f'# bench autotune on {nt} events', file=sys.stderr, flush=True)
             tuned = m.me_autotune(dmom[:nt], nt, args.alpha_s, out[:nt], stream)
+        elif executor is not None:
+            m.me_set_executor(executor)
         print(f'# bench {process} nevt={nevt} mode={mode}: warmup {args.warmup}', file=sys.stderr,
               flush=True)
         for _ in range(max(1, args.warmup)):
@@ -261,9 +267,10 @@ def main():
     mixed = None
     if not args.fp64_only:
         try:
-            ms_m, res_m, _, _, _, _ = run(binding.ME_CS_FP16X2)
+            ms_m, res_m, _, _, _, _ = run(binding.ME_CS_FP16X2, (tuned or {}).get('executor'))
             rel = np.abs(res_m / res - 1)
             mixed = {'colorsum': 'split FP16 hi+lo on MFMA, FP32 accumulation, FP64 row dots',
+                     'executor': (tuned or {}).get('executor', 0),
                      'value': nevt / (ms_m * 1e-3), 'unit': 'ME evals/s', 'ms_per_step': ms_m,
                      'max_rel_err_vs_fp64': float(rel.max()),
                      'rms_rel_err_vs_fp64': float(np.sqrt(np.mean(rel ** 2))), 'stated_bound': 1e-5}
@@ -310,7 +317,8 @@ def main():
     if mixed is not None:
         line['mixed'] = mixed
     if args.surrogate:
-        line['surrogate'] = surrogate_leg(args, process, nevt, mom, dmom, binding, rambo)
+        line['surrogate'] = surrogate_leg(args, process, nevt, mom, dmom, binding, rambo,
+                                          (tuned or {}).get('executor'))
     if args.batch:
         print('# bench uneven batch', file=sys.stderr, flush=True)
         line['uneven_batch'] = batch_leg(args, binding, rambo)

@@ -56,10 +56,11 @@ extern "C" {
 #define ME_EXEC_LANE 0  /* one lane per (event, helicity): generated straight-line code, registers */
 #define ME_EXEC_TEAM 1  /* one team of 32 or 64 lanes per (event, helicity): generated step
                            program, currents staged in LDS.  The matrix-core colour-sum modes use
+                           the split executor's group sums and flows under ME_EXEC_SPLIT, else
                            the one-lane diagram kernel when the process has one (all but
                            gg_ttxgggg), else the team program.  gg_ttxgggg has only the team
-                           program: ME_EXEC_LANE, me_select and me_compute_batch return ME_EINVAL
-                           for it. */
+                           program: ME_EXEC_LANE, ME_EXEC_SPLIT, me_select and me_compute_batch
+                           return ME_EINVAL for it. */
 
 #define ME_EXEC_SPLIT 2 /* three kernels per event chunk: one lane per (event, helicity) stores the
                            sums of its colour groups (no colour flows kept in registers); a
@@ -163,8 +164,10 @@ int me_set_colorsum_mode(me_handle h, int mode);
  * the configuration beyond rounding order of the helicity sum. */
 int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves);
 
-/* Executor of the FP64 colour-sum mode (ME_EXEC_LANE, ME_EXEC_TEAM or
- * ME_EXEC_SPLIT); all give the same |M|^2 up to rounding order.  The team executor uses the helicity
+/* Executor of the diagrams (ME_EXEC_LANE, ME_EXEC_TEAM or ME_EXEC_SPLIT); all give
+ * the same |M|^2 up to rounding order.  In the matrix-core colour-sum modes
+ * ME_EXEC_SPLIT runs the split executor's group sums and flows before the matrix-core
+ * colour sum, the other two the one-lane (or team) diagram kernel.  The team executor uses the helicity
  * chunking of the grid path (target_waves of me_set_launch). */
 int me_set_executor(me_handle h, int executor);
 

@@ -47,9 +47,10 @@ struct cs_types<CS_FMT_BF16> {
   }
 };
 
-// J: [nrow][NCOL][2] FP64.  cf_hi / cf_lo: [MB*32][KS*16] in the MFMA format
-// (cf_lo may be null).  out[row] = ME_row * inv_den.
-template <int NCOL, int FMT>
+// J: [nrow][NCOL][2] FP64, or with TR set [2 NCOL][nrow] (the split executor's
+// flows).  cf_hi / cf_lo: [MB*32][KS*16] in the MFMA format (cf_lo may be null).
+// out[row] = ME_row * inv_den.
+template <int NCOL, int FMT, bool TR = false>
 __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restrict__ J, int64_t nrow,
                                                          const void* __restrict__ cf_hi_raw,
                                                          const void* __restrict__ cf_lo_raw,
@@ -70,7 +71,9 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
   const int part = j >> 4;               // 0 = real parts, 1 = imaginary parts
   const int64_t row = (int64_t)blockIdx.x * 16 + r;
   const bool valid = row < nrow;
-  const double* x = J + (valid ? row : 0) * (NCOL * 2) + part;
+  // element c of this X row at x[2 c st]
+  const int64_t st = TR ? nrow : 1;
+  const double* x = TR ? J + (int64_t)part * nrow + (valid ? row : 0) : J + (valid ? row : 0) * (NCOL * 2) + part;
 
   // power-of-two scale of the row (both parts) so that max|X| is in [1, 2)
   double scale = 1.0, unscale = 1.0;
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int c = 16 * kk + 8 * half + t;
-        if (c < NCOL && valid) m = fmax(m, fabs(x[2 * c]));
+        if (c < NCOL && valid) m = fmax(m, fabs(x[2 * c * st]));
       }
     m = fmax(m, __shfl_xor(m, 16));
     m = fmax(m, __shfl_xor(m, 32));
@@ -105,7 +108,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           const int c = 16 * kk + 8 * half + t;
-          const double v = (c < NCOL && valid) ? x[2 * c] * scale : 0.0;
+          const double v = (c < NCOL && valid) ? x[2 * c * st] * scale : 0.0;
           const elem hi = (elem)v;
           bh[t] = hi;
           bl[t] = (elem)(v - (double)hi);
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
-        if (i < NCOL && valid) s += x[2 * i] * (double)acc[v];
+        if (i < NCOL && valid) s += x[2 * i * st] * (double)acc[v];
       }
     }
   } else {
@@ -139,7 +142,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int c = 16 * kk + 8 * half + t;
-      const double v = (c < NCOL && valid) ? x[2 * c] * scale : 0.0;
+      const double v = (c < NCOL && valid) ? x[2 * c * st] * scale : 0.0;
       const elem hi = (elem)v;
       bh[t] = hi;
       bl[t] = (elem)(v - (double)hi);
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
-      if (i < NCOL && valid) s += x[2 * i] * (double)acc[mb][v];
+      if (i < NCOL && valid) s += x[2 * i * st] * (double)acc[mb][v];
     }
   }
   s += __shfl_xor(s, 32);   // the two halves of the M rows

@@ -622,7 +622,8 @@ namespace {
 // Size the scratch of one me_compute call (outside any capture).
 int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
-  if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_SPLIT) {
+  if (h->executor == ME_EXEC_SPLIT) {
+    // every colour-sum mode: group sums and flows of an event chunk
     const int64_t chunk = split_chunk(h, nevt);
     int rc = ensure_sums(h, (size_t)chunk * nhel * 2 * (h->desc->ngroup + h->desc->ncol));
     if (rc) return rc;
@@ -742,6 +743,39 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     return ME_OK;
   }
+  const int fmt_mc = h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1;
+  if (h->executor == ME_EXEC_SPLIT) {
+    // matrix-core colour sum of the split executor's flows: group sums and flows of
+    // an event chunk, then the split-precision colour sum of every row
+    const int64_t chunk = split_chunk(h, nevt);
+    const int npar = h->desc->npar;
+    for (int64_t off = 0; off < nevt; off += chunk) {
+      const int64_t n = std::min<int64_t>(chunk, nevt - off);
+      double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
+      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
+                      h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}, 1};
+      if (h->timing)
+        for (int k = 0; k < 3; ++k) a.ev[k] = mark_event(h, s);
+      hipError_t e = h->desc->split(a);
+      if (e != hipSuccess) return hip_fail(e, "split kernels launch");
+      if (h->timing && a.ev[0] && a.ev[1] && a.ev[2]) {
+        h->timed.push_back({ME_KT_DIAGRAM, a.ev[0], a.ev[1]});
+        h->timed.push_back({ME_KT_FLOWS, a.ev[1], a.ev[2]});
+      }
+      me::ColourArgs ca{jt, n * nhel, fmt_mc, h->d_cf_hi, h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
+      KernelMark kc(h, ME_KT_COLOUR, s);
+      e = h->desc->colour(ca);
+      if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+      kc.done();
+      KernelMark kr(h, ME_KT_REDUCE, s);
+      hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                         h->d_partial, nhel, n, 1.0 / h->desc->iden, out_me2 + off);
+      kr.done();
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    }
+    return ME_OK;
+  }
   // matrix-core colour sum: stage the dual amplitudes of an event chunk, one row per
   // (helicity, event), then colour-sum every row and reduce over helicities
   const int ncol = h->desc->ncol;
@@ -749,7 +783,7 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
   const size_t row_doubles = (size_t)ncol * 2;
   int64_t chunk = (int64_t)(ME_JAMP_SCRATCH_BYTES / (sizeof(double) * row_doubles * nhel));
   chunk = std::min<int64_t>(std::max<int64_t>(64, (chunk / 64) * 64), nevt);
-  const int fmt = h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1;
+  const int fmt = fmt_mc;
   for (int64_t off = 0; off < nevt; off += chunk) {
     const int64_t n = std::min<int64_t>(chunk, nevt - off);
     me::LaunchArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, 1, nhel,

@@ -175,11 +175,17 @@ hipError_t launch(const LaunchArgs& a) {
 template <class P>
 hipError_t launch_colour(const ColourArgs& a) {
   const dim3 grid((unsigned)((a.nrow + 15) / 16));
-  if (a.fmt == CS_FMT_FP16)
+  if (a.fmt == CS_FMT_FP16 && !a.transposed)
     hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_FP16>), grid, dim3(64), 0, a.stream,
                        a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
-  else
+  else if (!a.transposed)
     hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_BF16>), grid, dim3(64), 0, a.stream,
+                       a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
+  else if (a.fmt == CS_FMT_FP16)
+    hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_FP16, true>), grid, dim3(64), 0, a.stream,
+                       a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
+  else
+    hipLaunchKernelGGL((colour_mfma_kernel<P::NCOL, CS_FMT_BF16, true>), grid, dim3(64), 0, a.stream,
                        a.jamps, a.nrow, a.cf_hi, a.cf_lo, a.inv_den, a.out);
   return hipGetLastError();
 }
@@ -287,6 +293,7 @@ hipError_t launch_split(const SplitArgs& a) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.ev[2]) (void)hipEventRecord(a.ev[2], a.stream);
+  if (a.flows_only) return hipSuccess;
   constexpr int RPB = 4 * 8 * COLOUR_F64_TILES;   // rows per tile of the colour kernel
   const int64_t tiles = (rows + RPB - 1) / RPB;
   hipLaunchKernelGGL(colour_f64_kernel<P::NCOL>, dim3((unsigned)std::min<int64_t>(tiles, COLOUR_F64_GRID)),

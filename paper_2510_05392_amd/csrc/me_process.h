@@ -35,6 +35,7 @@ struct ColourArgs {
   double inv_den;       // 1 / CF denominator
   double* out;          // device, [nrow]
   hipStream_t stream;
+  int transposed;       // jamps laid out [2 ncol][nrow] (the split executor's flows)
 };
 
 using ColourLauncher = hipError_t (*)(const ColourArgs&);
@@ -85,6 +86,7 @@ struct SplitArgs {
   const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
   hipStream_t stream;
   hipEvent_t ev[4];      // recorded before the first, between, and after the last kernel, or nullptr
+  int flows_only;        // stop after the flows (a matrix-core colour sum of jt follows)
 };
 
 using SplitLauncher = hipError_t (*)(const SplitArgs&);

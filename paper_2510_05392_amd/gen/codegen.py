@@ -221,7 +221,8 @@ class Emitter:
             self.emit_object(key)
             done.add(key)
 
-        for gi, (key, members) in enumerate(self.plan.scheduled_groups()):
+        order = self.plan.split_groups() if split else self.plan.scheduled_groups()
+        for gi, (key, members) in enumerate(order):
             if groups is not None and gi not in groups:
                 continue
             first_lead = members[0][0]
@@ -253,7 +254,7 @@ class Emitter:
         (acc[2 lk] real, acc[2 lk + 1] imaginary part of local flow lk); chunk c holds
         groups [c chunk, (c + 1) chunk) of the order amplitudes() stores them in, group
         c chunk + gl at b[2 gl 64] (real) and b[(2 gl + 1) 64] (imaginary)."""
-        groups = self.plan.scheduled_groups()
+        groups = self.plan.split_groups()
         fpw = -(-len(self.plan.basis) // nwave)
         nch = -(-len(groups) // chunk)
         lines = [f"  switch (w * {nch} + c) {{"]

@@ -147,3 +147,12 @@ def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels, parts):
     meh = h.split_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels)
     ref = ome.me_helicities(ome.process(npar), mom, AS, hels)
     assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
+
+
+@pytest.mark.parametrize('n', [3, 4, 5])
+def test_split_group_order_is_a_permutation(n):
+    # the split executor's group order only reorders the scheduled groups
+    plan = topology.Plan(n)
+    a, b = plan.scheduled_groups(), plan.split_groups()
+    assert len(a) == len(b)
+    assert sorted(map(repr, a)) == sorted(map(repr, b))

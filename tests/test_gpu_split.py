@@ -26,8 +26,8 @@ def binding():
     return b
 
 
-def _run(binding, name, mom, executor, alphas=None, graph=False):
-    m = binding.MatrixElement(name, use_graph=graph)
+def _run(binding, name, mom, executor, alphas=None, graph=False, mode=0):
+    m = binding.MatrixElement(name, use_graph=graph, colorsum_mode=mode)
     m.me_set_executor(executor)
     d = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
     out = torch.empty(len(mom), dtype=torch.float64, device='cuda')
@@ -91,7 +91,7 @@ def test_split_deterministic_alphas_and_graph(binding):
 
 
 @pytest.mark.parametrize('executor,mode,expect', [(2, 0, [1, 1, 1, 1]), (0, 0, [1, 0, 0, 1]), (1, 0, [1, 0, 0, 1]),
-                                                  (0, 1, [1, 0, 1, 1])])
+                                                  (0, 1, [1, 0, 1, 1]), (2, 1, [1, 1, 1, 1])])
 def test_kernel_timing(binding, executor, mode, expect):
     # per-kernel events: one launch per kernel class of a one-chunk call, durations
     # positive, results equal to an untimed call (also on a graph handle, which runs
@@ -114,3 +114,36 @@ def test_kernel_timing(binding, executor, mode, expect):
     m.me_set_kernel_timing(False)
     assert np.array_equal(m.compute(d, AS).cpu().numpy(), ref)
     assert m.me_kernel_times()[1] == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize('mode', [1, 2])
+def test_split_flows_into_matrix_core_colour_sum(binding, mode):
+    # the split executor's flows ([2 ncol][rows] layout) into the split-FP16 / BF16
+    # matrix-core colour sum: within 1e-5 of the oracle, and equal to the one-lane
+    # kernel's matrix-core result up to the rounding of the flows
+    _say(f'case split flows into matrix-core colour sum, mode {mode}')
+    g = _golden('gg_ttxggg_seed1003_first197.npz')
+    mom = rambo.generate(7, 197, 1003)
+    split = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_SPLIT, mode=mode)
+    lane = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_LANE, mode=mode)
+    rel = np.abs(split / g['me_ext'] - 1)
+    _say(f'  max rel err vs oracle {rel.max():.2e}; vs lane {np.max(np.abs(split / lane - 1)):.2e}')
+    assert rel.max() < 1e-5
+    assert np.max(np.abs(split / lane - 1)) < 1e-6
+    for name, npar, n in (('gg_ttx', 4, 77), ('gg_ttxgg', 6, 131)):
+        mom = rambo.generate(npar, n, 31)
+        a = _run(binding, name, mom, binding.ME_EXEC_SPLIT, mode=mode)
+        b = _run(binding, name, mom, binding.ME_EXEC_SPLIT)
+        assert np.max(np.abs(a / b - 1)) < 1e-5
+
+
+def test_split_matrix_core_full_size(binding):
+    # the benchmark workload through the split executor with the split-FP16 colour sum
+    # (many event chunks, graph replay) against the FP64 split executor
+    _say('case split + FP16 colour sum, full size ggttggg 262144')
+    mom = rambo.generate(7, 262144, 1003)
+    a = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_SPLIT, mode=1, graph=True)
+    b = _run(binding, 'gg_ttxggg', mom, binding.ME_EXEC_SPLIT)
+    rel = np.abs(a / b - 1)
+    _say(f'  max rel {rel.max():.2e}')
+    assert rel.max() < 1e-5
