@@ -215,37 +215,50 @@ __global__ void __launch_bounds__(256) colour_f64_kernel(const double* __restric
     const double* x[NT];
     bool valid[NT];
     int64_t row[NT];
-  #pragma unroll
+#pragma unroll
     for (int t = 0; t < NT; ++t) {
       row[t] = (wave * NT + t) * 8 + (j & 7);
       valid[t] = row[t] < nrow;
       x[t] = jt + (int64_t)part * nrow + (valid[t] ? row[t] : 0);
     }
     f64x4 acc[NT][MB];
-  #pragma unroll
+#pragma unroll
     for (int t = 0; t < NT; ++t)
-  #pragma unroll
+#pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // B operands of steps ks + 1 and ks + 2 are loaded while step ks runs
+    auto ldb = [&](int kk, double* bb) {
+      const int cc = 4 * kk + kq;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bb[t] = (kk < KS && cc < NCOL && valid[t]) ? x[t][(int64_t)(2 * cc) * nrow] : 0.0;
+    };
+    double b1[NT], b2[NT];
+    ldb(0, b1);
+    ldb(1, b2);
     for (int ks = 0; ks < KS; ++ks) {
       const int c = 4 * ks + kq;
       double b[NT];
-  #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = (c < NCOL && valid[t]) ? x[t][(int64_t)(2 * c) * nrow] : 0.0;
-  #pragma unroll
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        b[t] = b1[t];
+        b1[t] = b2[t];
+      }
+      ldb(ks + 2, b2);
+#pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const double a = (double)cfs[(16 * mb + j) * KPS + c];
-  #pragma unroll
+#pragma unroll
         for (int t = 0; t < NT; ++t) acc[t][mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[t][mb], 0, 0, 0);
       }
     }
-  #pragma unroll
+#pragma unroll
     for (int t = 0; t < NT; ++t) {
       // row dot products sum_i X[j][i] D[i][j], then over the four lane groups and
       // over the real and imaginary parts of the row
       double s = 0.0;
-  #pragma unroll
+#pragma unroll
       for (int mb = 0; mb < MB; ++mb)
-  #pragma unroll
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = 16 * mb + 4 * v + kq;
           if (i < NCOL && valid[t]) s += x[t][(int64_t)(2 * i) * nrow] * acc[t][mb][v];

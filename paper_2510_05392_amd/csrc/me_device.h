@@ -24,6 +24,12 @@ struct cx {
 };
 
 __device__ __forceinline__ cx mk(double r, double i) { return cx{r, i}; }
+// An opaque copy of v: two copies are never merged, and nothing computed from one
+// is moved across the point where it is made.
+__device__ __forceinline__ double opaque(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 __device__ __forceinline__ cx operator+(cx a, cx b) { return cx{a.r + b.r, a.i + b.i}; }
 __device__ __forceinline__ cx operator-(cx a, cx b) { return cx{a.r - b.r, a.i - b.i}; }
 __device__ __forceinline__ cx operator-(cx a) { return cx{-a.r, -a.i}; }

@@ -258,16 +258,23 @@ __global__ void __launch_bounds__(256) flows_kernel(const double* __restrict__ s
 #pragma unroll
     for (int i = 0; i < PER; ++i) buf[bi][(w + 4 * i) * 64 + lane] = st[i];
   };
+  double st2[PER];
   load(0);
   put(0);
+  if (NCH > 1) load(1);
   __syncthreads();
   for (int c = 0; c < NCH; ++c) {
-    // the next chunk's loads are in flight while this chunk's updates run; one
-    // barrier per chunk suffices because a buffer is rewritten only after every
-    // wave has passed the barrier that ends its last use
-    if (c + 1 < NCH) load(c + 1);
+    // chunk c + 1 waits in registers and chunk c + 2 is loading while chunk c's
+    // updates run; one barrier per chunk suffices because a buffer is rewritten only
+    // after every wave has passed the barrier that ends its last use
+#pragma unroll
+    for (int i = 0; i < PER; ++i) st2[i] = st[i];
+    if (c + 2 < NCH) load(c + 2);
     P::flow_chunk(w, c, &buf[c & 1][lane], acc);
-    if (c + 1 < NCH) put((c + 1) & 1);
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) buf[(c + 1) & 1][(w + 4 * i) * 64 + lane] = st2[i];
+    }
     __syncthreads();
   }
   if (!ok) return;

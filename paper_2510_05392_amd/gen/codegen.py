@@ -42,9 +42,14 @@ def _cx(c):
 
 
 class Emitter:
-    def __init__(self, name, plan: Plan):
+    def __init__(self, name, plan: Plan, remat=False):
+        """remat: recompute each momentum sum from the external momenta at every use
+        (through an opaque copy, so that the compiler keeps them apart) instead of
+        keeping it live from its first use."""
         self.name = name
         self.plan = plan
+        self.remat = remat
+        self.nremat = 0
         self.n = plan.n
         self.npar = self.n + 2
         self.lines = []
@@ -61,7 +66,12 @@ class Emitter:
     def mom(self, mask):
         """Name of the momentum flowing into the diagram through the gluons of `mask`."""
         name = f"P{mask}"
-        if mask in self.masks_done:
+        if self.remat and bin(mask).count('1') == 1 and (mask & 3):
+            return f"p[{slot_particle(mask.bit_length() - 1)}]"   # an incoming momentum itself
+        if self.remat:
+            self.nremat += 1
+            name = f"P{mask}_{self.nremat}"
+        elif mask in self.masks_done:
             return name
         self.masks_done.add(mask)
         terms = []
@@ -76,6 +86,10 @@ class Emitter:
                 expr = expr[2:]
             elif expr.startswith('- '):
                 expr = '-' + expr[2:]
+            if self.remat:
+                # the first term through an opaque copy: no two sums are merged
+                first = f"p[{terms[0][1]}][{u}]"
+                expr = expr.replace(first, f"opaque({first})", 1)
             comps.append(expr)
         self.lines.append(f"  const double {name}[4] = {{{', '.join(comps)}}};")
         return name
@@ -149,7 +163,10 @@ class Emitter:
 
     def negmom(self, mask):
         name = f"N{mask}"
-        if mask in self.neg_done:
+        if self.remat:
+            self.nremat += 1
+            name = f"N{mask}_{self.nremat}"
+        elif mask in self.neg_done:
             return name
         self.neg_done.add(mask)
         pm = self.mom(mask)
@@ -316,6 +333,8 @@ FLOW_CHUNK = 16
 # currents per kernel, less spill traffic); SUMS_WPE waves per SIMD for them.
 SUMS_PARTS = {}
 SUMS_WPE = {'gg_ttxggg': 2}
+# momentum sums recomputed at each use in the group-sum code (Emitter remat)
+SUMS_REMAT = {}
 
 # Largest process that also gets the one-lane-per-(event, helicity) code; beyond
 # it the straight-line function would be too large to compile in reasonable
@@ -327,8 +346,9 @@ def part_ranges(ngroup, nparts):
     return [range(k * ngroup // nparts, (k + 1) * ngroup // nparts) for k in range(nparts)]
 
 
-def generate(name, sums_parts=None, sums_wpe=None):
+def generate(name, sums_parts=None, sums_wpe=None, remat=None):
     npar = PROCESS_NPAR[name]
+    remat = SUMS_REMAT.get(name, False) if remat is None else remat
     n = npar - 2
     plan = Plan(n)
     cf, den = colour_matrix(n)
@@ -339,8 +359,8 @@ def generate(name, sums_parts=None, sums_wpe=None):
     ngroup = len(plan.scheduled_groups())
     nparts = sums_parts or SUMS_PARTS.get(name, 1)
     wpe = sums_wpe or SUMS_WPE.get(name, 1)
-    parts = [Emitter(name, plan).amplitudes(split=True, groups=r) for r in part_ranges(ngroup, nparts)] \
-        if lane else []
+    parts = [Emitter(name, plan, remat=remat).amplitudes(split=True, groups=r)
+             for r in part_ranges(ngroup, nparts)] if lane else []
     assemble = Emitter(name, plan).flow_chunks(FLOW_WAVES, FLOW_CHUNK) if lane else []
     team_src, _ = team_gen.emit(name, plan)
     out = []

@@ -11,13 +11,13 @@ CSRC = os.path.join(ROOT, 'paper_2510_05392_amd', 'csrc')
 OUT = os.path.join(ROOT, '_build', 'cpu_harness')
 
 
-def build(name, opt='-O1', sums_parts=None):
-    """sums_parts: number of group-sum parts of the split executor (default: the
-    generator's choice for the process)."""
+def build(name, opt='-O1', sums_parts=None, remat=None):
+    """sums_parts: number of group-sum parts of the split executor; remat: momentum
+    sums recomputed at each use in them (defaults: the generator's choice)."""
     from paper_2510_05392_amd.gen import codegen
     os.makedirs(OUT, exist_ok=True)
-    src, _, _ = codegen.generate(name, sums_parts=sums_parts)
-    tag = f'{name}_p{sums_parts}' if sums_parts else name
+    src, _, _ = codegen.generate(name, sums_parts=sums_parts, remat=remat)
+    tag = name + (f'_p{sums_parts}' if sums_parts else '') + ('' if remat is None else f'_r{int(remat)}')
     hdr = os.path.join(OUT, f'{tag}.inc')
     if not os.path.exists(hdr) or open(hdr).read() != src:
         with open(hdr, 'w') as f:

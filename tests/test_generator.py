@@ -134,14 +134,16 @@ def test_team_program_slots_and_schedule():
                 assert a1 > b0, (s, rs)
 
 
-@pytest.mark.parametrize('name,npar,nevt,opt,hels,parts', [
-    ('gg_ttx', 4, 16, '-O1', None, None), ('gg_ttxg', 5, 8, '-O1', None, None),
-    ('gg_ttxgg', 6, 4, '-O1', None, None), ('gg_ttxgg', 6, 4, '-O1', None, 3),
-    ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127), None)])
-def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels, parts):
-    # colour-group sums stored per row (by the group-sum parts in turn), then the
-    # flows formed from them chunk by chunk, compiled for the host
-    h = harness.build(name, opt, sums_parts=parts)
+@pytest.mark.parametrize('name,npar,nevt,opt,hels,parts,remat', [
+    ('gg_ttx', 4, 16, '-O1', None, None, None), ('gg_ttxg', 5, 8, '-O1', None, None, None),
+    ('gg_ttxgg', 6, 4, '-O1', None, None, None), ('gg_ttxgg', 6, 4, '-O1', None, 3, None),
+    ('gg_ttxgg', 6, 4, '-O1', None, None, True),
+    ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127), None, None)])
+def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels, parts, remat):
+    # colour-group sums stored per row (by the group-sum parts in turn, with momentum
+    # sums kept or recomputed at each use), then the flows formed from them chunk by
+    # chunk, compiled for the host
+    h = harness.build(name, opt, sums_parts=parts, remat=remat)
     mom = rambo.generate(npar, nevt, 7)
     hels = list(range(2 ** npar)) if hels is None else list(hels)
     meh = h.split_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels)
