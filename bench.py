@@ -30,7 +30,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # only for the kernel they were taken on.
 MEASURED_TRAFFIC = {
     ('gg_ttxggg', 262144, (1, 1, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
-    ('gg_ttxggg', 262144, (0, 0, 2)): (6.107e10, 'profiles/sums_kernel_gg_ttxggg_262144.md'),
+    ('gg_ttxggg', 262144, (0, 0, 2)): (1.127e11, 'profiles/sums_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}

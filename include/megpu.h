@@ -72,7 +72,7 @@ extern "C" {
 /* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 /* device scratch of the split executor's colour-group sums and colour flows */
-#define ME_SPLIT_SCRATCH_BYTES (8ull << 30)
+#define ME_SPLIT_SCRATCH_BYTES (16ull << 30)
 
 typedef struct me_ctx* me_handle;
 

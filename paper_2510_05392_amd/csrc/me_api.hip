@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <set>
 #include <string>
 #include <vector>
@@ -223,12 +224,19 @@ int ensure_sums(me_ctx* c, size_t n) {
 
 // Events per chunk of the split executor: the group sums and the colour flows of a
 // chunk (2 NGROUP + 2 NCOL doubles per row, nhel rows per event) fill at most
-// ME_SPLIT_SCRATCH_BYTES.
+// ME_SPLIT_SCRATCH_BYTES.  Where the limit allows, the chunk is a whole number of
+// rounds of the group-sum kernel's waves (chunk / 64 x nhel wavefronts, a multiple
+// of the SIMDs x its waves per SIMD), so that no launch ends on a part-filled round.
 int64_t split_chunk(const me_ctx* h, int64_t nevt) {
-  const size_t per_event =
-      sizeof(double) * 2 * (size_t)(h->desc->ngroup + h->desc->ncol) * h->good.size();
+  const int64_t nhel = (int64_t)h->good.size();
+  const size_t per_event = sizeof(double) * 2 * (size_t)(h->desc->ngroup + h->desc->ncol) * (size_t)nhel;
   int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
-  chunk = std::max<int64_t>(64, (chunk / 64) * 64);
+  const int64_t slots = (int64_t)h->simds * std::max(1, h->desc->sums_wpe);
+  const int64_t step = 64 * (slots / std::gcd(slots, nhel));
+  if (chunk >= step)
+    chunk = (chunk / step) * step;
+  else
+    chunk = std::max<int64_t>(64, (chunk / 64) * 64);
   return std::min<int64_t>(chunk, nevt);
 }
 

@@ -317,14 +317,15 @@ template <class P>
 const ProcessDesc* describe(SplitLauncher split) {
   Launcher lane = nullptr;
   ColourLauncher colour = &launch_colour<P>;
-  int ngroup = 0;
+  int ngroup = 0, sums_wpe = 1;
   if constexpr (P::LANE) {
     lane = &launch<P>;
     ngroup = P::NGROUP;
+    sums_wpe = P::SUMS_WPE;
   }
   static const ProcessDesc d = {P::NAME,   P::NPAR,  P::NCOL,     P::NHEL, P::IDEN,
                                 P::CF_DEN, P::NDIAG, P::cf_int(), lane,    colour,
-                                &launch_team<typename P::Team>, 64 / P::Team::T, split, ngroup};
+                                &launch_team<typename P::Team>, 64 / P::Team::T, split, ngroup, sums_wpe};
   return &d;
 }
 

@@ -101,6 +101,7 @@ struct ProcessDesc {
   int team_events_per_block;  // events per workgroup of the team executor (64 / lanes per team)
   SplitLauncher split;        // split executor (group sums, then flows + colour sum), or nullptr
   int ngroup;                 // colour groups (group sums per row of the split executor)
+  int sums_wpe;               // waves per SIMD of the split executor's group-sum kernel
 };
 
 }  // namespace me

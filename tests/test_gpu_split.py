@@ -61,7 +61,7 @@ def test_split_ggttggg_golden(binding):
 
 
 def test_split_full_size_multi_chunk(binding):
-    # the benchmark workload (60 event chunks of the group-sum scratch), sampled
+    # the benchmark workload (several event chunks of the group-sum scratch), sampled
     # events against the oracle, and gg->ttgg at 524288 events against the lane executor
     _say('case split full size ggttggg 262144')
     mom = rambo.generate(7, 262144, 1003)
