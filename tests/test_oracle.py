@@ -49,6 +49,30 @@ def test_colour_coefficients_are_units():
                 assert c in (1, -1, 1j, -1j)
 
 
+# --- normalisation -------------------------------------------------------------
+
+@pytest.mark.parametrize("npar,expect", [(4, 256), (5, 256), (6, 512), (7, 1536), (8, 6144)])
+def test_iden_average_and_symmetry_factor(npar, expect):
+    """IDEN = (initial helicity states) x (initial colour states) x (symmetry
+    factor of identical final-state particles), reading of the normalisation
+    (the paper leaves it implicit in its ME engine).  The values are the
+    convention's (4 * 64 * k!), and the symmetry factor is recounted here by
+    brute force: the permutations of the final-state species list
+    (t, tbar, g, ..., g) that leave it unchanged.
+
+    Mutation caught: dropping the k! factor in ``colour.iden`` (every k >= 2
+    fails), or averaging over the final instead of the initial states."""
+    k = npar - 4
+    final = ('t', 'tbar') + ('g',) * k
+    sym = sum(1 for perm in itertools.permutations(range(len(final)))
+              if tuple(final[i] for i in perm) == final)
+    initial_hel = 2 * 2                      # two gluons, two helicities each
+    initial_col = 8 * 8                      # two gluons, eight colours each
+    assert initial_hel * initial_col * sym == expect
+    assert colour.iden(npar) == expect
+    assert me.process(npar).iden == expect
+
+
 # --- colour matrix -----------------------------------------------------------
 
 def test_colour_matrix_two_gluons_exact():

@@ -106,3 +106,76 @@ def test_two_stage_unweighting_is_unbiased():
     got1 = np.histogram(x[acc1], edges, weights=res1)[0]
     chi2b = (((got1 / got1.sum() - expect) ** 2) / (expect / got1.sum())).sum()
     assert chi2b < 30
+
+
+def test_adam_three_steps_against_unrolled_sums():
+    """Three Adam steps against the textbook moments written as explicit sums
+    over the gradient history, m_t = (1-b1) sum_s b1^(t-s) g_s and likewise v_t
+    with g^2, bias-corrected with the step count t = 1, 2, 3.
+
+    Mutations caught: a step counter that never advances (bias correction of
+    step 1 reused), moments that are overwritten instead of decayed, and b1/b2
+    swapped between the two moments."""
+    rng = np.random.default_rng(11)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 0.05
+    params = _params(rng, [3, 2, 1])
+    p0 = [(w.copy(), b.copy()) for w, b in params]
+    hist = [[(rng.normal(size=w.shape), rng.normal(size=b.shape)) for w, b in params]
+            for _ in range(3)]
+    st = S.adam_state(params)
+    expect = [[w.copy(), b.copy()] for w, b in p0]
+    for t in (1, 2, 3):
+        S.adam_step(params, hist[t - 1], st, lr=lr, b1=b1, b2=b2, eps=eps)
+        for li in range(len(params)):
+            for which in (0, 1):
+                gs = [hist[s - 1][li][which] for s in range(1, t + 1)]
+                m = (1 - b1) * sum(b1 ** (t - s) * g for s, g in zip(range(1, t + 1), gs))
+                v = (1 - b2) * sum(b2 ** (t - s) * g * g for s, g in zip(range(1, t + 1), gs))
+                mh = m / (1 - b1 ** t)
+                vh = v / (1 - b2 ** t)
+                expect[li][which] = expect[li][which] - lr * mh / (np.sqrt(vh) + eps)
+        for (w, b), (ew, eb) in zip(params, expect):
+            assert np.allclose(w, ew, rtol=1e-13, atol=1e-15)
+            assert np.allclose(b, eb, rtol=1e-13, atol=1e-15)
+    assert st['t'] == 3
+
+
+def test_two_stage_overweights_with_quantile_maxima():
+    """Two-stage unweighting with maxima below the largest weights (as the
+    calibration quantiles do), on a toy where every probability is a multiple
+    of 1/8 and each event meets the 8 x 8 grid of random numbers
+    ((i + 1/2)/8, (j + 1/2)/8): event e is then accepted exactly
+    64 p1(e) p2(e) times, p1 = min(1, w_hat/w_hat_max), p2 = min(1, x/x_max),
+    x = w/w_hat.  Known exactly:
+      * the number of accepted events,
+      * the overweights (residual > 1): the accepts of the events with
+        w_hat > w_hat_max or x > x_max,
+      * the residual-weight sum, 64 sum_e w_e / (w_hat_max x_max): each accept
+        carries max(1, w_hat/w_hat_max) max(1, x/x_max), so accept count times
+        residual is 64 (w_hat/w_hat_max)(x/x_max) for every event (unbiased).
+
+    Mutations caught: dropping either max(1, .) factor of the residual weight
+    (the sum then falls short), using min instead of max, or forgetting to
+    divide the exact weight by the surrogate weight in stage 2."""
+    w_hat = np.array([1.0, 2.0, 3.0, 6.0, 2.0, 6.0])
+    x = np.array([0.5, 1.0, 2.0, 3.0, 3.0, 0.5])
+    w = w_hat * x
+    what_max, x_max = 4.0, 2.0                  # below max(w_hat) = 6, max(x) = 3
+    grid = (np.arange(8) + 0.5) / 8
+    r1 = np.repeat(np.tile(grid, 8)[None, :], len(w), 0).reshape(-1)
+    r2 = np.repeat(np.repeat(grid, 8)[None, :], len(w), 0).reshape(-1)
+    ev = np.repeat(np.arange(len(w)), 64)
+    acc, resid, idx = S.two_stage(w_hat[ev], lambda i: w[ev[i]], r1, r2, what_max, x_max)
+    p1 = np.minimum(1, w_hat / what_max)
+    p2 = np.minimum(1, x / x_max)
+    n_acc = 64 * p1 * p2
+    assert acc.sum() == int(round(n_acc.sum()))
+    # stage 1 needs the exact weight only for its own accepts
+    assert len(idx) == int(round(8 * (8 * p1).sum()))
+    over = (w_hat > what_max) | (x > x_max)
+    assert (resid > 1).sum() == int(round(n_acc[over].sum()))
+    assert np.isclose(resid.sum(), 64 * w.sum() / (what_max * x_max), rtol=1e-14)
+    # per event: every accepted copy carries the same residual
+    for e in range(len(w)):
+        r = resid[ev[acc] == e]
+        assert np.allclose(r, max(1, w_hat[e] / what_max) * max(1, x[e] / x_max))
