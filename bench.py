@@ -99,11 +99,11 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None)
     t_train = time.perf_counter() - t0
     del train
     val = torch.from_numpy(rambo.generate(npar, min(32768, args.sur_cal), 2003)).cuda()
-    err = pipe.log_error(val)
+    rms, worst = pipe.log_error(val)
     calm, calw = rambo.generate(npar, args.sur_cal, 2005, return_weights=True)
     dcal, dcw = torch.from_numpy(calm).cuda(), torch.from_numpy(calw).cuda()
     what_max, x_max = pipe.calibrate(dcal, dcw, quantile=0.99)
-    w_max = float(torch.quantile(pipe.exact(dcal) * dcw, 0.99))
+    w_max = pipe.exact_weight_max(dcal, dcw, 0.99)
     _, wps = rambo.generate(npar, nevt, SEED[process], return_weights=True)
     dw = torch.from_numpy(wps).cuda()
     g = torch.Generator(device='cuda').manual_seed(7)
@@ -118,10 +118,15 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None)
                       + ('split-FP16' if exact_mode == binding.ME_CS_FP16X2 else 'FP64') + ' exact |M|^2 stage 2',
             'n_events': nevt, 'stage1_events': two['stage1'], 'exact_calls_saved': 1 - two['stage1'] / nevt,
             'accepted': two['accepted'], 'overweights': two['overweight'],
+            'overweight_fraction': two['overweight'] / max(1, two['accepted']),
+            'effective_sample_size': two['ess'],
+            'ess_value': two['ess'] / two['time_total'],
             'one_stage_accepted': one['accepted'], 'one_stage_value': nevt / one['time_total'],
+            'one_stage_effective_sample_size': one['ess'],
+            'one_stage_ess_value': one['ess'] / one['time_total'],
             'unweighting_efficiency': two['accepted'] / nevt,
             'one_stage_efficiency': one['accepted'] / nevt,
-            'rms_log_error': float(np.sqrt(np.mean(err ** 2))), 'train_events': args.sur_train,
+            'rms_log_error': rms, 'max_log_error': worst, 'train_events': args.sur_train,
             'maxima': f'0.99 quantiles of a {args.sur_cal}-event calibration sample '
                       '(events above: residual weights > 1)',
             'train_epochs': args.sur_epochs, 'train_seconds': t_train, 'final_mse': hist[-1],

@@ -13,9 +13,15 @@
  * summed, as in the paper's helicity filtering.
  *
  * Conventions shared by all entry points
- *   process   "gg_ttx", "gg_ttxg", "gg_ttxgg", "gg_ttxggg" (k = 0..3 final gluons)
+ *   process   "gg_ttx", "gg_ttxg", "gg_ttxgg", "gg_ttxggg", "gg_ttxgggg" (k = 0..4
+ *             final gluons; the paper's complexity table lists them with their
+ *             diagram, helicity and colour counts)
  *   momenta   device pointer, float64 [nevt][npar][4], (E, px, py, pz) in GeV,
- *             particle order g g t tbar g ...; the two beams along +-z
+ *             particle order g g t tbar g ...; the two beams along +-z.  This is
+ *             the caller's layout (the paper's engine takes 4 npar values per
+ *             event); the one-lane kernels read a structure-of-arrays copy
+ *             [npar][4][nevt] that the library writes first, so that the 64
+ *             lanes of a wavefront load 64 consecutive doubles
  *   outputs   device pointers, float64, owned by the caller
  *   stream    hipStream_t cast to void*, or NULL for the handle's stream (the
  *             null stream); all work is enqueued on it, nothing synchronises
@@ -78,11 +84,25 @@ typedef struct me_ctx* me_handle;
 
 typedef struct {
   double mt;            /* top mass in GeV (default 173.0); gluons are massless */
+  double wt;            /* top width in GeV (default 0).  Only 0 is accepted: the width is
+                           zero in every propagator (internal top lines of these processes
+                           never go on shell, and a zero width keeps the amplitudes exactly
+                           gauge invariant); any other value is ME_EINVAL */
   int colorsum_mode;    /* ME_CS_* (default ME_CS_FP64) */
   int all_helicities;   /* 1: skip the filter and sum all 2^npar helicities (default 0) */
   int use_graph;        /* 1: capture the launch sequence of me_compute in a hipGraph on the first
                            call with given (momenta, out, nevt, alpha_s) and replay it afterwards */
+  int check;            /* 1: every me_compute / me_compute_alphas / me_compute_host first checks
+                           its events (see ME_CHECK_TOL) and synchronises the stream; default 0,
+                           or 1 when the environment variable ME_CHECK is set to 1 */
 } me_params;
+
+/* Input check (me_params.check): an event fails when its four-momentum is not
+ * conserved, |sum_in p - sum_out p|_mu > ME_CHECK_TOL * sqrt(s) for some mu, or
+ * a particle is off shell, |p^2 - m^2| > ME_CHECK_TOL * E^2 (m = mt for t and
+ * tbar, 0 for gluons).  The call then returns ME_EINVAL naming the first
+ * failing event and writes no output. */
+#define ME_CHECK_TOL 1e-9
 
 /* Fill *p with the defaults. */
 int me_params_default(me_params* p);
@@ -91,14 +111,28 @@ int me_params_default(me_params* p);
  * "gg_ttxgggg": g g -> t tbar + 0..4 gluons); p may be NULL for the defaults.
  * Allocates small device tables; the helicity filter runs on the first
  * me_compute call unless me_filter_helicities was called first.  Unknown
- * process or mode: ME_EINVAL. */
+ * process or mode, mt <= 0 or wt != 0: ME_EINVAL.  (The paper's engine is
+ * built for one process: section "A closer look at the internals of the ME
+ * engine".) */
 int me_init(const char* process, const me_params* p, me_handle* out);
 
 /* out_me2[i] = helicity- and colour-summed, initial-state averaged |M|^2 of
  * event i, in GeV^(8 - 2 npar); alpha_s is a fixed scalar (g = sqrt(4 pi alpha_s)).
- * nevt = 0 is a no-op.  Results are bit-reproducible for a fixed nevt. */
+ * nevt = 0 is a no-op.  Results are bit-reproducible for a fixed nevt.  This is
+ * the paper's engine contract (momenta of nevt events in, one ME per event out;
+ * section "A closer look at the internals of the ME engine" and its pseudo-code
+ * of the monolithic kernel: loop over helicities, diagrams into the dual
+ * amplitudes, colour sum, running sum over helicities). */
 int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                double* out_me2, void* stream);
+
+/* As me_compute on host memory: momenta[nevt][npar][4] and out_me2[nevt] are
+ * host pointers (the caller's).  The library allocates device copies, computes
+ * on the handle's stream and copies the result back before returning (it
+ * synchronises).  For tests and small callers; the device-pointer me_compute is
+ * the fast path. */
+int me_compute_host(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
+                    double* out_me2);
 
 /* As me_compute with a running coupling: alpha_s[i] (device, [nevt]) is the
  * strong coupling of event i, g_i = sqrt(4 pi alpha_s[i]) (the paper's engine
@@ -107,6 +141,28 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
  * alpha_s = 0.118 (which helicities contribute does not depend on it). */
 int me_compute_alphas(me_handle h, const double* momenta, int64_t nevt, const double* alpha_s,
                       double* out_me2, void* stream);
+
+/* Single-diagram-enhancement channel weights (the paper's engine also takes an
+ * event-by-event channel identifier for MadEvent's single-diagram-enhanced
+ * multichannel integration: section "A closer look at the internals of the ME
+ * engine"; its complexity table counts the channels, the diagrams built from
+ * three-point vertices only: 3, 15, 105, 945 for k = 0..3).  With chan[i] in
+ * 1..nchan (device, int32 [nevt]):
+ *   num[i] = sum_h |A_chan(h)|^2,  den[i] = sum_h sum_c |A_c(h)|^2,
+ * A_c the colour-stripped amplitude of channel diagram c (colour coefficients
+ * +-1, +-i), h over the good helicities; the channel weight is num / den.
+ * Channels are numbered in ascending order of the tuple, from the top end of
+ * the quark line, of their gluon trees written as strings (a leaf is its gluon
+ * slot 0..k+1, a three-gluon vertex "(" + its children's strings, sorted,
+ * joined by "," + ")").  chan outside 1..nchan gives num = 0.  Outputs are
+ * device arrays of nevt doubles.  Processes without the one-lane code
+ * (gg_ttxgggg) have no channel kernel: ME_EINVAL. */
+int me_channel_weights(me_handle h, const double* momenta, int64_t nevt, double alpha_s, const int32_t* chan,
+                       double* num, double* den, void* stream);
+
+/* Number of single-diagram-enhancement channels of the handle's process (0 when
+ * it has no channel kernel). */
+int me_num_channels(me_handle h, int32_t* nchan);
 
 /* Helicity and colour selection for event output (the paper's engine returns
  * one helicity and one leading colour per event, drawn with two random
@@ -124,39 +180,55 @@ int me_compute_alphas(me_handle h, const double* momenta, int64_t nevt, const do
 int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, const double* r_hel,
               const double* r_col, double* out_me2, int32_t* sel_hel, int32_t* sel_col, void* stream);
 
-/* Helicity filter (the paper's good-helicity selection): evaluates every
- * helicity on the first min(nevt, 16) events and keeps h when
- * max_events ME_h / ME > 1e-14.  Synchronises the stream. */
+/* Helicity filter (the paper's good-helicity selection, which its complexity
+ * table and the section on the internals of the ME engine describe as a
+ * sequential first pass; here one parallel launch): evaluates every helicity on
+ * the first min(nevt, 16) events and keeps h when max_events ME_h / ME > 1e-14.
+ * Synchronises the stream.  Drops a captured graph. */
 int me_filter_helicities(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                          void* stream);
 
 /* Copy the good helicity indices (ascending) into idx[cap] (host); *n_out gets
- * their number.  Before filtering this is the full list. */
+ * their number.  Before filtering this is the full list.  (The helicities the
+ * paper's monolithic kernel loops over.)  idx may be NULL to query the count;
+ * cap smaller than the count is ME_EINVAL. */
 int me_good_helicities(me_handle h, int32_t* idx, int32_t cap, int32_t* n_out);
 
-/* Process sizes: particles, colour flows, helicity combinations, diagrams. */
+/* Process sizes: particles, colour flows, helicity combinations, diagrams (the
+ * columns of the paper's complexity table).  Any pointer may be NULL. */
 int me_info(me_handle h, int32_t* npar, int32_t* ncolor, int32_t* nhel, int32_t* ndiag);
 
-/* Exact colour matrix CF = cf_int / denom; cf_int[ncolor*ncolor] (host), cap >= ncolor^2. */
+/* Exact colour matrix CF = cf_int / denom (the integer matrix and denominator
+ * of the paper's colour-sum equation, section "Color sum as a separate GPU
+ * kernel"); cf_int[ncolor*ncolor] (host, row-major), cap >= ncolor^2 else
+ * ME_EINVAL. */
 int me_colour_matrix(me_handle h, int32_t* cf_int, int32_t cap, int32_t* denom);
 
 /* Per-helicity colour sums sum_ij conj(J_i) CF_ij J_j (not divided by IDEN) for
- * the nh helicities hels[] (host array): out[k][nevt] (device). */
+ * the nh helicities hels[] (host array): out[k][nevt] (device).  (One term of
+ * the running helicity sum of the monolithic kernel's pseudo-code.)  Helicity
+ * indices outside [0, 2^npar) are ME_EINVAL. */
 int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                      const int32_t* hels, int32_t nh, double* out, void* stream);
 
 /* Dual amplitudes J_i(h) for the helicities hels[] (host): out[k][nevt][ncolor][2]
  * (device, re/im interleaved), colour flows in lexicographic order of the
- * gluon permutations. */
+ * gluon permutations.  (The jamp array that the pseudo-code of the monolithic
+ * kernel fills from the Feynman diagrams before the colour sum.) */
 int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
              const int32_t* hels, int32_t nh, double* out, void* stream);
 
 /* Switch the colour-sum arithmetic of a handle (ME_CS_*).  In the matrix-core
  * modes the dual amplitudes of up to ME_JAMP_SCRATCH_BYTES are staged in a
- * library-owned device buffer between the diagram and colour-sum kernels. */
+ * library-owned device buffer between the diagram and colour-sum kernels.  (The
+ * paper's colour sum on tensor cores and in mixed precision: sections "Color
+ * sum dispatcher to kernel or BLAS" and "Tensor core profiling".)  Setting the
+ * current mode again is a no-op; a change drops a captured graph; on failure
+ * the handle keeps its previous mode and tables. */
 int me_set_colorsum_mode(me_handle h, int mode);
 
-/* Launch configuration of the FP64 path: persistent = 1 runs a grid of
+/* Launch configuration of the FP64 path (the paper's helicity streams and
+ * grid sizes are the prior art: section "Helicity streams"): persistent = 1 runs a grid of
  * waves_per_simd x (4 x compute units) wavefronts that take work items
  * (64-event tile, hel_per_item helicities; 0 = all) from an atomic counter;
  * persistent = 0 launches one workgroup per item, splitting the helicities so
@@ -164,14 +236,17 @@ int me_set_colorsum_mode(me_handle h, int mode);
  * the configuration beyond rounding order of the helicity sum. */
 int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_item, int target_waves);
 
-/* Executor of the diagrams (ME_EXEC_LANE, ME_EXEC_TEAM or ME_EXEC_SPLIT); all give
+/* Executor of the diagrams (the paper's kernel splitting into diagram groups,
+ * sections "Feynman diagram groups as kernels" and "Diagram groups as device
+ * functions", is the prior art) (ME_EXEC_LANE, ME_EXEC_TEAM or ME_EXEC_SPLIT); all give
  * the same |M|^2 up to rounding order.  In the matrix-core colour-sum modes
  * ME_EXEC_SPLIT runs the split executor's group sums and flows before the matrix-core
  * colour sum, the other two the one-lane (or team) diagram kernel.  The team executor uses the helicity
  * chunking of the grid path (target_waves of me_set_launch). */
 int me_set_executor(me_handle h, int executor);
 
-/* Per-kernel timing, for measurement.  While on, me_compute runs eagerly (no graph
+/* Per-kernel timing, for measurement (the paper profiles each kernel of the split
+ * engine the same way, section "Color sum profiling").  While on, me_compute runs eagerly (no graph
  * replay) and brackets every kernel it launches with events on the caller's stream,
  * classed as ME_KT_DIAGRAM (me_kernel, team_kernel or sums_kernel: the diagrams of
  * every (event, helicity)), ME_KT_FLOWS (flows_kernel), ME_KT_COLOUR (matrix-core
@@ -188,7 +263,9 @@ int me_set_executor(me_handle h, int executor);
 int me_set_kernel_timing(me_handle h, int on);
 int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
 
-/* Autotuner: times a fixed set of launch configurations (and, in ME_CS_FP64 mode,
+/* Autotuner (the paper scans diagrams per group and kernel splitting by hand,
+ * section "Studies of a 2->6 process"; here the library times the candidates).
+ * Times a fixed set of launch configurations (and, in ME_CS_FP64 mode,
  * both executors) on these events (writing out_me2, synchronising the stream)
  * and keeps the fastest; best[5] (host, may be NULL) receives (persistent,
  * waves_per_simd, hel_per_item, target_waves, executor). */
@@ -211,12 +288,14 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
 int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* momenta,
                      const int64_t* nevts, double alpha_s, double* const* outs, void* stream);
 
-/* Release the handle and everything it owns.  Finalising a handle twice, or
- * using it afterwards, returns ME_ESTATE; passing NULL is a no-op. */
+/* Release the handle and everything it owns (device tables, scratch, graph,
+ * streams, events).  Finalising a handle twice, or using it afterwards, returns
+ * ME_ESTATE; passing NULL is a no-op.  Work still queued on the caller's stream
+ * must have finished (the library does not synchronise it). */
 int me_finalize(me_handle h);
 
 /* ---------------------------------------------------------------- surrogate
- * A multilayer perceptron predicting the normalised log|M|^2 from the pair
+ * (An addition: the paper has no surrogate.)  A multilayer perceptron predicting the normalised log|M|^2 from the pair
  * invariants log(2 p_i.p_j / s) (i < j, normalised with a per-feature mean and
  * inverse standard deviation), trained by mean squared error with Adam, and
  * the two-stage unweighting that uses it (stage 1 on the surrogate weight,
@@ -276,6 +355,51 @@ int me_gather_momenta(const double* momenta, const int64_t* idx, int64_t m, int 
 int me_unweight_stage2(const double* me_exact, const int64_t* idx, int64_t m, const double* wps,
                        const double* what, const double* r2, double what_max, double x_max, double* resid,
                        void* stream);
+
+/* Introspection for tests: the activations of the last forward pass (me_sur_predict
+ * or me_sur_grads; of the last chunk of 65536 rows for larger predictions), first
+ * `rows` rows, copied to host[rows][n]: kind 0 = the input of linear layer `layer`
+ * (BF16 values as FP32, n = its input width; layer 0 = the feature rows), kind 1 =
+ * its output before the activation (FP32, n = its output width).  Synchronises the
+ * device. */
+int me_sur_activations(me_surrogate s, int layer, int kind, int64_t rows, float* host);
+
+/* Normalisation of the surrogate's inputs and target from a training sample
+ * (features of momenta as me_sur_features writes them in raw[n][nfeat], exact
+ * |M|^2 in me2[n], device): sets the per-feature mean and inverse standard
+ * deviation (1 / max(std, 1e-6)) of the handle and returns the mean and
+ * standard deviation of log|M|^2 in *ymean, *ystd (host).  Population moments,
+ * summed in FP64 in a fixed order.  Synchronises the stream. */
+int me_sur_fit_normalisation(me_surrogate s, const float* raw, int64_t n, const double* me2, double* ymean,
+                             double* ystd, void* stream);
+/* Training targets target[i] = (log me2[i] - ymean) / ystd (FP32, device). */
+int me_sur_targets(const double* me2, int64_t n, double ymean, double ystd, float* target, void* stream);
+/* One epoch's order of the training set: feat_out[r] = feat[perm[r]] (rows of
+ * kpad BF16 values), target_out[r] = target[perm[r]] (all device; perm int64). */
+int me_sur_gather_rows(const uint16_t* feat, const float* target, const int64_t* perm, int64_t n, int kpad,
+                       uint16_t* feat_out, float* target_out, void* stream);
+/* Surrogate RMS and largest absolute error of log|M|^2: d = y ystd + ymean -
+ * log me2 over n events; *rms, *max_abs (host).  Synchronises the stream. */
+int me_sur_log_error(const float* y, const double* me2, int64_t n, double ymean, double ystd, double* rms,
+                     double* max_abs, void* stream);
+/* Maxima of the two-stage unweighting from a calibration sample: with w_hat =
+ * exp(y ystd + ymean) wps and x = me2 wps / w_hat, *what_max and *x_max (host)
+ * are their q-quantiles (linear interpolation between the order statistics at
+ * q (n - 1)); q >= 1 gives the maxima.  Synchronises the stream. */
+int me_unweight_maxima(const float* y, const double* wps, const double* me2, int64_t n, double ymean, double ystd,
+                       double q, double* what_max, double* x_max, void* stream);
+/* q-quantile (as above) of the exact weights w = me2 wps: *w_max (host). */
+int me_unweight_quantile(const double* me2, const double* wps, int64_t n, double q, double* w_max, void* stream);
+/* One-stage unweighting on exact weights (the method without a surrogate):
+ * w = me2 wps, accept when r[i] < min(1, w / w_max); resid[i] = max(1, w / w_max)
+ * when accepted, 0 otherwise (device arrays of n). */
+int me_unweight_onestage(const double* me2, const double* wps, const double* r, int64_t n, double w_max,
+                         double* resid, void* stream);
+/* Summary of residual weights resid[m] (0 = rejected): accepted and overweight
+ * (> 1) counts, sum and sum of squares of the weights (host outputs); the Kish
+ * effective sample size is sum_w^2 / sum_w2.  Synchronises the stream. */
+int me_unweight_summary(const double* resid, int64_t m, int64_t* n_acc, int64_t* n_over, double* sum_w,
+                        double* sum_w2, void* stream);
 
 /* Message for the last error on this thread ("" if none). */
 const char* me_last_error(void);

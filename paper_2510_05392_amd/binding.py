@@ -29,15 +29,17 @@ ME_EXEC_SPLIT = 2
 ME_KT_DIAGRAM, ME_KT_FLOWS, ME_KT_COLOUR, ME_KT_REDUCE = 0, 1, 2, 3
 ME_KT_KINDS = 4
 
-EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_filter_helicities',
+EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_compute_host', 'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
            'me_compute_alphas', 'me_select', 'me_set_executor', 'me_set_kernel_timing',
-           'me_kernel_times', 'me_finalize',
+           'me_kernel_times', 'me_finalize', 'me_channel_weights', 'me_num_channels',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
            'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
            'me_unweight_stage1', 'me_gather_momenta', 'me_unweight_stage2',
+           'me_sur_fit_normalisation', 'me_sur_activations', 'me_sur_targets', 'me_sur_gather_rows', 'me_sur_log_error',
+           'me_unweight_maxima', 'me_unweight_quantile', 'me_unweight_onestage', 'me_unweight_summary',
            'me_last_error']
 
 
@@ -48,8 +50,8 @@ class MeError(RuntimeError):
 
 
 class me_params(ctypes.Structure):
-    _fields_ = [('mt', ctypes.c_double), ('colorsum_mode', ctypes.c_int),
-                ('all_helicities', ctypes.c_int), ('use_graph', ctypes.c_int)]
+    _fields_ = [('mt', ctypes.c_double), ('wt', ctypes.c_double), ('colorsum_mode', ctypes.c_int),
+                ('all_helicities', ctypes.c_int), ('use_graph', ctypes.c_int), ('check', ctypes.c_int)]
 
 
 class me_sur_params(ctypes.Structure):
@@ -72,6 +74,8 @@ def load(path=LIB_PATH):
     lib.me_params_default.argtypes = [ctypes.POINTER(me_params)]
     lib.me_init.argtypes = [ctypes.c_char_p, ctypes.POINTER(me_params), ctypes.POINTER(vp)]
     lib.me_compute.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
+    lib.me_compute_host.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.me_filter_helicities.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     lib.me_good_helicities.argtypes = [vp, i32p, ctypes.c_int32, i32p]
     lib.me_info.argtypes = [vp, i32p, i32p, i32p, i32p]
@@ -87,6 +91,8 @@ def load(path=LIB_PATH):
     lib.me_set_executor.argtypes = [vp, ctypes.c_int]
     lib.me_select.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.me_finalize.argtypes = [vp]
+    lib.me_channel_weights.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp]
+    lib.me_num_channels.argtypes = [vp, i32p]
     fp, dbl = ctypes.POINTER(ctypes.c_float), ctypes.c_double
     lib.me_sur_init.argtypes = [ctypes.POINTER(me_sur_params), ctypes.POINTER(vp)]
     lib.me_sur_finalize.argtypes = [vp]
@@ -103,6 +109,16 @@ def load(path=LIB_PATH):
     lib.me_unweight_stage1.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, vp, vp, ctypes.POINTER(i64), vp]
     lib.me_gather_momenta.argtypes = [vp, vp, i64, ctypes.c_int, vp, vp]
     lib.me_unweight_stage2.argtypes = [vp, vp, i64, vp, vp, vp, dbl, dbl, vp, vp]
+    dblp, i64p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)
+    lib.me_sur_fit_normalisation.argtypes = [vp, vp, i64, vp, dblp, dblp, vp]
+    lib.me_sur_targets.argtypes = [vp, i64, dbl, dbl, vp, vp]
+    lib.me_sur_activations.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64, fp]
+    lib.me_sur_gather_rows.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, vp, vp]
+    lib.me_sur_log_error.argtypes = [vp, vp, i64, dbl, dbl, dblp, dblp, vp]
+    lib.me_unweight_maxima.argtypes = [vp, vp, vp, i64, dbl, dbl, dbl, dblp, dblp, vp]
+    lib.me_unweight_quantile.argtypes = [vp, vp, i64, dbl, dblp, vp]
+    lib.me_unweight_onestage.argtypes = [vp, vp, vp, i64, dbl, vp, vp]
+    lib.me_unweight_summary.argtypes = [vp, i64, i64p, i64p, dblp, dblp, vp]
     lib.me_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = ctypes.c_int
@@ -141,14 +157,17 @@ class MatrixElement:
     """One handle of the C ABI for one process."""
 
     def __init__(self, process: str, mt: float = 173.0, all_helicities: bool = False,
-                 colorsum_mode: int = ME_CS_FP64, use_graph: bool = False):
+                 colorsum_mode: int = ME_CS_FP64, use_graph: bool = False, check=None, wt: float = 0.0):
         lib = load()
         p = me_params()
         _check(lib.me_params_default(ctypes.byref(p)))
         p.mt = mt
+        p.wt = wt
         p.all_helicities = int(all_helicities)
         p.colorsum_mode = int(colorsum_mode)
         p.use_graph = int(use_graph)
+        if check is not None:
+            p.check = int(bool(check))
         h = ctypes.c_void_p()
         _check(lib.me_init(process.encode(), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -160,6 +179,16 @@ class MatrixElement:
     # the binding names mirror the C entry points
     def me_compute(self, momenta, nevt, alpha_s, out, stream=None):
         _check(load().me_compute(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream)))
+
+    def me_compute_host(self, momenta, alpha_s):
+        """Host-pointer variant: momenta is a C-contiguous float64 numpy array [nevt][npar][4]."""
+        import numpy as np
+        mom = np.ascontiguousarray(momenta, dtype=np.float64)
+        out = np.zeros(mom.shape[0], dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().me_compute_host(self._h, mom.ctypes.data_as(dp), mom.shape[0], alpha_s,
+                                      out.ctypes.data_as(dp)))
+        return out
 
     def me_compute_alphas(self, momenta, nevt, alpha_s, out, stream=None):
         _check(load().me_compute_alphas(self._h, _ptr(momenta), nevt, _ptr(alpha_s), _ptr(out),
@@ -194,6 +223,15 @@ class MatrixElement:
         arr = (ctypes.c_int32 * len(hels))(*hels)
         _check(load().me_jamps(self._h, _ptr(momenta), nevt, alpha_s, arr, len(hels),
                                _ptr(out), _stream(stream)))
+
+    def me_channel_weights(self, momenta, nevt, alpha_s, chan, num, den, stream=None):
+        _check(load().me_channel_weights(self._h, _ptr(momenta), nevt, alpha_s, _ptr(chan), _ptr(num), _ptr(den),
+                                         _stream(stream)))
+
+    def me_num_channels(self):
+        n = ctypes.c_int32()
+        _check(load().me_num_channels(self._h, ctypes.byref(n)))
+        return n.value
 
     def me_set_launch(self, persistent, waves_per_simd=1, hel_per_item=0, target_waves=4096):
         _check(load().me_set_launch(self._h, persistent, waves_per_simd, hel_per_item, target_waves))
@@ -289,6 +327,22 @@ class Surrogate:
         s, ps = self._host(inv_std)
         _check(load().me_sur_set_normalisation(self._h, pm, ps))
 
+    def me_sur_fit_normalisation(self, raw, n, me2, stream=None):
+        """Sets the feature normalisation from raw[n][nfeat]; returns (ymean, ystd) of log|M|^2."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(load().me_sur_fit_normalisation(self._h, _ptr(raw), n, _ptr(me2), ctypes.byref(a), ctypes.byref(b),
+                                               _stream(stream)))
+        return a.value, b.value
+
+    def me_sur_activations(self, layer, kind, rows):
+        """Input (kind 0) or pre-activation output (kind 1) of linear layer `layer` in the last forward pass."""
+        import numpy as np
+        n = (self.nfeat if layer == 0 else self.width) if kind == 0 else (1 if layer == self.depth else self.width)
+        out = np.zeros((rows, n), dtype=np.float32)
+        _check(load().me_sur_activations(self._h, layer, kind, rows,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
     def me_sur_features(self, momenta, nevt, npar, feat, raw=None, stream=None):
         _check(load().me_sur_features(self._h, _ptr(momenta), nevt, npar, _ptr(feat), _ptr(raw),
                                       _stream(stream)))
@@ -333,3 +387,47 @@ def me_gather_momenta(momenta, idx, m, npar, out, stream=None):
 def me_unweight_stage2(me_exact, idx, m, wps, what, r2, what_max, x_max, resid, stream=None):
     _check(load().me_unweight_stage2(_ptr(me_exact), _ptr(idx), m, _ptr(wps), _ptr(what), _ptr(r2),
                                      what_max, x_max, _ptr(resid), _stream(stream)))
+
+
+def me_sur_targets(me2, n, ymean, ystd, target, stream=None):
+    _check(load().me_sur_targets(_ptr(me2), n, ymean, ystd, _ptr(target), _stream(stream)))
+
+
+def me_sur_gather_rows(feat, target, perm, n, kpad, feat_out, target_out, stream=None):
+    _check(load().me_sur_gather_rows(_ptr(feat), _ptr(target), _ptr(perm), n, kpad, _ptr(feat_out),
+                                     _ptr(target_out), _stream(stream)))
+
+
+def me_sur_log_error(y, me2, n, ymean, ystd, stream=None):
+    """(RMS, largest absolute) error of the surrogate's log|M|^2."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(load().me_sur_log_error(_ptr(y), _ptr(me2), n, ymean, ystd, ctypes.byref(a), ctypes.byref(b),
+                                   _stream(stream)))
+    return a.value, b.value
+
+
+def me_unweight_maxima(y, wps, me2, n, ymean, ystd, q, stream=None):
+    """(what_max, x_max): q-quantiles of the surrogate weight and of the exact/surrogate ratio."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(load().me_unweight_maxima(_ptr(y), _ptr(wps), _ptr(me2), n, ymean, ystd, q, ctypes.byref(a),
+                                     ctypes.byref(b), _stream(stream)))
+    return a.value, b.value
+
+
+def me_unweight_quantile(me2, wps, n, q, stream=None):
+    a = ctypes.c_double()
+    _check(load().me_unweight_quantile(_ptr(me2), _ptr(wps), n, q, ctypes.byref(a), _stream(stream)))
+    return a.value
+
+
+def me_unweight_onestage(me2, wps, r, n, w_max, resid, stream=None):
+    _check(load().me_unweight_onestage(_ptr(me2), _ptr(wps), _ptr(r), n, w_max, _ptr(resid), _stream(stream)))
+
+
+def me_unweight_summary(resid, m, stream=None):
+    """(accepted, overweights, sum of weights, sum of squared weights)."""
+    a, o = ctypes.c_int64(), ctypes.c_int64()
+    s1, s2 = ctypes.c_double(), ctypes.c_double()
+    _check(load().me_unweight_summary(_ptr(resid), m, ctypes.byref(a), ctypes.byref(o), ctypes.byref(s1),
+                                      ctypes.byref(s2), _stream(stream)))
+    return a.value, o.value, s1.value, s2.value

@@ -26,6 +26,7 @@ LIB = os.path.join(HERE, 'libmegpu.so')
 PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg', 'gg_ttxgggg']
 # headers the generated process units include
 PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h', 'me_team.h']
+SDE_HEADERS = ['me_sde.h', 'me_sde_desc.h']
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
@@ -68,6 +69,18 @@ def generate_sources(procs, build_dir):
             _write_if_changed(spath, split)
             units.append((spath, os.path.join(OBJ, f'split_{name}.o'),
                           [inc] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
+            # single-diagram-enhancement channel sums: generated code of their own,
+            # in a unit of their own
+            sde_src, _ = codegen.generate_sde(name)
+            sinc = os.path.join(GEN, f'{name}_sde.inc')
+            _write_if_changed(sinc, sde_src)
+            sde = (f'// Single-diagram-enhancement kernel of process {name} (generated).\n'
+                   f'#include "{name}_sde.inc"\n#include "me_sde.h"\n'
+                   f'namespace me {{\nconst SdeDesc* sde_{name}() {{ return describe_sde<me::{name}_sde>(); }}\n}}\n')
+            sdepath = os.path.join(GEN, f'sde_{name}.hip')
+            _write_if_changed(sdepath, sde)
+            units.append((sdepath, os.path.join(OBJ, f'sde_{name}.o'),
+                          [sinc] + [os.path.join(CSRC, h) for h in PROC_HEADERS + SDE_HEADERS]))
         else:
             unit = (f'// Kernels and descriptor of process {name} (generated).\n'
                     f'#include "{name}.inc"\n#include "me_kernels.h"\n'
@@ -91,6 +104,10 @@ def generate_sources(procs, build_dir):
             break
         lane.append(n)
     reg.append(f'static const int kNumBatchProcesses = {len(lane)};')
+    # single-diagram-enhancement kernels, aligned with kProcesses (none without one-lane code)
+    reg += [f'const SdeDesc* sde_{n}();' for n in lane]
+    reg.append('static const SdeDesc* (*const kSde[])() = {'
+               + ', '.join(f'sde_{n}' if n in lane else 'nullptr' for n in procs) + '};')
     batch = ['// Multi-process batch kernel over the processes of this library (generated).']
     batch += [f'#include "{n}.inc"' for n in lane]
     batch += ['#include "me_kernels.h"', 'namespace me {',
@@ -105,7 +122,7 @@ def generate_sources(procs, build_dir):
                      [os.path.join(GEN, f'{n}.inc') for n in lane] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
                   [regfile, os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_process.h'),
-                   os.path.join(CSRC, 'me_error.h')]))
+                   os.path.join(CSRC, 'me_error.h'), os.path.join(CSRC, 'me_sde_desc.h')]))
     units.append((os.path.join(CSRC, 'surrogate.hip'), os.path.join(OBJ, 'surrogate.o'),
                   [os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_error.h')]))
     return units
@@ -114,10 +131,16 @@ def generate_sources(procs, build_dir):
 def _compile(src, obj, extra_deps, build_dir, force=False):
     deps = [src] + list(extra_deps)
     flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') or src.startswith(build_dir) else [])
-    key = hashlib.sha1((' '.join(flags) + HIPCC).encode()).hexdigest()[:8]
+    # the object is reused only when the flags and the contents of every input are
+    # those it was compiled from (contents, not modification times: a source edited
+    # while its object was compiling must not pass for up to date)
+    h = hashlib.sha1((' '.join(flags) + HIPCC).encode())
+    for d in deps:
+        with open(d, 'rb') as f:
+            h.update(f.read())
+    key = h.hexdigest()[:16]
     stamp = obj + '.flags'
-    if (not force and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key
-            and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps)):
+    if not force and os.path.exists(obj) and os.path.exists(stamp) and open(stamp).read() == key:
         return obj, False
     # the resource-usage remarks (registers, spills, occupancy) are kept next to the object
     cmd = [HIPCC, *flags, '-Rpass-analysis=kernel-resource-usage', '-c', src, '-o', obj + '.tmp']

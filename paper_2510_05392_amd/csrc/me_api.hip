@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -18,6 +20,7 @@
 #include "megpu.h"
 #include "me_error.h"
 #include "me_process.h"
+#include "me_sde_desc.h"
 
 namespace me {
 #include "registry.inc"   // const ProcessDesc* (*const kProcesses[])() and kNumProcesses
@@ -55,6 +58,50 @@ __global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nch
 }
 
 __global__ void zero_counter_kernel(int* c) { *c = 0; }
+
+// Caller layout [nevt][np4] -> structure of arrays [np4][nevt] (np4 = 4 npar);
+// thread e reads its event's np4 consecutive doubles and writes one double per
+// row, so every store of a wavefront is 64 consecutive doubles.
+__global__ void aos_to_soa_kernel(const double* __restrict__ aos, int64_t nevt, int np4,
+                                  double* __restrict__ soa) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  const double* src = aos + e * np4;
+  for (int c = 0; c < np4; ++c) soa[(int64_t)c * nevt + e] = src[c];
+}
+
+// Input check (ME_CHECK_TOL): momentum conservation of g g -> t tbar + gluons
+// (particles 0, 1 incoming) and the mass shells (mt for particles 2, 3, massless
+// otherwise).  bad[0] counts failing events, bad[1] keeps the smallest failing
+// index (integer atomics on a small device record, no floating-point atomics).
+__global__ void check_kernel(const double* __restrict__ mom, int64_t nevt, int npar, double mt,
+                             double tol, unsigned long long* __restrict__ bad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  const double* p = mom + e * npar * 4;
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  bool ok = true;
+  for (int q = 0; q < npar; ++q) {
+    const double* v = p + 4 * q;
+    const double sgn = q < 2 ? 1.0 : -1.0;
+    for (int u = 0; u < 4; ++u) sum[u] += sgn * v[u];
+    const double m = (q == 2 || q == 3) ? mt : 0.0;
+    const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+    if (!(fabs(m2 - m * m) <= tol * v[0] * v[0]) || !(v[0] > 0.0)) ok = false;
+  }
+  const double rs = p[0] + p[4];   // sqrt(s) for beams along +-z
+  for (int u = 0; u < 4; ++u)
+    if (!(fabs(sum[u]) <= tol * rs)) ok = false;
+  if (!ok) {
+    atomicAdd(&bad[0], 1ull);
+    atomicMin(&bad[1], (unsigned long long)e);
+  }
+}
+
+__global__ void check_reset_kernel(unsigned long long* bad) {
+  bad[0] = 0ull;
+  bad[1] = ~0ull;
+}
 
 // Inverse-CDF draw over non-negative weights w[k * stride + e], k = 0..n-1, in
 // ascending k: the first k whose running sum exceeds r * total; when rounding
@@ -110,6 +157,7 @@ __global__ void select_col_kernel(const double* __restrict__ jamps, int ncol, in
 struct me_ctx {
   const me::ProcessDesc* desc = nullptr;
   int proc_index = 0;         // position in the library's process list (batch kernel)
+  const me::SdeDesc* sde = nullptr;  // single-diagram-enhancement kernel, or nullptr
   me_params params{};
   std::vector<int> good;      // host copy of the good helicities
   int* d_hels = nullptr;      // device, good helicities (capacity nhel)
@@ -121,6 +169,9 @@ struct me_ctx {
   double* d_sums = nullptr;   // colour-group sums, then colour flows, of the split executor
   size_t sums_cap = 0;        // doubles
   double* d_cf64 = nullptr;   // colour matrix for the split executor's FP64 matrix-core colour form
+  double* d_soa = nullptr;    // structure-of-arrays copy of the momenta [npar][4][nevt]
+  size_t soa_cap = 0;         // doubles
+  unsigned long long* d_check = nullptr;  // input check record (count, first failing event)
   // per-kernel timing (me_set_kernel_timing): recorded (class, start, stop) events
   bool timing = false;
   struct Timed { int kind; hipEvent_t a, b; };
@@ -222,6 +273,22 @@ int ensure_sums(me_ctx* c, size_t n) {
   return ensure_buffer(&c->d_sums, &c->sums_cap, n, "group sums");
 }
 
+int ensure_soa(me_ctx* c, int64_t nevt) {
+  const size_t n = (size_t)nevt * c->desc->npar * 4;
+  if (n <= c->soa_cap) return ME_OK;
+  drop_graph(c);
+  return ensure_buffer(&c->d_soa, &c->soa_cap, n, "momenta (structure of arrays)");
+}
+
+// Enqueue the structure-of-arrays copy of nevt events (capacity ensured before).
+int enqueue_soa(me_ctx* c, const double* momenta, int64_t nevt, hipStream_t s) {
+  hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s, momenta, nevt,
+                     c->desc->npar * 4, c->d_soa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "momentum layout kernel launch");
+  return ME_OK;
+}
+
 // Events per chunk of the split executor: the group sums and the colour flows of a
 // chunk (2 NGROUP + 2 NCOL doubles per row, nhel rows per event) fill at most
 // ME_SPLIT_SCRATCH_BYTES.  Where the limit allows, the chunk is a whole number of
@@ -300,9 +367,13 @@ void free_tables(me_ctx* c) {
 }
 
 // Colour matrix tables for the matrix-core modes: [32*MB][16*KS] zero padded.
+// The new tables are built first and replace the old ones only on success, so a
+// failure leaves the handle's mode and tables as they were.
 int build_tables(me_ctx* c, int mode) {
-  free_tables(c);
-  if (mode == ME_CS_FP64) return ME_OK;
+  if (mode == ME_CS_FP64) {
+    free_tables(c);
+    return ME_OK;
+  }
   const int n = c->desc->ncol;
   const int kp = ((n + 15) / 16) * 16, mp = ((n + 31) / 32) * 32;
   std::vector<uint16_t> hi((size_t)mp * kp, 0), lo((size_t)mp * kp, 0);
@@ -327,16 +398,22 @@ int build_tables(me_ctx* c, int mode) {
       hi[(size_t)i * kp + k] = bh;
       lo[(size_t)i * kp + k] = bl;
     }
-  hipError_t e = hipMalloc(&c->d_cf_hi, hi.size() * 2);
-  if (e == hipSuccess) e = hipMemcpy(c->d_cf_hi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
+  void* d_hi = nullptr;
+  void* d_lo = nullptr;
+  hipError_t e = hipMalloc(&d_hi, hi.size() * 2);
+  if (e == hipSuccess) e = hipMemcpy(d_hi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess && split) {
-    e = hipMalloc(&c->d_cf_lo, lo.size() * 2);
-    if (e == hipSuccess) e = hipMemcpy(c->d_cf_lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+    e = hipMalloc(&d_lo, lo.size() * 2);
+    if (e == hipSuccess) e = hipMemcpy(d_lo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
-    free_tables(c);
+    if (d_hi) (void)hipFree(d_hi);
+    if (d_lo) (void)hipFree(d_lo);
     return hip_fail(e, "colour-matrix tables");
   }
+  free_tables(c);
+  c->d_cf_hi = d_hi;
+  c->d_cf_lo = d_lo;
   return ME_OK;
 }
 
@@ -411,9 +488,12 @@ extern "C" {
 int me_params_default(me_params* p) {
   if (!p) return fail(ME_EINVAL, "null params");
   p->mt = 173.0;
+  p->wt = 0.0;
   p->colorsum_mode = ME_CS_FP64;
   p->all_helicities = 0;
   p->use_graph = 0;
+  const char* env = std::getenv("ME_CHECK");
+  p->check = (env && std::strcmp(env, "1") == 0) ? 1 : 0;
   return ME_OK;
 }
 
@@ -434,11 +514,13 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   me_params_default(&prm);
   if (p) prm = *p;
   if (!(prm.mt > 0.0)) return fail(ME_EINVAL, "mt must be positive");
+  if (prm.wt != 0.0) return fail(ME_EINVAL, "only a zero top width is implemented (wt must be 0)");
   if (!valid_mode(prm.colorsum_mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
   me_ctx* c = new (std::nothrow) me_ctx;
   if (!c) return fail(ME_ENOMEM, "host allocation failed");
   c->desc = desc;
   c->proc_index = proc_index;
+  c->sde = me::kSde[proc_index] ? me::kSde[proc_index]() : nullptr;
   c->params = prm;
   if (!desc->launch) c->executor = ME_EXEC_TEAM;
   c->good.resize(desc->nhel);
@@ -469,10 +551,12 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
       c->simds = 4 * cus;
   }
   if (hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->d_check, 2 * sizeof(unsigned long long)) != hipSuccess ||
       hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipFree(c->d_hels);
     (void)hipFree(c->d_scratch_hels);
     if (c->d_counter) (void)hipFree(c->d_counter);
+    if (c->d_check) (void)hipFree(c->d_check);
     if (c->d_cf64) (void)hipFree(c->d_cf64);
     free_tables(c);
     delete c;
@@ -503,6 +587,8 @@ int me_finalize(me_handle h) {
   release_timed(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->d_counter) (void)hipFree(h->d_counter);
+  if (h->d_check) (void)hipFree(h->d_check);
+  if (h->d_soa) (void)hipFree(h->d_soa);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   free_tables(h);
@@ -557,9 +643,16 @@ int me_helicity_sums(me_handle h, const double* momenta, int64_t nevt, double al
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
+  if (h->desc->launch) {
+    rc = ensure_soa(h, nevt);
+    if (rc == ME_OK) rc = enqueue_soa(h, momenta, nevt, s);
+    if (rc) return rc;
+  }
   // one helicity per chunk: the per-chunk partial sums are the per-helicity sums
   me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, out,
                    nullptr, s};
+  a.soa = h->d_soa;
+  a.mstride = nevt;
   hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
   if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
   const int64_t n = nevt * nh;
@@ -580,8 +673,15 @@ int me_jamps(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   hipStream_t s = (hipStream_t)stream;
   rc = upload_scratch_hels(h, hels, nh, s);
   if (rc) return rc;
+  if (h->desc->launch) {
+    rc = ensure_soa(h, nevt);
+    if (rc == ME_OK) rc = enqueue_soa(h, momenta, nevt, s);
+    if (rc) return rc;
+  }
   me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_scratch_hels, nh, 1, nh, nullptr,
                    out, s};
+  a.soa = h->d_soa;
+  a.mstride = nevt;
   hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
   if (e != hipSuccess) return hip_fail(e, "jamp kernel launch");
   return ME_OK;
@@ -620,6 +720,8 @@ int me_filter_helicities(me_handle h, const double* momenta, int64_t nevt, doubl
     if (best > 1e-14) good.push_back(k);
   }
   if (good.empty()) return fail(ME_EINVAL, "no helicity contributes on the test events");
+  // a captured graph holds the old helicity count
+  drop_graph(h);
   h->good = good;
   h->filtered = true;
   return upload_good(h, s);
@@ -630,6 +732,12 @@ namespace {
 // Size the scratch of one me_compute call (outside any capture).
 int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
+  if (h->desc->launch) {
+    // the one-lane kernels (lane and split executors) read the momenta as a
+    // structure of arrays
+    int rc = ensure_soa(h, nevt);
+    if (rc) return rc;
+  }
   if (h->executor == ME_EXEC_SPLIT) {
     // every colour-sum mode: group sums and flows of an event chunk
     const int64_t chunk = split_chunk(h, nevt);
@@ -655,6 +763,25 @@ int prepare(me_ctx* h, int64_t nevt) {
   return ensure_partial(h, (size_t)chunk * nhel);
 }
 
+// Input check of me_params.check: momentum conservation and mass shells of every
+// event (ME_CHECK_TOL).  Synchronises the stream; ME_EINVAL names the first
+// failing event.
+int run_check(me_ctx* h, const double* momenta, int64_t nevt, hipStream_t s) {
+  hipLaunchKernelGGL(check_reset_kernel, dim3(1), dim3(1), 0, s, h->d_check);
+  hipLaunchKernelGGL(check_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s, momenta, nevt,
+                     h->desc->npar, h->params.mt, ME_CHECK_TOL, h->d_check);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "input check launch");
+  unsigned long long bad[2] = {0, 0};
+  e = hipMemcpyAsync(bad, h->d_check, sizeof(bad), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "input check readback");
+  if (bad[0] != 0)
+    return fail(ME_EINVAL, "input check: " + std::to_string(bad[0]) + " event(s) violate momentum conservation "
+                "or the mass shells, the first is event " + std::to_string(bad[1]));
+  return ME_OK;
+}
+
 // Enqueue the kernels of one me_compute call on stream s (capturable: no
 // allocation, no synchronisation, no memset; with per-kernel timing on it records
 // events and is not captured).
@@ -662,6 +789,10 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
             hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
+  if (h->desc->launch && !(h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_TEAM)) {
+    int rc = enqueue_soa(h, momenta, nevt, s);
+    if (rc) return rc;
+  }
   if (h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_SPLIT) {
     // event chunks: group sums of every (helicity, event) row, then flows and the
     // colour form per row, then the fixed-order helicity sum of the chunk
@@ -672,7 +803,7 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       const int64_t n = std::min<int64_t>(chunk, nevt - off);
       // flows after the group sums of a full chunk
       double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
-      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
+      me::SplitArgs a{h->d_soa + off, nevt, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
                       h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}};
       // with timing on, the launcher records a.ev[k] before kernel k (sums, flows,
       // colour form) and a.ev[3] after the last; the events are marked here (taken
@@ -733,6 +864,8 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, hpc, nchunk,
                      h->d_partial, nullptr, s};
     a.alphas = alphas;
+    a.soa = h->d_soa;
+    a.mstride = nevt;
     if (h->persistent) {
       hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, h->d_counter);
       a.counter = h->d_counter;
@@ -760,7 +893,7 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     for (int64_t off = 0; off < nevt; off += chunk) {
       const int64_t n = std::min<int64_t>(chunk, nevt - off);
       double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
-      me::SplitArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
+      me::SplitArgs a{h->d_soa + off, nevt, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
                       h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}, 1};
       if (h->timing)
         for (int k = 0; k < 3; ++k) a.ev[k] = mark_event(h, s);
@@ -797,6 +930,8 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     me::LaunchArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, 1, nhel,
                      nullptr, h->d_jamps, s};
     a.alphas = alphas ? alphas + off : nullptr;
+    a.soa = h->d_soa + off;
+    a.mstride = nevt;
     // the diagram kernel of the process: one-lane code, else the team program
     KernelMark kd(h, ME_KT_DIAGRAM, s);
     hipError_t e = h->desc->launch ? h->desc->launch(a) : h->desc->team(a);
@@ -830,6 +965,10 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
   if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
   hipStream_t s = (hipStream_t)stream;
+  if (h->params.check) {
+    rc = run_check(h, momenta, nevt, s);
+    if (rc) return rc;
+  }
   if (!h->filtered) {
     rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
     if (rc) return rc;
@@ -868,6 +1007,87 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   return ME_OK;
 }
 
+int me_compute_host(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !out_me2) return fail(ME_EINVAL, "null pointer");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  const size_t in_bytes = (size_t)nevt * h->desc->npar * 4 * sizeof(double);
+  const size_t out_bytes = (size_t)nevt * sizeof(double);
+  double* d_in = nullptr;
+  double* d_out = nullptr;
+  hipError_t e = hipMalloc(&d_in, in_bytes);
+  if (e == hipSuccess) e = hipMalloc(&d_out, out_bytes);
+  if (e != hipSuccess) {
+    if (d_in) (void)hipFree(d_in);
+    return fail(ME_ENOMEM, std::string("hipMalloc(host-call buffers): ") + hipGetErrorString(e));
+  }
+  e = hipMemcpy(d_in, momenta, in_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "hipMemcpy(momenta)");
+  } else {
+    rc = me_compute(h, d_in, nevt, alpha_s, d_out, nullptr);
+    if (rc == ME_OK) {
+      e = hipMemcpy(out_me2, d_out, out_bytes, hipMemcpyDeviceToHost);   // waits for the null stream
+      if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(results)");
+    }
+  }
+  // a graph captured on these temporary buffers must not outlive them
+  if (h->g_mom == d_in) drop_graph(h);
+  (void)hipFree(d_in);
+  (void)hipFree(d_out);
+  return rc;
+}
+
+int me_num_channels(me_handle h, int32_t* nchan) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!nchan) return fail(ME_EINVAL, "null nchan");
+  *nchan = h->sde ? h->sde->nchan : 0;
+  return ME_OK;
+}
+
+int me_channel_weights(me_handle h, const double* momenta, int64_t nevt, double alpha_s, const int32_t* chan,
+                       double* num, double* den, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !chan || !num || !den) return fail(ME_EINVAL, "null pointer");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  if (!h->sde) return fail(ME_EINVAL, std::string(h->desc->name) + " has no channel-sum kernel");
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->filtered) {
+    rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  const int nhel = (int)h->good.size();
+  // helicity chunks fill the grid as in the one-lane FP64 path
+  const int64_t blocks = (nevt + 63) / 64;
+  int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (h->target_waves + blocks - 1) / blocks));
+  const int hpc = (nhel + nchunk - 1) / nchunk;
+  nchunk = (nhel + hpc - 1) / hpc;
+  rc = ensure_partial(h, 2 * (size_t)nchunk * nevt);
+  if (rc == ME_OK) rc = ensure_soa(h, nevt);
+  if (rc == ME_OK) rc = enqueue_soa(h, momenta, nevt, s);
+  if (rc) return rc;
+  double* pn = h->d_partial;
+  double* pd = h->d_partial + (size_t)nchunk * nevt;
+  me::SdeArgs a{h->d_soa, nevt, nevt, coupling(alpha_s), h->params.mt, h->d_hels, nhel, hpc, nchunk,
+                (const int*)chan, pn, pd, s};
+  hipError_t e = h->sde->launch(a);
+  if (e != hipSuccess) return hip_fail(e, "channel-sum kernel launch");
+  const unsigned nb = (unsigned)((nevt + 255) / 256);
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(nb), dim3(256), 0, s, pn, nchunk, nevt, 1.0, num);
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(nb), dim3(256), 0, s, pd, nchunk, nevt, 1.0, den);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+  return ME_OK;
+}
+
 int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* momenta,
                      const int64_t* nevts, double alpha_s, double* const* outs, void* stream) {
   if (nproc < 1 || nproc > me::kBatchMaxSeg) return fail(ME_EINVAL, "nproc must be in [1, 8]");
@@ -879,7 +1099,7 @@ int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* mo
     if (rc) return rc;
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(ME_EINVAL, "a handle may appear only once in a batch");
-    if (nevts[i] < 0 || nevts[i] > (int64_t)64 * 0x7fffff) return fail(ME_EINVAL, "bad nevt");
+    if (nevts[i] < 0 || nevts[i] > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "bad nevt");
     if (nevts[i] > 0 && (!momenta[i] || !outs[i])) return fail(ME_EINVAL, "null pointer");
     if (hs[i]->proc_index >= me::kNumBatchProcesses)
       return fail(ME_EINVAL, std::string(hs[i]->desc->name) + " is not in the batch kernel");
@@ -899,6 +1119,11 @@ int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* mo
       if (rc) return rc;
     }
     int rc = ensure_partial(h, h->good.size() * (size_t)nevts[i]);
+    if (rc == ME_OK) rc = ensure_soa(h, nevts[i]);
+    if (rc) return rc;
+  }
+  for (int i : order) {
+    int rc = enqueue_soa(hs[i], momenta[i], nevts[i], s);
     if (rc) return rc;
   }
   me::BatchArgs a{};
@@ -906,7 +1131,7 @@ int me_compute_batch(int32_t nproc, const me_handle* hs, const double* const* mo
   for (int i : order) {
     me_ctx* h = hs[i];
     me::BatchSeg& g = a.seg[a.nseg++];
-    g.mom = momenta[i];
+    g.mom = h->d_soa;
     g.nevt = nevts[i];
     g.g = coupling(alpha_s);
     g.mt = h->params.mt;
@@ -946,6 +1171,10 @@ int me_compute_alphas(me_handle h, const double* momenta, int64_t nevt, const do
   if (nevt == 0) return ME_OK;
   if (!momenta || !alpha_s || !out_me2) return fail(ME_EINVAL, "null pointer");
   if (nevt > (int64_t)64 * 0x7fffffff) return fail(ME_EINVAL, "nevt too large");
+  if (h->params.check) {
+    rc = run_check(h, momenta, nevt, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   if (!h->filtered) {
     // the filter needs one coupling; the good helicities do not depend on it
     rc = me_filter_helicities(h, momenta, nevt, 0.118, stream);
@@ -984,9 +1213,14 @@ int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, 
   if (rc) return rc;
   rc = ensure_jamps(h, (size_t)chunk * row_doubles);
   if (rc) return rc;
+  rc = ensure_soa(h, nevt);
+  if (rc == ME_OK) rc = enqueue_soa(h, momenta, nevt, s);
+  if (rc) return rc;
   const double g = coupling(alpha_s);
   // 1. per-helicity colour sums, one helicity per chunk
   me::LaunchArgs a{momenta, nevt, g, h->params.mt, h->d_hels, nhel, 1, nhel, h->d_partial, nullptr, s};
+  a.soa = h->d_soa;
+  a.mstride = nevt;
   hipError_t e = h->desc->launch(a);
   if (e != hipSuccess) return hip_fail(e, "helicity kernel launch");
   // 2. helicity draw and the summed |M|^2
@@ -1004,6 +1238,8 @@ int me_select(me_handle h, const double* momenta, int64_t nevt, double alpha_s, 
     me::LaunchArgs b{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, 1, 1, 1, nullptr,
                      h->d_jamps, s};
     b.hel_of_event = (const int*)sel_hel + off;
+    b.soa = h->d_soa + off;
+    b.mstride = nevt;
     e = h->desc->launch(b);
     if (e != hipSuccess) return hip_fail(e, "dual-amplitude kernel launch");
     hipLaunchKernelGGL(select_col_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_jamps,
@@ -1095,6 +1331,19 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   h->hel_per_item = cands[best_i].hpi;
   h->target_waves = cands[best_i].tw > 0 ? cands[best_i].tw : save_tw;
   h->executor = cands[best_i].x;
+  // scratch that only a losing candidate needed is released (the split executor's
+  // group sums alone can take ME_SPLIT_SCRATCH_BYTES); the next me_compute sizes
+  // what the winner needs
+  if (h->executor != ME_EXEC_SPLIT && h->d_sums) {
+    (void)hipFree(h->d_sums);
+    h->d_sums = nullptr;
+    h->sums_cap = 0;
+  }
+  if (h->params.colorsum_mode == ME_CS_FP64 && h->d_jamps) {
+    (void)hipFree(h->d_jamps);
+    h->d_jamps = nullptr;
+    h->jamps_cap = 0;
+  }
   if (best) {
     best[0] = h->persistent;
     best[1] = h->waves_per_simd;
@@ -1159,6 +1408,9 @@ int me_set_colorsum_mode(me_handle h, int mode) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!valid_mode(mode)) return fail(ME_EINVAL, "unknown colour-sum mode");
+  if (mode == h->params.colorsum_mode) return ME_OK;
+  // a captured graph holds the old tables' addresses
+  drop_graph(h);
   rc = build_tables(h, mode);
   if (rc) return rc;
   h->params.colorsum_mode = mode;

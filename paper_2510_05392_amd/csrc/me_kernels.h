@@ -19,14 +19,16 @@
 
 namespace me {
 
+// Momenta in structure-of-arrays layout: component u of particle q of event e is
+// soa[(4 q + u) * stride + e], so the 64 lanes of a wavefront (64 consecutive
+// events) load 64 consecutive doubles per component.
 template <class P>
-__device__ __forceinline__ void load_momenta(const double* __restrict__ mom, int64_t e,
+__device__ __forceinline__ void load_momenta(const double* __restrict__ soa, int64_t stride, int64_t e,
                                              double (*p)[4]) {
-  const double* src = mom + e * (P::NPAR * 4);
 #pragma unroll
   for (int q = 0; q < P::NPAR; ++q) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) p[q][u] = src[q * 4 + u];
+    for (int u = 0; u < 4; ++u) p[q][u] = soa[(int64_t)(4 * q + u) * stride + e];
   }
 }
 
@@ -49,7 +51,7 @@ __device__ __forceinline__ void helicity_signs(int h, int* lam) {
 // sqrt(4 pi alphas[e]) (running alpha_s), and hel_of_event[e] replaces the
 // helicity list by one helicity per event (nhel = hel_per_chunk = 1).
 template <class P>
-__device__ __forceinline__ void run_item(const double* __restrict__ mom, int64_t nevt, double g,
+__device__ __forceinline__ void run_item(const double* __restrict__ mom, int64_t mstride, int64_t nevt, double g,
                                          double mt, const int* __restrict__ hels, int nhel,
                                          int hel_per_chunk, int64_t e, int c,
                                          double* __restrict__ partial,
@@ -57,7 +59,7 @@ __device__ __forceinline__ void run_item(const double* __restrict__ mom, int64_t
                                          const double* __restrict__ alphas = nullptr,
                                          const int* __restrict__ hel_of_event = nullptr) {
   double p[P::NPAR][4];
-  load_momenta<P>(mom, e, p);
+  load_momenta<P>(mom, mstride, e, p);
   if (alphas) g = sqrt(4.0 * 3.14159265358979323846 * alphas[e]);
   const int k0 = c * hel_per_chunk;
   const int k1 = min(nhel, k0 + hel_per_chunk);
@@ -102,7 +104,7 @@ __device__ __forceinline__ int next_item(int* counter) {
 }
 
 template <class P>
-__global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, int64_t nevt,
+__global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, int64_t mstride, int64_t nevt,
                                                 double g, double mt, const int* __restrict__ hels,
                                                 int nhel, int hel_per_chunk, int ntiles, int nitems,
                                                 int* __restrict__ counter,
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, 
     const int c = item / ntiles;
     const int64_t e = (int64_t)tile * 64 + threadIdx.x;
     if (e < nevt)
-      run_item<P>(mom, nevt, g, mt, hels, nhel, hel_per_chunk, e, c, partial, jamp_out, alphas,
+      run_item<P>(mom, mstride, nevt, g, mt, hels, nhel, hel_per_chunk, e, c, partial, jamp_out, alphas,
                   hel_of_event);
     if (!counter) break;
     item = next_item(counter);
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(64) me_kernel(const double* __restrict__ mom, 
 template <class... Ps>
 __device__ __forceinline__ void run_batch_item(const BatchSeg& s, int64_t e, int k) {
   int i = 0;
-  ((s.proc == i++ ? run_item<Ps>(s.mom, s.nevt, s.g, s.mt, s.hels, s.nhel, 1, e, k, s.partial, nullptr)
+  ((s.proc == i++ ? run_item<Ps>(s.mom, s.nevt, s.nevt, s.g, s.mt, s.hels, s.nhel, 1, e, k, s.partial, nullptr)
                   : (void)0),
    ...);
 }
@@ -166,7 +168,7 @@ hipError_t launch(const LaunchArgs& a) {
   const int ntiles = (int)((a.nevt + 63) / 64);
   const int nitems = ntiles * a.nchunk;
   const dim3 grid = a.counter ? dim3((unsigned)a.waves) : dim3((unsigned)ntiles, (unsigned)a.nchunk);
-  hipLaunchKernelGGL(me_kernel<P>, grid, dim3(64), 0, a.stream, a.mom, a.nevt, a.g, a.mt, a.hels,
+  hipLaunchKernelGGL(me_kernel<P>, grid, dim3(64), 0, a.stream, a.soa, a.mstride, a.nevt, a.g, a.mt, a.hels,
                      a.nhel, a.hel_per_chunk, ntiles, nitems, a.counter, a.out, a.jamp_out, a.alphas,
                      a.hel_of_event);
   return hipGetLastError();
@@ -202,13 +204,13 @@ hipError_t launch_colour(const ColourArgs& a) {
 //  colour_f64_kernel: the colour form of every row on the FP64 matrix cores.
 template <class P, int K>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P::SUMS_WPE, P::SUMS_WPE)))
-sums_kernel(const double* __restrict__ mom, int64_t n, double g, double mt, const int* __restrict__ hels, int nhel,
-            double* __restrict__ sums, const double* __restrict__ alphas) {
+sums_kernel(const double* __restrict__ mom, int64_t mstride, int64_t n, double g, double mt,
+            const int* __restrict__ hels, int nhel, double* __restrict__ sums, const double* __restrict__ alphas) {
   const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int k = blockIdx.y;
   if (e >= n) return;
   double p[P::NPAR][4];
-  load_momenta<P>(mom, e, p);
+  load_momenta<P>(mom, mstride, e, p);
   if (alphas) g = sqrt(4.0 * 3.14159265358979323846 * alphas[e]);
   int lam[P::NPAR];
   helicity_signs<P>(hels[k], lam);
@@ -223,7 +225,7 @@ hipError_t launch_sums(const SplitArgs& a) {
     return hipSuccess;
   } else {
     hipLaunchKernelGGL((sums_kernel<P, K>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0,
-                       a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
+                       a.stream, a.soa, a.mstride, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_sums<P, K + 1>(a);

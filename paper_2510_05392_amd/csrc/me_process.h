@@ -7,7 +7,7 @@
 namespace me {
 
 struct LaunchArgs {
-  const double* mom;    // device, [nevt][npar][4]
+  const double* mom;    // device, [nevt][npar][4] (the caller's layout; read by the team executor)
   int64_t nevt;
   double g;             // strong coupling sqrt(4 pi alpha_s)
   double mt;            // top mass (GeV)
@@ -22,6 +22,10 @@ struct LaunchArgs {
   int waves = 0;           // persistent grid size (wavefronts) when counter is set
   const double* alphas = nullptr;   // device, per-event alpha_s [nevt], or nullptr (use g)
   const int* hel_of_event = nullptr;  // device, one helicity index per event [nevt], or nullptr
+  // structure-of-arrays copy of the momenta read by the one-lane kernels:
+  // component u of particle q of event e at soa[(4 q + u) * mstride + e]
+  const double* soa = nullptr;
+  int64_t mstride = 0;
 };
 
 using Launcher = hipError_t (*)(const LaunchArgs&);
@@ -45,7 +49,7 @@ using ColourLauncher = hipError_t (*)(const ColourArgs&);
 constexpr int kBatchMaxSeg = 8;
 
 struct BatchSeg {
-  const double* mom;    // device, [nevt][npar][4]
+  const double* mom;    // device, structure of arrays [npar][4][nevt]
   int64_t nevt;
   double g;
   double mt;
@@ -73,7 +77,8 @@ using BatchLauncher = hipError_t (*)(const BatchArgs&, int waves, hipStream_t);
 // sums[2 NGROUP][rows], a second forms the colour flows from them and the
 // colour sum sum_ij CF_int Re(conj(J_i) J_j) into partial[rows].
 struct SplitArgs {
-  const double* mom;     // device, [n][npar][4] (the chunk's events)
+  const double* soa;     // device, structure of arrays: component u of particle q of the chunk's
+  int64_t mstride;       // event e at soa[(4 q + u) * mstride + e]
   int64_t n;
   double g;
   double mt;

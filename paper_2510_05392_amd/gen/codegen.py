@@ -265,6 +265,35 @@ class Emitter:
                 self.lines.append(f"  jamp[{k}] = jamp[{k}] {sign} {term};")
         return self.lines
 
+    def channel_sums(self, channel_of_piece):
+        """Single-diagram-enhancement sums of one (event, helicity): for every diagram
+        built from three-point vertices only (a channel, numbered by
+        channel_of_piece), |A|^2 of its Lorentz amplitude (colour coefficients
+        +-1, +-i, so |A|^2 is the diagram's own) is added to *den, and to *num when
+        the channel is `chan`.  Only the currents these diagrams need are made."""
+        done = set()
+
+        def need(key):
+            if key in done:
+                return
+            for d in self.plan.objects[key]:
+                need(d)
+            self.emit_object(key)
+            done.add(key)
+
+        for key, members in self.plan.scheduled_groups():
+            for lead, amp in members:
+                cid = channel_of_piece.get(amp[0])
+                if cid is None:
+                    continue
+                for o in amp[1:]:
+                    need(o)
+                setup, expr = self.amp_expr(amp[1:])
+                self.lines.append("  { " + ' '.join(setup) + f" const cx a = {expr}; "
+                                  f"const double q = a.r * a.r + a.i * a.i; *den += q; "
+                                  f"*num += chan == {cid} ? q : 0.0; }}")
+        return self.lines
+
     def flow_chunks(self, nwave, chunk):
         """Flows formed from group sums staged through LDS, chunk by chunk: wave w of
         the workgroup owns flows [w fpw, (w + 1) fpw) and keeps them in acc
@@ -344,6 +373,54 @@ LANE_MAX_NPAR = 7
 
 def part_ranges(ngroup, nparts):
     return [range(k * ngroup // nparts, (k + 1) * ngroup // nparts) for k in range(nparts)]
+
+
+def tree_key(trees, t):
+    """Canonical string of a gluon tree built from three-point vertices: a leaf is
+    its gluon slot number, a vertex "(" + its two children's strings, sorted,
+    joined by "," + ")"."""
+    node = trees.nodes[t]
+    if node[0] == 'leaf':
+        return str(node[1])
+    assert node[0] == 'v3'
+    return '(' + ','.join(sorted((tree_key(trees, node[1]), tree_key(trees, node[2])))) + ')'
+
+
+def _cubic(trees, t):
+    node = trees.nodes[t]
+    if node[0] == 'leaf':
+        return True
+    return node[0] == 'v3' and _cubic(trees, node[1]) and _cubic(trees, node[2])
+
+
+def channels(plan):
+    """{piece index: channel number} for the single-diagram-enhancement channels:
+    the diagrams with three-point vertices only, numbered 1..N in ascending order
+    of the tuple of their gluon trees' keys taken from the top end of the quark
+    line (any numbering serves the method; this one is fixed so that two
+    independent enumerations agree)."""
+    keyed = sorted((tuple(tree_key(plan.trees, t) for t in piece), i)
+                   for i, piece in enumerate(plan.pieces) if all(_cubic(plan.trees, t) for t in piece))
+    return {i: c + 1 for c, (_, i) in enumerate(keyed)}
+
+
+def generate_sde(name, plan=None):
+    """Source of the single-diagram-enhancement function of a one-lane process."""
+    npar = PROCESS_NPAR[name]
+    plan = plan or Plan(npar - 2)
+    chan = channels(plan)
+    body = Emitter(name, plan).channel_sums(chan)
+    out = [f"// Generated for process {name}: single-diagram-enhancement sums over its "
+           f"{len(chan)} channels.  Do not edit.",
+           "#pragma once", '#include "me_device.h"', "namespace me {", f"struct {name}_sde {{",
+           f'  static constexpr const char* NAME = "{name}";',
+           f"  static constexpr int NPAR = {npar};",
+           f"  static constexpr int NCHAN = {len(chan)};",
+           "  static __device__ __forceinline__ void channel_amp2(const double (*p)[4], const int* lam, double g, "
+           "double mt, int chan, double* num, double* den) {"]
+    out.extend('  ' + l for l in body)
+    out += ["  }", "};", "}  // namespace me"]
+    return '\n'.join(out) + '\n', len(chan)
 
 
 def generate(name, sums_parts=None, sums_wpe=None, remat=None):

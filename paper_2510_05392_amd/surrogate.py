@@ -57,30 +57,31 @@ class SurrogatePipeline:
 
     # ---------------------------------------------------------------- training
     def fit(self, mom, epochs=20, batch=4096, lr=2e-3, lr_final=1e-4, seed=0, log=None):
-        """Train on device momenta; returns the per-epoch mean training losses."""
+        """Train on device momenta; returns the per-epoch mean training losses.
+
+        Labels come from the exact FP64 path; normalisation statistics, targets and
+        each epoch's shuffled copy of the training set are formed by library
+        kernels (the permutation is drawn on the host and passed in)."""
         torch = self.torch
         n = mom.shape[0]
-        logme = torch.log(self.exact(mom))
+        stream = torch.cuda.current_stream()
+        me2 = self.exact(mom)
         _, raw = self.features(mom, raw=True)
-        raw_h = raw.double().cpu().numpy()
-        mean = raw_h.mean(axis=0)
-        std = raw_h.std(axis=0)
-        self.sur.me_sur_set_normalisation(mean.astype(np.float32), (1.0 / np.maximum(std, 1e-6)).astype(np.float32))
-        y = logme.cpu().numpy()
-        self.ymean, self.ystd = float(y.mean()), float(y.std())
+        self.ymean, self.ystd = self.sur.me_sur_fit_normalisation(raw, n, me2, stream)
         feat = self.features(mom)
-        target = ((logme - self.ymean) / self.ystd).float()
+        target = self._empty(n, torch.float32)
+        binding.me_sur_targets(me2, n, self.ymean, self.ystd, target, stream)
         rng = np.random.Generator(np.random.PCG64(seed))
         nbatch = n // batch
         loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
-        stream = torch.cuda.current_stream()
+        fe = self._empty(feat.shape, feat.dtype)
+        ta = self._empty(n, torch.float32)
         history = []
         step = 0
         total_steps = epochs * nbatch
         for ep in range(epochs):
-            perm = torch.from_numpy(rng.permutation(n)).to(self.dev)
-            fe = feat[perm].contiguous()
-            ta = target[perm].contiguous()
+            perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(self.dev)
+            binding.me_sur_gather_rows(feat, target, perm, n, self.sur.kpad, fe, ta, stream)
             loss.zero_()
             for b in range(nbatch):
                 # cosine decay from lr to lr_final
@@ -104,22 +105,36 @@ class SurrogatePipeline:
         return y
 
     def log_error(self, mom):
-        """Surrogate log|M|^2 minus exact log|M|^2 per event (numpy)."""
-        y = self.predict(mom).double() * self.ystd + self.ymean
-        return (y - self.torch.log(self.exact(mom))).cpu().numpy()
+        """(RMS, largest absolute) error of the surrogate's log|M|^2 on these events."""
+        y = self.predict(mom)
+        return binding.me_sur_log_error(y, self.exact(mom), mom.shape[0], self.ymean, self.ystd,
+                                        self.torch.cuda.current_stream())
 
     # ---------------------------------------------------------------- unweighting
     def calibrate(self, mom, wps, quantile=1.0):
-        """Maxima of the surrogate weight and of the exact/surrogate ratio on a sample."""
-        torch = self.torch
-        y = self.predict(mom).double()
-        what = torch.exp(y * self.ystd + self.ymean) * wps
-        x = self.exact(mom) * wps / what
-        q = (lambda t: float(t.max())) if quantile >= 1.0 else (lambda t: float(torch.quantile(t, quantile)))
-        return q(what), q(x)
+        """Maxima (or q-quantiles) of the surrogate weight and of the exact/surrogate
+        ratio on a calibration sample."""
+        y = self.predict(mom)
+        return binding.me_unweight_maxima(y, wps, self.exact(mom), mom.shape[0], self.ymean, self.ystd, quantile,
+                                          self.torch.cuda.current_stream())
+
+    def exact_weight_max(self, mom, wps, quantile=1.0):
+        """Maximum (or q-quantile) of the exact weights |M|^2 wps, for one-stage unweighting."""
+        return binding.me_unweight_quantile(self.exact(mom), wps, mom.shape[0], quantile,
+                                            self.torch.cuda.current_stream())
+
+    @staticmethod
+    def _summary(res, resid, m):
+        acc, over, sw, sw2 = binding.me_unweight_summary(resid, m)
+        res.update({'accepted': acc, 'overweight': over, 'sum_w': sw, 'sum_w2': sw2,
+                    'ess': (sw * sw / sw2) if sw2 > 0 else 0.0})
+        return res
 
     def unweight(self, mom, wps, r1, r2, what_max, x_max):
-        """Two-stage unweighting of device momenta; returns a dict of results and timings."""
+        """Two-stage unweighting of device momenta; returns a dict of results and timings:
+        'index' (stage-1 event indices) and 'resid' (their residual weights, 0 where
+        stage 2 rejected) as device tensors, counts, weight sums and the Kish
+        effective sample size of the accepted sample."""
         torch = self.torch
         n = mom.shape[0]
         stream = torch.cuda.current_stream()
@@ -139,19 +154,19 @@ class SurrogatePipeline:
         binding.me_unweight_stage2(me_sel, idx, m, wps, what, r2, what_max, x_max, resid, stream)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        res = resid[:m]
-        acc = res > 0
-        return {'n': n, 'stage1': m, 'accepted': int(acc.sum()), 'index': idx[:m][acc], 'resid': res[acc],
-                'overweight': int((res[acc] > 1).sum()), 'time_surrogate': t1 - t0, 'time_total': t2 - t0}
+        res = {'n': n, 'stage1': m, 'index': idx[:m], 'resid': resid[:m], 'time_surrogate': t1 - t0,
+               'time_total': t2 - t0}
+        return self._summary(res, resid, m)
 
     def unweight_exact(self, mom, wps, r, w_max):
-        """One-stage reference: exact weight of every event, accept with min(1, w / w_max)."""
+        """One-stage reference: exact weight of every event, accept with min(1, w / w_max);
+        'resid' holds every event's residual weight (0 = rejected)."""
         torch = self.torch
+        n = mom.shape[0]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        w = self.exact(mom) * wps
-        acc = r < torch.clamp(w / w_max, max=1.0)
-        resid = torch.clamp(w[acc] / w_max, min=1.0)
+        resid = self._empty(n, torch.float64)
+        binding.me_unweight_onestage(self.exact(mom), wps, r, n, w_max, resid, torch.cuda.current_stream())
         torch.cuda.synchronize()
-        return {'n': mom.shape[0], 'accepted': int(acc.sum()), 'index': torch.nonzero(acc)[:, 0], 'resid': resid,
-                'time_total': time.perf_counter() - t0}
+        res = {'n': n, 'resid': resid, 'time_total': time.perf_counter() - t0}
+        return self._summary(res, resid, n)

@@ -78,3 +78,44 @@ class Harness:
                                     ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                     ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
         return meh
+
+
+def build_sde(name, opt='-O1'):
+    """Host build of the generated single-diagram-enhancement function of a process."""
+    from paper_2510_05392_amd.gen import codegen
+    os.makedirs(OUT, exist_ok=True)
+    src, _ = codegen.generate_sde(name)
+    hdr = os.path.join(OUT, f'{name}_sde.inc')
+    if not os.path.exists(hdr) or open(hdr).read() != src:
+        with open(hdr, 'w') as f:
+            f.write(src)
+    lib = os.path.join(OUT, f'sde_harness_{name}.so')
+    deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(HERE, 'sde_harness.cpp')]
+    if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
+        cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE),
+               '-I', CSRC, f'-DSDE_HEADER="{hdr}"', f'-DSDENAME={name}_sde',
+               os.path.join(HERE, 'sde_harness.cpp'), '-o', lib + '.tmp']
+        subprocess.run(cmd, check=True)
+        os.replace(lib + '.tmp', lib)
+    return SdeHarness(lib)
+
+
+class SdeHarness:
+    def __init__(self, path):
+        self.lib = ctypes.CDLL(path)
+        self.lib.harness_nchan.restype = ctypes.c_int
+        self.nchan = self.lib.harness_nchan()
+
+    def eval(self, mom, g, mt, hels, chan):
+        """(num, den) per helicity and event: [nh][nevt] each."""
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        chan = np.ascontiguousarray(chan, dtype=np.int32)
+        num = np.zeros((len(hels), nevt))
+        den = np.zeros((len(hels), nevt))
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        self.lib.harness_sde_eval(mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
+                                  ctypes.c_double(mt), hels.ctypes.data_as(ip), ctypes.c_int(len(hels)),
+                                  chan.ctypes.data_as(ip), num.ctypes.data_as(dp), den.ctypes.data_as(dp))
+        return num, den

@@ -3,7 +3,10 @@
 Calls only the oracle (and the seeded input generator): no value here comes
 from the HIP path.  Run from the repository root:
 
-    python tests/golden/make_golden.py [ggttggg] [ggttgggg]
+    python tests/golden/make_golden.py [ggttggg] [ggttgggg] [sde_ggttggg] [wide_c1] ...
+
+(the wide_* sets run the oracle on every host core; wide_c2 takes about an hour
+of eight cores)
 """
 import os
 import sys
@@ -51,9 +54,82 @@ def ggttgggg():
                         momenta=full[idx], me=m64, me_ext=mext)
 
 
+def sde_ggttggg():
+    # single-diagram-enhancement channel sums of g g -> t tbar g g g: sum over all
+    # 128 helicities of |A_c|^2 for each of the 945 channels, 16 events of seed 1003
+    from oracle import sde
+    proc = me.process(7)
+    mom = rambo.generate(7, 16, 1003)
+    a2 = sde.channel_amp2(proc, mom, AS)
+    np.savez_compressed(os.path.join(HERE, 'gg_ttxggg_seed1003_sde16.npz'), momenta=mom, amp2=a2)
+
+
+# --- the wide parity sets, computed on every host core (multiprocessing over event
+# chunks; the oracle's arithmetic is unchanged)
+
+_PROC = {}
+
+
+def _chunk_values(args):
+    npar, mom, ext = args
+    if npar not in _PROC:
+        _PROC[npar] = me.process(npar)
+    if ext:
+        return me.matrix_element(_PROC[npar], mom.astype(np.longdouble), AS).astype(np.float64)
+    return me.matrix_element(_PROC[npar], mom, AS)
+
+
+def pooled_values(npar, mom, ext=False, chunk=256, workers=None):
+    import multiprocessing as mp
+    workers = workers or len(os.sched_getaffinity(0))
+    parts = [(npar, mom[i:i + chunk], ext) for i in range(0, len(mom), chunk)]
+    with mp.get_context('fork').Pool(workers) as pool:
+        return np.concatenate(pool.map(_chunk_values, parts, chunksize=1))
+
+
+def _save(name, **arrays):
+    np.savez_compressed(os.path.join(HERE, name), **arrays)
+    print('wrote', name, flush=True)
+
+
+def wide_c1():
+    # g g -> t tbar g g, the whole 524288-event workload (seed 1002), FP64 oracle values
+    mom = rambo.generate(6, 524288, 1002)
+    _save('gg_ttxgg_seed1002_n524288.npz', me=pooled_values(6, mom, chunk=2048))
+
+
+def wide_c2():
+    # g g -> t tbar g g g, the first 16384 events of the 262144-event workload (seed
+    # 1003), FP64 and extended precision
+    mom = rambo.generate(7, 16384, 1003)
+    _save('gg_ttxggg_seed1003_first16384.npz', me=pooled_values(7, mom),
+          me_ext=pooled_values(7, mom, ext=True, chunk=64))
+
+
+def wide_c4a(n=256):
+    # g g -> t tbar g g g g, the first n events of the 32768-event workload (seed 1005)
+    mom = rambo.generate(8, n, 1005)
+    _save(f'gg_ttxgggg_seed1005_first{n}.npz', me=pooled_values(8, mom, chunk=4))
+
+
+def wide_c4b():
+    # the uneven batch: the first 1024 events of each segment
+    out = {}
+    for name, npar, seed in (('gg_ttxg', 5, 1004), ('gg_ttxgg', 6, 1006), ('gg_ttxggg', 7, 1007)):
+        mom = rambo.generate(npar, 1024, seed)
+        out[f'{name}_me'] = pooled_values(npar, mom, chunk=64)
+        if npar == 7:
+            out[f'{name}_me_ext'] = pooled_values(npar, mom, ext=True, chunk=32)
+    _save('batch_first1024.npz', **out)
+
+
+GENERATORS = {'ggttggg': ggttggg, 'ggttgggg': ggttgggg, 'sde_ggttggg': sde_ggttggg,
+              'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4b': wide_c4b}
+
+
 def main(which):
-    for name in which or ('ggttggg', 'ggttgggg'):
-        {'ggttggg': ggttggg, 'ggttgggg': ggttgggg}[name]()
+    for name in which or tuple(GENERATORS):
+        GENERATORS[name]()
 
 
 if __name__ == '__main__':

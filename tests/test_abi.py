@@ -95,3 +95,34 @@ def test_host_validation_of_batch_select_and_executor(libpath):
     assert lib.me_set_executor(vp(0x1000), 1) == binding.ME_ESTATE
     lib.me_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     assert lib.me_set_launch(None, 1, 1, 1, 1) == binding.ME_EINVAL
+
+
+def test_params_width_check_and_host_call_validation(libpath, monkeypatch):
+    # me_params carries the top width (only 0 is implemented) and the input-check
+    # switch, whose default follows ME_CHECK; all of this is host-side
+    from paper_2510_05392_amd import binding
+    lib = ctypes.CDLL(libpath)
+    lib.me_last_error.restype = ctypes.c_char_p
+    lib.me_params_default.argtypes = [ctypes.POINTER(binding.me_params)]
+    p = binding.me_params()
+    monkeypatch.delenv('ME_CHECK', raising=False)
+    assert lib.me_params_default(ctypes.byref(p)) == 0
+    assert p.wt == 0.0 and p.check == 0 and p.use_graph == 0
+    monkeypatch.setenv('ME_CHECK', '1')
+    assert lib.me_params_default(ctypes.byref(p)) == 0
+    assert p.check == 1
+    monkeypatch.setenv('ME_CHECK', '0')
+    assert lib.me_params_default(ctypes.byref(p)) == 0
+    assert p.check == 0
+    # a non-zero width is refused before any device call
+    p.wt = 1.4915
+    h = ctypes.c_void_p()
+    lib.me_init.argtypes = [ctypes.c_char_p, ctypes.POINTER(binding.me_params), ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.me_init(b'gg_ttx', ctypes.byref(p), ctypes.byref(h)) == binding.ME_EINVAL
+    assert b'width' in lib.me_last_error()
+    assert h.value is None
+    # host-pointer variant: argument checks precede any device work
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.me_compute_host.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, ctypes.c_double, dp]
+    assert lib.me_compute_host(None, None, 1, 0.118, None) == binding.ME_EINVAL
+    assert lib.me_compute_host(ctypes.c_void_p(0x1000), None, 1, 0.118, None) == binding.ME_ESTATE

@@ -158,3 +158,34 @@ def test_split_group_order_is_a_permutation(n):
     a, b = plan.scheduled_groups(), plan.split_groups()
     assert len(a) == len(b)
     assert sorted(map(repr, a)) == sorted(map(repr, b))
+
+
+@pytest.mark.parametrize('name,npar,nevt,hels', [('gg_ttx', 4, 9, None), ('gg_ttxg', 5, 31, None),
+                                                 ('gg_ttxgg', 6, 7, [0, 5, 22, 41, 63])])
+def test_sde_channel_sums_on_host_vs_oracle(name, npar, nevt, hels):
+    """Generated single-diagram-enhancement sums (host build) against the oracle's
+    channel amplitudes: same channel numbering (keys from independent
+    enumerations), per helicity |A_chan|^2 and the sum over all channels."""
+    from oracle import sde as osde
+    from paper_2510_05392_amd.gen import codegen
+    proc = ome.process(npar)
+    _, okeys = osde.channels(proc)
+    plan = topology.Plan(npar - 2)
+    chan = codegen.channels(plan)
+    gkeys = sorted(tuple(codegen.tree_key(plan.trees, t) for t in plan.pieces[i]) for i in chan)
+    assert gkeys == [tuple(k) for k in okeys]
+    h = harness.build_sde(name)
+    assert h.nchan == len(okeys)
+    mom = rambo.generate(npar, nevt, 4242)
+    ids = (np.arange(nevt) % h.nchan) + 1
+    ids[-1] = 0                                     # no channel: numerator zero
+    hels = list(range(2 ** npar)) if hels is None else hels
+    g = math.sqrt(4 * math.pi * AS)
+    num, den = h.eval(mom, g, 173.0, hels, ids)
+    for k, hel in enumerate(hels):
+        ref = osde.channel_amp2(proc, mom, AS, hels=[hel])      # [nchan, nevt]
+        rden = ref.sum(axis=0)
+        scale = np.maximum(rden, 1e-300)
+        assert np.max(np.abs(den[k] - rden) / scale) < 1e-12
+        rnum = np.where(ids > 0, ref[np.maximum(ids, 1) - 1, np.arange(nevt)], 0.0)
+        assert np.max(np.abs(num[k] - rnum) / scale) < 1e-12

@@ -46,9 +46,36 @@ def _unflatten(flat, sizes):
     return out
 
 
-def test_surrogate_forward_and_gradients_vs_cpu(binding):
-    _say('case surrogate gradients vs cpu (15-64-64-1, 300 rows)')
-    nfeat, width, depth, nb = 15, 64, 2, 300
+def _bf16_bits_ulp(x):
+    """One BF16 unit in the last place of each value (2^(e-7) for |x| in [2^e, 2^(e+1)))."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    e = np.floor(np.log2(np.maximum(x, 1e-38)))
+    return 2.0 ** (e - 7)
+
+
+def _silu64(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def _dsilu64(z):
+    sg = 1.0 / (1.0 + np.exp(-z))
+    return sg * (1.0 + z * (1.0 - sg))
+
+
+GAMMA_FP32 = 2.0 ** -24   # unit roundoff of the FP32 accumulation
+
+
+@pytest.mark.parametrize('width,depth,nb', [(256, 4, 300)])
+def test_surrogate_layers_and_gradients_elementwise(binding, width, depth, nb):
+    """Every layer of the GPU network element by element against an FP64 reference
+    that takes the GPU's own BF16 inputs and BF16 weights: pre-activations within
+    the FP32 accumulation bound gamma_K sum|h||w| (K terms, any order), activations
+    equal to bf16(silu(z)) up to one BF16 ulp where the FP32 exponential sits on a
+    rounding boundary; gradients of every weight and bias element by element
+    against the same reference with dZ rounded to BF16 where the kernels round it
+    (bound: four BF16 ulps of each product term plus the FP32 accumulation)."""
+    _say(f'case surrogate layers and gradients elementwise (15-{width}x{depth}-1, {nb} rows)')
+    nfeat = 15
     sur = binding.Surrogate(nfeat, width, depth, seed=7)
     sizes = [nfeat] + [width] * depth + [1]
     params = _unflatten(sur.me_sur_get_params(), sizes)
@@ -62,31 +89,74 @@ def test_surrogate_forward_and_gradients_vs_cpu(binding):
     sur.me_sur_features(dmom, nb, 6, feat)
     rng = np.random.default_rng(1)
     target = rng.normal(size=nb).astype(np.float32)
-    y = torch.empty(nb, dtype=torch.float32, device='cuda')
-    sur.me_sur_predict(feat, nb, y)
     tg = torch.from_numpy(target).cuda()
     loss = torch.zeros(1, dtype=torch.float32, device='cuda')
     sur.me_sur_grads(feat, tg, nb, loss)
     torch.cuda.synchronize()
-    # the GPU features (BF16) against the FP64 ones, except the constant (g1, g2)
-    # column whose normalised value is rounding noise amplified by 1 / std
+    # features: the GPU's BF16 rows against the FP64 ones, except the constant
+    # (g1, g2) column whose normalised value is rounding noise amplified by 1 / std
     xg = feat.view(torch.bfloat16).float().cpu().numpy().astype(np.float64)[:, :nfeat]
     xc = (raw - mean) / std
-    assert np.all(np.abs(xg[:, 1:] - xc[:, 1:]) <= 2.0 ** -7 * np.abs(xc[:, 1:]) + 1e-3)
-    # CPU FP64 reference of the network on the same BF16 inputs and weights
-    x = xg
-    pb = [(_bf16(w), b) for w, b in params]
-    yref, _ = S.forward(pb, x)
-    ygpu = y.cpu().numpy()
-    assert np.max(np.abs(ygpu - yref)) < 0.05 * max(1.0, np.abs(yref).max())
-    lref, gref = S.loss_and_grads(pb, x, target)
-    assert abs(float(loss.item()) / nb - lref) < 0.03 * lref
+    assert np.all(np.abs(xg[:, 1:] - xc[:, 1:]) <= _bf16_bits_ulp(xc[:, 1:]) + 1e-3)
+    L = depth + 1
+    H = [sur.me_sur_activations(l, 0, nb).astype(np.float64) for l in range(L)]
+    Z = [sur.me_sur_activations(l, 1, nb).astype(np.float64) for l in range(L)]
+    assert np.array_equal(H[0], xg)
+    w16 = [_bf16(w) for w, _ in params]
+    flips = 0
+    for l in range(L):
+        ref = H[l] @ w16[l].T + params[l][1]
+        K = H[l].shape[1]
+        bound = K * GAMMA_FP32 * (np.abs(H[l]) @ np.abs(w16[l]).T + np.abs(params[l][1])) + GAMMA_FP32 * np.abs(ref)
+        assert np.all(np.abs(Z[l] - ref) <= bound), (l, np.max(np.abs(Z[l] - ref) / np.maximum(bound, 1e-300)))
+        if l + 1 < L:
+            want = _bf16(_silu64(Z[l]))
+            diff = np.abs(H[l + 1] - want)
+            assert np.all(diff <= _bf16_bits_ulp(want) * 1.0001), l
+            flips += int((diff > 0).sum())
+    assert flips <= 0.01 * nb * width * depth
+    # gradients: FP64 backward on the GPU's forward activations, dZ rounded to BF16 as
+    # the kernels round it (the bias gradients sum the FP32 dZ).  Alongside, a
+    # first-order bound on the GPU's deviation: e_f bounds |dZ_gpu - dZ| before the
+    # BF16 rounding, e_h after it (a rounding of a perturbed value can land one BF16
+    # ulp away, <= 2^-7 |dZ|); every product adds the FP32 accumulation bound and
+    # the FP32 SiLU derivative is taken good to 1e-6.
+    y = Z[L - 1][:, 0]
+    dzf = (2.0 / nb) * (y - target.astype(np.float64))[:, None]
+    e_f = 4 * GAMMA_FP32 * np.abs(dzf)
+    dzh = _bf16(dzf)
+    e_h = e_f + 2.0 ** -7 * np.abs(dzf)
+    gref = [None] * L
+    bnd = [None] * L
+    for l in range(L - 1, -1, -1):
+        gref[l] = (dzh.T @ H[l], dzf.sum(axis=0))
+        bnd[l] = (e_h.T @ np.abs(H[l]) + nb * GAMMA_FP32 * (np.abs(dzh).T @ np.abs(H[l])),
+                  e_f.sum(axis=0) + nb * GAMMA_FP32 * np.abs(dzf).sum(axis=0))
+        if l == 0:
+            break
+        K = dzh.shape[1]
+        dh = dzh @ w16[l]
+        e_dh = e_h @ np.abs(w16[l]) + K * GAMMA_FP32 * (np.abs(dzh) @ np.abs(w16[l]))
+        ds = _dsilu64(Z[l - 1])
+        dzf = dh * ds
+        e_f = e_dh * np.abs(ds) + np.abs(dh) * 1e-6 + 2 * GAMMA_FP32 * np.abs(dzf)
+        dzh = _bf16(dzf)
+        e_h = e_f + 2.0 ** -7 * np.abs(dzf)
     ggpu = _unflatten(sur.me_sur_get_grads(), sizes)
-    for (gw, gb), (rw, rb) in zip(ggpu, gref):
-        for a, b in ((gw, rw), (gb, rb)):
-            cos = float((a * b).sum() / (np.linalg.norm(a) * np.linalg.norm(b)))
-            assert cos > 0.995, cos
-            assert abs(np.linalg.norm(a) / np.linalg.norm(b) - 1) < 0.05
+    for l, ((gw, gb), (rw, rb), (bw, bb)) in enumerate(zip(ggpu, gref, bnd)):
+        for name, a, b, t in (('W', gw, rw, bw), ('b', gb, rb, bb)):
+            err = np.abs(a - b)
+            assert np.all(err <= t + 1e-30), (l, name, float(np.max(err / np.maximum(t, 1e-300))))
+    lref = float(np.mean((y - target) ** 2))
+    assert abs(float(loss.item()) / nb - lref) <= 1e-5 * lref
+    # end to end against the FP64 reference with its own BF16 rounding (no GPU
+    # activations): the same network within a few BF16 ulps of the output
+    pb = [(w16[l], params[l][1]) for l in range(L)]
+    h = xg
+    for l in range(L):
+        z = h @ pb[l][0].T + pb[l][1]
+        h = _bf16(_silu64(z)) if l + 1 < L else z
+    assert np.max(np.abs(Z[L - 1][:, 0] - h[:, 0])) <= 1e-2 * max(1.0, np.abs(h).max())
 
 
 def test_adam_step_matches_reference(binding):
@@ -123,9 +193,8 @@ def test_training_reduces_loss_and_predicts(trained):
     pipe, hist = trained
     assert hist[-1] < 0.25 * hist[0]
     val = torch.from_numpy(rambo.generate(6, 32768, 2003)).cuda()
-    err = pipe.log_error(val)
-    rms = float(np.sqrt(np.mean(err ** 2)))
-    _say(f'  validation RMS log-error {rms:.3f} (target spread {pipe.ystd:.3f})')
+    rms, worst = pipe.log_error(val)
+    _say(f'  validation RMS log-error {rms:.3f}, largest {worst:.3f} (target spread {pipe.ystd:.3f})')
     assert rms < 0.5 * pipe.ystd
 
 
@@ -146,9 +215,17 @@ def test_unweighting_kernels_match_cpu_reference(trained, binding):
     exact = ome.matrix_element(ome.process(6), mom, AS) * wps
     acc, resid, idx = S.two_stage(w_hat, lambda i: exact[i], r1, r2, what_max, x_max)
     assert res['stage1'] == len(idx)
-    got = res['index'].cpu().numpy()
-    assert np.array_equal(np.sort(got), np.nonzero(acc)[0])
-    assert np.allclose(res['resid'].cpu().numpy(), resid, rtol=1e-9)
+    assert np.array_equal(res['index'].cpu().numpy(), idx)
+    gres = res['resid'].cpu().numpy()
+    assert np.array_equal(idx[gres > 0], np.nonzero(acc)[0])
+    assert np.allclose(gres[gres > 0], resid, rtol=1e-9)
+    # the summary kernel against the GPU's own residual weights (an event at the
+    # calibration maximum sits on the overweight boundary, where the CPU's exp can
+    # land one ulp above 1)
+    acc_g = gres[gres > 0]
+    assert res['accepted'] == int(acc.sum()) and res['overweight'] == int((acc_g > 1).sum())
+    assert np.isclose(res['sum_w'], acc_g.sum(), rtol=1e-13) and np.isclose(res['sum_w2'], (acc_g ** 2).sum(),
+                                                                             rtol=1e-13)
 
 
 def test_surrogate_gain_and_unbiasedness(trained, binding):
@@ -172,8 +249,7 @@ def test_surrogate_gain_and_unbiasedness(trained, binding):
     r2 = torch.rand(n, dtype=torch.float64, device='cuda', generator=g)
     two = pipe.unweight(dmom, dw, r1, r2, what_max, x_max)
     w_exact = pipe.exact(dmom) * dw
-    w_cal = pipe.exact(cal) * cw
-    one = pipe.unweight_exact(dmom, dw, r2, float(torch.quantile(w_cal, 0.99)))
+    one = pipe.unweight_exact(dmom, dw, r2, pipe.exact_weight_max(cal, cw, 0.99))
     saved = 1 - two['stage1'] / n
     _say(f"  stage-1 events {two['stage1']} of {n} (exact calls saved {saved:.1%}); accepted two-stage "
          f"{two['accepted']}, one-stage {one['accepted']}; overweights {two['overweight']}")
@@ -193,3 +269,79 @@ def test_surrogate_gain_and_unbiasedness(trained, binding):
     chi2 = float((((got - ntot * expect) ** 2) / np.maximum(var, 1.0)).sum())
     _say(f'  chi2 of the two-stage sample vs exact-weighted distribution: {chi2:.1f} (8 bins)')
     assert chi2 < 30
+
+
+def test_statistics_targets_and_row_gather_vs_numpy(binding):
+    """Normalisation statistics, training targets and the per-epoch row gather of the
+    library against numpy on the same device data."""
+    _say('case surrogate statistics / targets / gather (70001 events)')
+    n = 70001
+    mom = rambo.generate(6, n, 21)
+    dmom = torch.from_numpy(mom).cuda()
+    me = binding.MatrixElement('gg_ttxgg')
+    me2 = me.compute(dmom, AS)
+    sur = binding.Surrogate(15, 64, 1, seed=2)
+    raw = torch.empty((n, 15), dtype=torch.float32, device='cuda')
+    feat = torch.empty((n, sur.kpad), dtype=torch.int16, device='cuda')
+    sur.me_sur_features(dmom, n, 6, feat, raw)
+    ymean, ystd = sur.me_sur_fit_normalisation(raw, n, me2)
+    torch.cuda.synchronize()
+    rh = raw.cpu().numpy().astype(np.float64)
+    lm = np.log(me2.cpu().numpy())
+    assert abs(ymean - lm.mean()) <= 1e-12 * abs(lm.mean()) and abs(ystd / lm.std() - 1) <= 1e-10
+    # the handle now normalises with the fitted statistics: features recomputed
+    sur.me_sur_features(dmom, n, 6, feat)
+    xg = feat.view(torch.bfloat16).float().cpu().numpy().astype(np.float64)[:, :15]
+    mu, sd = rh.mean(axis=0), np.maximum(rh.std(axis=0), 1e-6)
+    xc = ((rh - mu.astype(np.float32)) * (1 / sd).astype(np.float32))
+    assert np.all(np.abs(xg[:, 1:] - xc[:, 1:]) <= _bf16_bits_ulp(xc[:, 1:]) * 1.0001 + 1e-6)
+    tgt = torch.empty(n, dtype=torch.float32, device='cuda')
+    binding.me_sur_targets(me2, n, ymean, ystd, tgt)
+    want = ((lm - ymean) / ystd).astype(np.float32)
+    got = tgt.cpu().numpy()
+    assert np.all(np.abs(got - want) <= np.spacing(np.abs(want)))
+    perm = np.random.default_rng(4).permutation(n).astype(np.int64)
+    fo = torch.empty_like(feat)
+    to = torch.empty_like(tgt)
+    binding.me_sur_gather_rows(feat, tgt, torch.from_numpy(perm).cuda(), n, sur.kpad, fo, to)
+    torch.cuda.synchronize()
+    assert np.array_equal(fo.cpu().numpy(), feat.cpu().numpy()[perm])
+    assert np.array_equal(to.cpu().numpy(), got[perm])
+
+
+@pytest.mark.parametrize('n,q', [(1, 0.99), (2, 0.5), (1000, 1.0), (65537, 0.99), (65536, 0.5), (4097, 0.001)])
+def test_maxima_quantiles_onestage_summary_vs_numpy(binding, n, q):
+    """Quantiles by device radix selection (linear interpolation between order
+    statistics, numpy's default), one-stage unweighting, residual-weight summary
+    and log error against numpy on the same inputs."""
+    _say(f'case unweighting maxima n={n} q={q}')
+    rng = np.random.default_rng(n)
+    y = rng.normal(size=n).astype(np.float32)
+    wps = rng.lognormal(size=n)
+    me2 = rng.lognormal(mean=-20, sigma=3, size=n)
+    # ties: a block of equal weights
+    me2[: n // 3] = me2[0]
+    wps[: n // 3] = wps[0]
+    r = rng.random(n)
+    ymean, ystd = -20.0, 3.0
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    what_max, x_max = binding.me_unweight_maxima(d(y), d(wps), d(me2), n, ymean, ystd, q)
+    what = np.exp(y.astype(np.float64) * ystd + ymean) * wps
+    x = me2 * wps / what
+    ref = (lambda v: v.max()) if q >= 1 else (lambda v: np.quantile(v, q))
+    assert abs(what_max / ref(what) - 1) < 1e-14 and abs(x_max / ref(x) - 1) < 1e-14
+    w = me2 * wps
+    w_max = binding.me_unweight_quantile(d(me2), d(wps), n, q)
+    assert abs(w_max / ref(w) - 1) < 1e-14
+    resid = torch.empty(n, dtype=torch.float64, device='cuda')
+    binding.me_unweight_onestage(d(me2), d(wps), d(r), n, w_max, resid)
+    acc = r < np.minimum(1.0, w / w_max)
+    want = np.where(acc, np.maximum(1.0, w / w_max), 0.0)
+    got = resid.cpu().numpy()
+    assert np.array_equal(got > 0, acc) and np.allclose(got, want, rtol=1e-15, atol=0)
+    na, no, sw, sw2 = binding.me_unweight_summary(resid, n)
+    assert na == int(acc.sum()) and no == int((want > 1).sum())
+    assert np.isclose(sw, want.sum(), rtol=1e-13) and np.isclose(sw2, (want ** 2).sum(), rtol=1e-13)
+    rms, worst = binding.me_sur_log_error(d(y), d(me2), n, ymean, ystd)
+    dl = y.astype(np.float64) * ystd + ymean - np.log(me2)
+    assert abs(rms / np.sqrt(np.mean(dl ** 2)) - 1) < 1e-12 and abs(worst / np.abs(dl).max() - 1) < 1e-14
