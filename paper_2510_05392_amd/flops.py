@@ -1,69 +1,56 @@
 """Algorithmic FP64 work of one (event, helicity) of the generated path.
 
-Counting rules: every real add, subtract, multiply, divide and square root is
-one flop (a fused multiply-add is two); complex add = 2, complex multiply = 6,
-complex a + b*c = 8, real x complex = 2, multiplication by +-i and negation
-are free.  The per-routine figures below are read off the device routines
-(csrc/me_device.h) at those rules, counting each distinct intermediate once;
-a process's figure is the sum over its evaluation plan (currents, amplitude
-contractions, colour-flow accumulation) plus the triangular colour quadratic
-form.  This is the number the benchmark's roofline fraction divides by the
-measured kernel time.
+Counting rules: every real addition, subtraction, multiplication, division and
+square root the device code writes is one flop; negation and the factor i are
+free.  ROUTINE holds the count of one call of each device routine
+(csrc/me_device.h) and OPS the counts of the arithmetic the generator writes
+inline; the generator's Emitter adds them up as it writes a process's code, so
+a process's figure is exactly the operations its code performs (beam gluons
+along +-z take the branch without the azimuth divisions, as in every event of
+the workloads).  tests/test_generator.py compiles the generated code for the
+host with an operation-counting scalar and checks these figures against the
+count, routine by routine and process by process.  This is the number the
+benchmark's roofline fraction divides by the measured kernel time.
 """
 from __future__ import annotations
 
 ROUTINE = {
-    'G': 24,          # ext_gluon: polar angles (10), components (14)
-    'U': 35,          # ext_ubar: helicity spinor (16), omegas (11), scaling (8)
-    'V': 37,          # ext_v: as ext_ubar plus two sign products
-    'v3': 162,        # v3_current: momenta (16), three dots (58), 1/P^2 (8), combine (80)
-    'v4': 133,        # v4_current: 1/P^2 (9), two complex dots (60), combine (64)
-    'KD3': 162,       # v3_open on a top-line current: as v3_current
-    'KD4': 133,       # v4_open on a top-line current: as v4_current
-    'Lh': 72,         # row_vertex: slash blocks (8), 2x2 blocks (56), coupling (8)
-    'Rh': 72,         # vertex_col
-    'L': 79,          # row_prop: q (4), propagator blocks + 1/(q^2-m^2) (11), product (56), scale (8)
-    'R': 79,          # prop_col
-    'K': 80,          # line_current: 8 complex products (48), combinations (24), coupling (8)
-    'dot': 30,        # sdot / vdot: 4 complex products, 3 complex adds
-    'ffv': 102,       # row_vertex + sdot
-    'jamp': 2,        # one complex accumulation (group sum or colour flow)
+    'G': 24,          # ext_gluon, momentum with a transverse component
+    'Gbeam': 22,      # ext_gluon along +-z (no azimuth divisions)
+    'U': 35,          # ext_ubar
+    'V': 37,          # ext_v
+    'v3': 166,        # v3_current
+    'v4': 141,        # v4_current<S>
+    'Lh': 80,         # row_vertex
+    'Rh': 80,         # vertex_col
+    'L': 94,          # row_prop
+    'R': 94,          # prop_col
+    'K': 80,          # line_current
+    'KD3': 154,       # v3_open
+    'KD4': 132,       # v4_open<S, H>
+    'sdot': 30,       # spinor contraction
+    'vdot': 30,       # Minkowski product of complex vectors
+    'msq': 7,         # Minkowski square of a real vector
 }
 
+OPS = {
+    'qsub': 4,        # q = p3 - P or P - p4 before a top propagator
+    'kd3_factor': 1,  # -g / P^2 (after msq)
+    'kd4_factor': 2,  # -g g / P^2 (after msq)
+    'cadd': 2,        # complex addition: a group-sum member, or a colour-flow update
+    'channel': 5,     # |A|^2 (3), added to the channel sum (1) and the selected channel (1)
+}
 
-def plan_flops(plan):
-    """FP64 flops per (event, helicity) for the diagram part of an evaluation plan."""
-    total = 0
-    masks = set()
-    for key in plan.order:
-        r = plan.routine(key)
-        total += ROUTINE[r]
-        if key[0] == 'J':
-            node = plan.trees.nodes[key[1]]
-            kids = node[1:] if node[0] == 'v3' else node[2:]
-            masks.add(plan.trees.mask[key[1]])
-            masks.update(plan.trees.mask[c] for c in kids)
-        elif key[0] in ('L', 'R'):
-            m = 0
-            for t in key[1]:
-                m |= plan.trees.mask[t]
-            masks.add(m)
-        elif key[0] == 'KD':
-            masks.add(plan.hole_mask(key))
-            masks.update(plan.trees.mask[t] for t in key[3][-1][3])
-    # momentum sums P(mask) = sum of |mask| external momenta, once per mask
-    total += sum(4 * (bin(m).count('1') - 1) for m in masks)
-    for amp in plan.amps:
-        total += ROUTINE['ffv'] if len(amp) == 4 else ROUTINE['dot']
-    # pieces with the same colour vector are summed, then added to each of its flows
-    for key, members in plan.colour_groups():
-        total += ROUTINE['jamp'] * (len(members) - 1 + len(key))
-    return total
+# ext_ubar and ext_v take one more division when the top (antitop) has pz < 0
+# (|p| + pz formed without cancellation); ROUTINE counts pz >= 0.  Over the
+# workloads each of the two is in the backward hemisphere in half of the events,
+# so the per-(event, helicity) figures below add the mean, one operation.
+QUARK_BRANCH_MEAN = 1
 
 
-def colour_sum_flops(ncol):
-    """Triangular quadratic form sum_ij CF_ij Re(J_i^* J_j) with integer CF."""
-    return 2 * ncol * ncol + 4 * ncol
+def momentum_sum(nterms):
+    """Flops of one four-momentum sum of nterms external momenta."""
+    return 4 * (nterms - 1)
 
 
 def _plan(name):
@@ -72,9 +59,48 @@ def _plan(name):
     return Plan(codegen.PROCESS_NPAR[name] - 2)
 
 
+def colour_sum_flops(cf):
+    """Triangular quadratic form sum_ij CF_ij Re(J_i^* J_j) with integer CF as the
+    one-lane code writes it: per row i, the products with its diagonal and its
+    non-zero entries j > i for the real and imaginary parts, their sums, and the
+    row's two products and two additions into the accumulator."""
+    n = len(cf)
+    total = 0
+    for i in range(n):
+        nnz = sum(1 for j in range(i + 1, n) if cf[i][j] != 0)
+        total += 2 * (2 * nnz + 1) + 4
+    return total
+
+
+def amplitudes_flops(name, plan=None):
+    """Dual amplitudes of one (event, helicity): currents, contractions, group sums
+    and colour-flow updates of the one-lane code."""
+    from .gen import codegen
+    plan = plan or _plan(name)
+    em = codegen.Emitter(name, plan)
+    em.amplitudes()
+    return em.ops
+
+
+def group_sums_flops(name, plan=None):
+    """Colour-group sums of one (event, helicity) of the split executor (all parts)."""
+    from .gen import codegen
+    plan = plan or _plan(name)
+    nparts = codegen.SUMS_PARTS.get(name, 1)
+    remat = codegen.SUMS_REMAT.get(name, False)
+    total = 0
+    for r in codegen.part_ranges(len(plan.scheduled_groups()), nparts):
+        em = codegen.Emitter(name, plan, remat=remat)
+        em.amplitudes(split=True, groups=r)
+        total += em.ops
+    return total
+
+
 def per_event_helicity(name):
     plan = _plan(name)
-    return plan_flops(plan) + colour_sum_flops(len(plan.basis))
+    from .gen.colour import colour_matrix
+    cf, _ = colour_matrix(plan.n)
+    return amplitudes_flops(name, plan) + colour_sum_flops(cf)
 
 
 def flow_updates(plan):
@@ -85,12 +111,12 @@ def flow_updates(plan):
 def diagram_kernel(name, executor):
     """FP64 flops per (event, helicity) of the kernel that evaluates the diagrams:
     everything for the one-lane and team executors (flows and colour form are fused
-    into it), the group sums alone for the split executor (executor 2), whose flows
-    and colour form run in kernels of their own."""
-    plan = _plan(name)
+    into it; the team program runs the same routines), the group sums alone for the
+    split executor (executor 2), whose flows and colour form run in kernels of their
+    own."""
     if executor == 2:
-        return plan_flops(plan) - ROUTINE['jamp'] * flow_updates(plan)
-    return plan_flops(plan) + colour_sum_flops(len(plan.basis))
+        return group_sums_flops(name) + QUARK_BRANCH_MEAN
+    return per_event_helicity(name) + QUARK_BRANCH_MEAN
 
 
 def split_bytes(name):

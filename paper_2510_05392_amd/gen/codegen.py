@@ -57,6 +57,10 @@ class Emitter:
         self.masks_done = set()
         self.neg_done = set()
         self.basis_index = {p: i for i, p in enumerate(plan.basis)}
+        # FP64 operations of the code written so far, one (event, helicity)
+        from .. import flops
+        self.fl = flops
+        self.ops = 0
 
     def var(self, key):
         if key not in self.names:
@@ -92,6 +96,7 @@ class Emitter:
                 expr = expr.replace(first, f"opaque({first})", 1)
             comps.append(expr)
         self.lines.append(f"  const double {name}[4] = {{{', '.join(comps)}}};")
+        self.ops += self.fl.momentum_sum(len(terms))
         return name
 
     def tree_mask(self, t):
@@ -112,10 +117,13 @@ class Emitter:
             q = slot_particle(s)
             outgoing = 'true' if s >= 2 else 'false'
             L.append(f"  cx {out}[4]; ext_gluon(p[{q}], lam[{q}], {outgoing}, {out});")
+            self.ops += self.fl.ROUTINE['Gbeam' if s < 2 else 'G']
         elif kind == 'U':
             L.append(f"  cx {out}[4]; ext_ubar(p[2], lam[2], mt, {out});")
+            self.ops += self.fl.ROUTINE['U']
         elif kind == 'V':
             L.append(f"  cx {out}[4]; ext_v(p[3], lam[3], mt, {out});")
+            self.ops += self.fl.ROUTINE['V']
         elif kind == 'J':
             node = self.plan.trees.nodes[key[1]]
             if node[0] == 'v3':
@@ -123,16 +131,19 @@ class Emitter:
                 pa, pb = self.mom(self.tree_mask(a)), self.mom(self.tree_mask(b))
                 va, vb = self.var(self.plan.jkey(a)), self.var(self.plan.jkey(b))
                 L.append(f"  cx {out}[4]; v3_current({va}, {pa}, {vb}, {pb}, g, {out});")
+                self.ops += self.fl.ROUTINE['v3']
             else:
                 s, a, b, c = node[1], node[2], node[3], node[4]
                 pm = self.mom(self.tree_mask(key[1]))
                 va, vb, vc = (self.var(self.plan.jkey(x)) for x in (a, b, c))
                 L.append(f"  cx {out}[4]; v4_current<{s}>({va}, {vb}, {vc}, {pm}, g, {out});")
+                self.ops += self.fl.ROUTINE['v4']
         elif kind == 'Lh':
             seq = key[1]
             prev = self.var(('L', seq[:-1]) if len(seq) > 1 else ('U',))
             j = self.var(self.plan.jkey(seq[-1]))
             L.append(f"  cx {out}[4]; row_vertex({prev}, {j}, g, {out});")
+            self.ops += self.fl.ROUTINE['Lh']
         elif kind == 'L':
             seq = key[1]
             pm = self.mom(self.seq_mask(seq))
@@ -140,11 +151,13 @@ class Emitter:
             # momentum along the fermion arrow: p3 - P(seq)
             L.append(f"  cx {out}[4]; {{ const double q[4] = {{p[2][0] - {pm}[0], p[2][1] - {pm}[1], "
                      f"p[2][2] - {pm}[2], p[2][3] - {pm}[3]}}; row_prop({src}, q, mt, {out}); }}")
+            self.ops += self.fl.OPS['qsub'] + self.fl.ROUTINE['L']
         elif kind == 'Rh':
             seq = key[1]
             nxt = self.var(('R', seq[1:]) if len(seq) > 1 else ('V',))
             j = self.var(self.plan.jkey(seq[0]))
             L.append(f"  cx {out}[4]; vertex_col({j}, {nxt}, g, {out});")
+            self.ops += self.fl.ROUTINE['Rh']
         elif kind == 'R':
             seq = key[1]
             pm = self.mom(self.seq_mask(seq))
@@ -152,10 +165,12 @@ class Emitter:
             # momentum along the fermion arrow: P(seq) - p4
             L.append(f"  cx {out}[4]; {{ const double q[4] = {{{pm}[0] - p[3][0], {pm}[1] - p[3][1], "
                      f"{pm}[2] - p[3][2], {pm}[3] - p[3][3]}}; prop_col(q, mt, {src}, {out}); }}")
+            self.ops += self.fl.OPS['qsub'] + self.fl.ROUTINE['R']
         elif kind == 'K':
             left = self.var(('L', key[1]) if key[1] else ('U',))
             right = self.var(('R', key[2]) if key[2] else ('V',))
             L.append(f"  cx {out}[4]; line_current({left}, {right}, g, {out});")
+            self.ops += self.fl.ROUTINE['K']
         elif kind == 'KD':
             self.emit_kd(key, out)
         else:
@@ -183,6 +198,8 @@ class Emitter:
         sib_vars = [self.var(self.plan.jkey(t)) for t in sibs]
         sib_moms = [self.mom(self.tree_mask(t)) for t in sibs]
         f = f"(-g / msq({self.mom(tmask)}))" if kind == 'v3' else f"(-g * g / msq({self.mom(tmask)}))"
+        self.ops += self.fl.ROUTINE['msq'] + self.fl.OPS['kd3_factor' if kind == 'v3' else 'kd4_factor']
+        self.ops += self.fl.ROUTINE['KD3' if kind == 'v3' else 'KD4']
         if kind == 'v3':
             # legs (parent, A, B); the two given legs in cyclic order after the open one
             if hole == 1:
@@ -202,9 +219,11 @@ class Emitter:
         if len(objs) == 3:
             # quark-gluon vertex amplitude  L (i g gamma.J) R
             left, j, right = (self.var(o) for o in objs)
+            self.ops += self.fl.ROUTINE['Lh'] + self.fl.ROUTINE['sdot']
             return [f"cx t[4]; row_vertex({left}, {j}, g, t);"], f"sdot(t, {right})"
         va, vb = self.var(objs[0]), self.var(objs[1])
         op = 'vdot' if objs[0][0] in ('K', 'KD') else 'sdot'
+        self.ops += self.fl.ROUTINE[op]
         return [], f"{op}({va}, {vb})"
 
     @staticmethod
@@ -256,6 +275,7 @@ class Emitter:
                     self.lines.append(head + f"{acc} = a; }}")
                 else:
                     self.lines.append(head + f"{acc} = {acc} {sign} {term}; }}")
+                    self.ops += self.fl.OPS['cadd']
             if split:
                 self.lines.append(f"  sout[{2 * gi} * sstride] = {acc}.r; sout[{2 * gi + 1} * sstride] = {acc}.i;")
                 continue
@@ -263,6 +283,7 @@ class Emitter:
             for k, rel in key:
                 sign, term = self._scaled(acc, rel * first_lead)
                 self.lines.append(f"  jamp[{k}] = jamp[{k}] {sign} {term};")
+                self.ops += self.fl.OPS['cadd']
         return self.lines
 
     def channel_sums(self, channel_of_piece):
@@ -292,6 +313,7 @@ class Emitter:
                 self.lines.append("  { " + ' '.join(setup) + f" const cx a = {expr}; "
                                   f"const double q = a.r * a.r + a.i * a.i; *den += q; "
                                   f"*num += chan == {cid} ? q : 0.0; }}")
+                self.ops += self.fl.OPS['channel']
         return self.lines
 
     def flow_chunks(self, nwave, chunk):

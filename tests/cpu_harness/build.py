@@ -119,3 +119,54 @@ class SdeHarness:
                                   ctypes.c_double(mt), hels.ctypes.data_as(ip), ctypes.c_int(len(hels)),
                                   chan.ctypes.data_as(ip), num.ctypes.data_as(dp), den.ctypes.data_as(dp))
         return num, den
+
+
+def build_count(name, opt='-O1'):
+    """Host build of a process's generated code with the operation-counting scalar."""
+    from paper_2510_05392_amd.gen import codegen
+    os.makedirs(OUT, exist_ok=True)
+    src, _, _ = codegen.generate(name)
+    hdr = os.path.join(OUT, f'{name}.inc')
+    if not os.path.exists(hdr) or open(hdr).read() != src:
+        with open(hdr, 'w') as f:
+            f.write(src)
+    lib = os.path.join(OUT, f'count_harness_{name}.so')
+    deps = [hdr, os.path.join(CSRC, 'me_device.h'), os.path.join(CSRC, 'me_team.h'),
+            os.path.join(HERE, 'count_harness.cpp')]
+    if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
+        cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE),
+               '-I', CSRC, f'-DPROCESS_HEADER="{hdr}"', f'-DPROCNAME={name}',
+               os.path.join(HERE, 'count_harness.cpp'), '-o', lib + '.tmp']
+        subprocess.run(cmd, check=True)
+        os.replace(lib + '.tmp', lib)
+    return CountHarness(lib)
+
+
+class CountHarness:
+    def __init__(self, path):
+        self.lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        for f in ('count_amplitudes', 'count_group_sums'):
+            getattr(self.lib, f).restype = ctypes.c_longlong
+            getattr(self.lib, f).argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        self.lib.count_colour_sum.restype = ctypes.c_longlong
+        self.lib.count_routine.restype = ctypes.c_longlong
+        self.lib.count_routine.argtypes = [ctypes.c_int]
+
+    def _mom(self, mom):
+        m = np.ascontiguousarray(mom, dtype=np.float64)
+        return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def amplitudes(self, mom, hel, g=1.2, mt=173.0):
+        m, ptr = self._mom(mom)
+        return self.lib.count_amplitudes(ptr, hel, g, mt)
+
+    def group_sums(self, mom, hel, g=1.2, mt=173.0):
+        m, ptr = self._mom(mom)
+        return self.lib.count_group_sums(ptr, hel, g, mt)
+
+    def colour_sum(self):
+        return self.lib.count_colour_sum()
+
+    def routine(self, which):
+        return self.lib.count_routine(which)

@@ -59,8 +59,38 @@ def test_every_piece_is_evaluated_once():
 
 
 def test_flop_model_is_positive_and_monotone():
-    f = [flops.per_event_helicity(p) for p in ('gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg')]
+    f = [flops.per_event_helicity(p) for p in ('gg_ttx', 'gg_ttxg', 'gg_ttxgg')]
     assert all(b > 4 * a for a, b in zip(f, f[1:]))
+
+
+# count_routine's order in tests/cpu_harness/count_harness.cpp
+ROUTINES = ['G', 'Gbeam', 'U', 'V', 'v3', 'v4', 'v4', 'v4', 'Lh', 'Rh', 'L', 'R', 'K', 'KD3', 'KD4', 'KD4', 'KD4',
+            'sdot', 'vdot', 'msq']
+
+
+@pytest.mark.parametrize('name,npar,opt', [('gg_ttx', 4, '-O1'), ('gg_ttxg', 5, '-O1'), ('gg_ttxgg', 6, '-O1'),
+                                           ('gg_ttxggg', 7, '-O0')])
+def test_flop_figures_equal_the_counted_operations(name, npar, opt):
+    """The flop figures of the roofline (per-routine table summed by the emitter)
+    equal the operations the generated code performs, counted by compiling it for
+    the host with an operation-counting scalar: every routine, and the whole
+    one-lane code, group-sum code and colour form of each process, on workload
+    events whose top / antitop take either branch of the spinor code."""
+    from paper_2510_05392_amd.gen import colour as gc
+    h = harness.build_count(name, opt)
+    for i, r in enumerate(ROUTINES):
+        assert h.routine(i) == flops.ROUTINE[r], r
+    plan = topology.Plan(npar - 2)
+    amp, sums = flops.amplitudes_flops(name, plan), flops.group_sums_flops(name, plan)
+    cf, _ = gc.colour_matrix(npar - 2)
+    assert h.colour_sum() == flops.colour_sum_flops(cf)
+    mom = rambo.generate(npar, 6, 1003)
+    for e in range(mom.shape[0]):
+        neg = int((mom[e, 2:4, 3] < 0).sum())
+        for hel in (0, 2 ** npar - 1, 5):
+            assert h.amplitudes(mom[e], hel) == amp + neg
+            assert h.group_sums(mom[e], hel) == sums + neg
+    assert flops.diagram_kernel(name, 2) == sums + flops.QUARK_BRANCH_MEAN
 
 
 @pytest.mark.parametrize('name,npar,nevt,opt,hels', [
