@@ -126,6 +126,26 @@ int me_init(const char* process, const me_params* p, me_handle* out);
 int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
                double* out_me2, void* stream);
 
+/* Device scratch of me_compute_noalloc: a static array in the library, one per GPU
+ * the library runs on, held until the process ends. */
+#define ME_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+/* For callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): as me_compute in ME_CS_FP64 mode
+ * with the grid launch of the one-lane kernel (the team program for gg_ttxgggg),
+ * whatever the handle's executor and colour-sum mode, and it calls no
+ * allocation: its scratch (momenta as structure of arrays, 32 npar nevt bytes for
+ * the one-lane kernel, and per-chunk partial sums, 8 nchunk nevt bytes, nchunk =
+ * the helicity chunks that fill about target_waves wavefronts) lives in a static
+ * device array of ME_NOALLOC_SCRATCH_BYTES.  Sizes needing more return ME_EINVAL
+ * (gg_ttxggg: up to 299 593 events at one chunk).  The helicity filter must have
+ * run (me_filter_helicities, or all_helicities = 1), else ME_EINVAL; the handle's
+ * device must be current.  Results equal me_compute's with the lane executor and
+ * the grid launch.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other handles, other threads) race. */
+int me_compute_noalloc(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+                       void* stream);
+
 /* As me_compute on host memory: momenta[nevt][npar][4] and out_me2[nevt] are
  * host pointers (the caller's).  The library allocates device copies, computes
  * on the handle's stream and copies the result back before returning (it

@@ -29,7 +29,8 @@ ME_EXEC_SPLIT = 2
 ME_KT_DIAGRAM, ME_KT_FLOWS, ME_KT_COLOUR, ME_KT_REDUCE = 0, 1, 2, 3
 ME_KT_KINDS = 4
 
-EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_compute_host', 'me_filter_helicities',
+EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_compute_host', 'me_compute_noalloc',
+           'me_filter_helicities',
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
            'me_compute_alphas', 'me_select', 'me_set_executor', 'me_set_kernel_timing',
@@ -74,6 +75,7 @@ def load(path=LIB_PATH):
     lib.me_params_default.argtypes = [ctypes.POINTER(me_params)]
     lib.me_init.argtypes = [ctypes.c_char_p, ctypes.POINTER(me_params), ctypes.POINTER(vp)]
     lib.me_compute.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
+    lib.me_compute_noalloc.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
     lib.me_compute_host.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, ctypes.c_double,
                                     ctypes.POINTER(ctypes.c_double)]
     lib.me_filter_helicities.argtypes = [vp, vp, i64, ctypes.c_double, vp]
@@ -189,6 +191,9 @@ class MatrixElement:
         _check(load().me_compute_host(self._h, mom.ctypes.data_as(dp), mom.shape[0], alpha_s,
                                       out.ctypes.data_as(dp)))
         return out
+
+    def me_compute_noalloc(self, momenta, nevt, alpha_s, out, stream=None):
+        _check(load().me_compute_noalloc(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream)))
 
     def me_compute_alphas(self, momenta, nevt, alpha_s, out, stream=None):
         _check(load().me_compute_alphas(self._h, _ptr(momenta), nevt, _ptr(alpha_s), _ptr(out),

@@ -26,6 +26,12 @@ namespace me {
 #include "registry.inc"   // const ProcessDesc* (*const kProcesses[])() and kNumProcesses
 }
 
+// Device scratch of me_compute_noalloc: one static array per GPU (each device
+// holds its own copy at its own address, resolved once per device with
+// hipGetSymbolAddress; host code never passes the array's name itself to a
+// kernel or a copy).  Calls that overlap on one GPU share it and race.
+static __device__ __align__(256) double scratch[ME_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
 namespace {
 
 thread_local std::string g_err;
@@ -47,6 +53,11 @@ int hip_fail(hipError_t e, const char* what) {
 
 std::mutex g_live_mu;
 std::set<const void*> g_live;
+
+// per-device address of the static scratch array (null until resolved)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 __global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nchunk, int64_t nevt,
                                      double scale, double* __restrict__ out) {
@@ -169,6 +180,8 @@ struct me_ctx {
   double* d_sums = nullptr;   // colour-group sums, then colour flows, of the split executor
   size_t sums_cap = 0;        // doubles
   double* d_cf64 = nullptr;   // colour matrix for the split executor's FP64 matrix-core colour form
+  int device = 0;             // device current at me_init
+  double* d_static = nullptr; // this device's static scratch array (me_compute_noalloc)
   double* d_soa = nullptr;    // structure-of-arrays copy of the momenta [npar][4][nevt]
   size_t soa_cap = 0;         // doubles
   unsigned long long* d_check = nullptr;  // input check record (count, first failing event)
@@ -549,6 +562,28 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       c->simds = 4 * cus;
+    c->device = dev;
+  }
+  {
+    // the static scratch array's address on this device, resolved once per device
+    // with the device current
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (c->device >= 0 && c->device < kMaxDevices) {
+      if (!g_scratch_ptr[c->device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+          (void)hipFree(c->d_hels);
+          (void)hipFree(c->d_scratch_hels);
+          if (c->d_cf64) (void)hipFree(c->d_cf64);
+          free_tables(c);
+          delete c;
+          return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        }
+        g_scratch_ptr[c->device] = static_cast<double*>(ptr);
+      }
+      c->d_static = g_scratch_ptr[c->device];
+    }
   }
   if (hipMalloc(&c->d_counter, sizeof(int)) != hipSuccess ||
       hipMalloc(&c->d_check, 2 * sizeof(unsigned long long)) != hipSuccess ||
@@ -1004,6 +1039,64 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   }
   hipError_t e = hipGraphLaunch(h->graph, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ME_OK;
+}
+
+int me_compute_noalloc(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
+                       void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (nevt < 0) return fail(ME_EINVAL, "nevt < 0");
+  if (nevt == 0) return ME_OK;
+  if (!momenta || !out_me2) return fail(ME_EINVAL, "null pointer");
+  if (!(alpha_s > 0.0)) return fail(ME_EINVAL, "alpha_s must be positive");
+  if (!h->filtered)
+    return fail(ME_EINVAL, "me_compute_noalloc needs the helicity filter to have run (me_filter_helicities, "
+                           "or all_helicities = 1)");
+  if (!h->d_static) return fail(ME_ESTATE, "no static scratch on this handle's device");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(ME_EINVAL, "me_compute_noalloc must run with the handle's device current");
+  const int nhel = (int)h->good.size();
+  const bool lane = h->desc->launch != nullptr;
+  // the FP64 grid path of the one-lane kernel (or of the team program): helicity
+  // chunks fill the grid; scratch = momenta as structure of arrays (one-lane
+  // kernel) + per-chunk partial sums
+  const int64_t per_block = lane ? 64 : h->desc->team_events_per_block;
+  const int64_t blocks = (nevt + per_block - 1) / per_block;
+  int nchunk = (int)std::min<int64_t>(nhel, std::max<int64_t>(1, (h->target_waves + blocks - 1) / blocks));
+  const int hpc = (nhel + nchunk - 1) / nchunk;
+  nchunk = (nhel + hpc - 1) / hpc;
+  const size_t soa_doubles = lane ? (size_t)nevt * h->desc->npar * 4 : 0;
+  const size_t need = (soa_doubles + (size_t)nchunk * nevt) * sizeof(double);
+  if (need > ME_NOALLOC_SCRATCH_BYTES)
+    return fail(ME_EINVAL, "me_compute_noalloc: " + std::to_string(nevt) + " events need " + std::to_string(need) +
+                               " bytes of scratch, more than ME_NOALLOC_SCRATCH_BYTES = " +
+                               std::to_string((unsigned long long)ME_NOALLOC_SCRATCH_BYTES));
+  hipStream_t s = (hipStream_t)stream;
+  double* soa = h->d_static;
+  double* partial = h->d_static + soa_doubles;
+  me::LaunchArgs a{momenta, nevt, coupling(alpha_s), h->params.mt, h->d_hels, nhel, hpc, nchunk, partial, nullptr, s};
+  hipError_t e;
+  if (lane) {
+    // every entry of the structure of arrays and of the partial sums is written
+    // before it is read: nothing needs clearing between calls
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s, momenta, nevt,
+                       h->desc->npar * 4, soa);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "momentum layout kernel launch");
+    a.soa = soa;
+    a.mstride = nevt;
+    e = h->desc->launch(a);
+  } else {
+    e = h->desc->team(a);
+  }
+  if (e != hipSuccess) return hip_fail(e, "matrix-element kernel launch");
+  const double scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((nevt + 255) / 256)), dim3(256), 0, s, partial, nchunk,
+                     nevt, scale, out_me2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
   return ME_OK;
 }
 
