@@ -28,41 +28,86 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # the work items (persistent, helicities/item, executor; the persistent grid's size does not change
 # what an item reads and writes); the numbers and the commands are in the named profile and hold
 # only for the kernel they were taken on.
+# key: (process, nevt, (persistent, hel_per_item, executor, split_wpe, split_rounds)) as me_autotune
+# reports them; no entry yet for the kernels as they are now (the momentum loads changed).
+TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds')
 MEASURED_TRAFFIC = {
-    ('gg_ttxggg', 262144, (1, 1, 0)): (4.896e12, 'profiles/me_kernel_gg_ttxggg_262144.md'),
-    ('gg_ttxggg', 262144, (0, 0, 2)): (1.127e11, 'profiles/sums_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
 SEED = {'gg_ttx': 1001, 'gg_ttxg': 1004, 'gg_ttxgg': 1002, 'gg_ttxggg': 1003, 'gg_ttxgggg': 1005}
 
 
-def cpu_baseline(process, mom, alpha_s, budget_s):
-    """Time the oracle on a bounded sample of the same workload (rank 0, N=1)."""
+_ORACLE = {}
+
+
+def _oracle_chunk(args):
+    """One worker's share of the CPU baseline: the oracle on a chunk of events, one
+    thread (numpy's BLAS pool limited to one thread in the worker)."""
+    npar, mom, alpha_s = args
+    from threadpoolctl import threadpool_limits
     from oracle import me as ome
-    proc = ome.process(NPAR[process])
-    n = 1
-    t_used = 0.0
-    done = 0
-    c0 = resource.getrusage(resource.RUSAGE_SELF)
-    w0 = time.perf_counter()
-    # double the sample until the budget is reached
-    while True:
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        ome.matrix_element(proc, mom[done:done + n], alpha_s)
-        dt = time.perf_counter() - t0
-        t_used += dt
-        done += n
-        if t_used + 1.5 * dt > budget_s or done + 2 * n > mom.shape[0]:
-            break
-        n *= 2
+        ome.matrix_element(_ORACLE[npar], mom, alpha_s)
+        return mom.shape[0], time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return 'unknown'
+
+
+def cpu_baseline(process, mom, alpha_s, budget_s):
+    """The oracle on the host cores (rank 0, N=1): a one-core calibration on a few
+    events, then one chunk per worker process (one per host core of this process's
+    CPU share, at most 16), each sized to take about half the budget; the value is
+    all the events over the wall time of the pooled run."""
+    import multiprocessing as mp
+
+    from oracle import me as ome
+    npar = NPAR[process]
+    if npar not in _ORACLE:
+        _ORACLE[npar] = ome.process(npar)
+    workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    n1 = {4: 256, 5: 64, 6: 16, 7: 4, 8: 1}[npar]
+    done1, t1 = _oracle_chunk((npar, mom[:n1], alpha_s))
+    rate1 = done1 / t1
+    per = int(max(1, min(rate1 * 0.5 * budget_s, mom.shape[0] // workers)))
+    chunks = [(npar, mom[n1 + w * per:n1 + (w + 1) * per], alpha_s) for w in range(workers)]
+    chunks = [c for c in chunks if c[1].shape[0] > 0]
+    w0 = time.perf_counter()
+    with mp.get_context('fork').Pool(len(chunks)) as pool:
+        res = pool.map(_oracle_chunk, chunks, chunksize=1)
     wall = time.perf_counter() - w0
-    c1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (c1.ru_utime - c0.ru_utime) + (c1.ru_stime - c0.ru_stime)
-    return {'value': done / t_used, 'unit': 'ME evals/s', 'cores': max(1, round(cpu / wall)),
-            'kind': 'oracle',
-            'sample': f'first {done} events of the same {process} workload, all helicities, '
-                      f'numpy FP64 oracle, {t_used:.1f} s'}
+    done = sum(r[0] for r in res)
+    per_core = sorted(r[0] / r[1] for r in res)
+    return {'value': done / wall, 'unit': 'ME evals/s', 'cores': len(chunks), 'kind': 'oracle',
+            'single_core_value': per_core[len(per_core) // 2], 'cpu_model': _cpu_model(),
+            'host_cpus': os.cpu_count(),
+            'sample': f'events {n1}..{n1 + done - 1} of the same {process} workload ({per} per worker process, '
+                      f'one thread each, all helicities, numpy FP64 oracle, {wall:.1f} s wall); single-core value: '
+                      f'median worker rate in that run (sized from events 0..{n1 - 1}, {t1:.1f} s on one core)'}
+
+
+HBM_PEAK_TBS = 8.0
+
+
+def binding_resource(traffic, ms_per_launch, achieved_tflops):
+    """Which roof the dominant kernel presses on: its measured HBM traffic per launch
+    over its duration against HBM peak, next to its FP64 rate against the FP64 peak."""
+    alu = achieved_tflops / FP64_VALU_PEAK_TFLOPS
+    if not traffic:
+        return {'fp64_frac': alu, 'hbm_frac': None, 'resource': 'unmeasured (no counter run for this kernel)'}
+    tbs = traffic[0] / (ms_per_launch * 1e-3) / 1e12
+    hbm = tbs / HBM_PEAK_TBS
+    return {'fp64_frac': alu, 'hbm_TBps': tbs, 'hbm_frac': hbm,
+            'resource': 'HBM (register-spill traffic)' if hbm > alu else 'FP64 vector ALU'}
 
 
 def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None):
@@ -217,10 +262,10 @@ def main():
             m.me_set_launch(p_, w_, h_, t_)
             m.me_set_executor(x_)
             tuned = {'persistent': p_, 'waves_per_simd': w_, 'hel_per_item': h_, 'target_waves': t_,
-                     'executor': x_}
-        elif args.autotune and mode == binding.ME_CS_FP64:
+                     'executor': x_, 'split_wpe': 0, 'split_fchunk': 0, 'split_rounds': 0, 'colour_grid': 0}
+        elif args.autotune:
             nt = min(nevt, 65536)
-            print(f'# bench autotune on {nt} events', file=sys.stderr, flush=True)
+            print(f'# bench autotune on {nt} events (mode {mode})', file=sys.stderr, flush=True)
             tuned = m.me_autotune(dmom[:nt], nt, args.alpha_s, out[:nt], stream)
         elif executor is not None:
             m.me_set_executor(executor)
@@ -272,10 +317,10 @@ def main():
     mixed = None
     if not args.fp64_only:
         try:
-            ms_m, res_m, _, _, _, _ = run(binding.ME_CS_FP16X2, (tuned or {}).get('executor'))
+            ms_m, res_m, _, tuned_m, _, _ = run(binding.ME_CS_FP16X2, (tuned or {}).get('executor'))
             rel = np.abs(res_m / res - 1)
             mixed = {'colorsum': 'split FP16 hi+lo on MFMA, FP32 accumulation, FP64 row dots',
-                     'executor': (tuned or {}).get('executor', 0),
+                     'launch': tuned_m,
                      'value': nevt / (ms_m * 1e-3), 'unit': 'ME evals/s', 'ms_per_step': ms_m,
                      'max_rel_err_vs_fp64': float(rel.max()),
                      'rms_rel_err_vs_fp64': float(np.sqrt(np.mean(rel ** 2))), 'stated_bound': 1e-5}
@@ -284,7 +329,7 @@ def main():
 
     traffic = None
     if tuned:
-        key = (process, nevt, tuple(tuned[k] for k in ('persistent', 'hel_per_item', 'executor')))
+        key = (process, nevt, tuple(tuned[k] for k in TRAFFIC_KEY))
         traffic = MEASURED_TRAFFIC.get(key)
     executor = (tuned or {}).get('executor', 0)
     kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>'}.get(executor,
@@ -315,8 +360,11 @@ def main():
                      'traffic': traffic[0] if traffic else None,
                      'traffic_source': traffic[1] if traffic else None,
                      'kernel': kname, 'flops_per_event_helicity': f_unit,
+                     'flops_source': 'operations of the generated code, counted (tests/test_generator.py)',
                      'kernel_ms_per_launch': kms / launches[binding.ME_KT_DIAGRAM],
-                     'launches': launches[binding.ME_KT_DIAGRAM]},
+                     'launches': launches[binding.ME_KT_DIAGRAM],
+                     'binding_resource': binding_resource(traffic, kms / launches[binding.ME_KT_DIAGRAM],
+                                                          achieved)},
         'kernels': kernels,
     }
     if mixed is not None:

@@ -75,6 +75,13 @@ extern "C" {
                            cores.  The group sums and flows of a chunk use at most
                            ME_SPLIT_SCRATCH_BYTES of library-owned device memory */
 
+#define ME_EXEC_BG 3    /* colour-ordered Berends-Giele recursion: a workgroup evaluates whole
+                           (event, helicity) rows level by level over ordered gluon sequences
+                           (currents and top-line spinors in LDS), writing every row's dual
+                           amplitudes (ME_SPLIT_SCRATCH_BYTES of library scratch per event
+                           chunk); then the colour form of every row on the matrix cores
+                           (FP64, or split FP16 / BF16 in those modes).  Every process has it. */
+
 /* device scratch the matrix-core colour-sum modes may hold for staged dual amplitudes */
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 /* device scratch of the split executor's colour-group sums and colour flows */
@@ -95,6 +102,8 @@ typedef struct {
   int check;            /* 1: every me_compute / me_compute_alphas / me_compute_host first checks
                            its events (see ME_CHECK_TOL) and synchronises the stream; default 0,
                            or 1 when the environment variable ME_CHECK is set to 1 */
+  int autotune;         /* 1: the first me_compute runs me_autotune on (at most 65536 of) its
+                           events before computing them (default 0) */
 } me_params;
 
 /* Input check (me_params.check): an event fails when its four-momentum is not
@@ -285,12 +294,30 @@ int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
 
 /* Autotuner (the paper scans diagrams per group and kernel splitting by hand,
  * section "Studies of a 2->6 process"; here the library times the candidates).
- * Times a fixed set of launch configurations (and, in ME_CS_FP64 mode,
- * both executors) on these events (writing out_me2, synchronising the stream)
- * and keeps the fastest; best[5] (host, may be NULL) receives (persistent,
- * waves_per_simd, hel_per_item, target_waves, executor). */
+ * Times every candidate on these events (writing out_me2, synchronising the
+ * stream) and keeps the fastest.  Candidates: the one-lane kernel's grid and
+ * persistent launches (FP64 mode; one staged launch in the matrix-core modes), the
+ * team program's helicity chunkings, and the split executor with its group-sum
+ * kernel compiled for 1 or 2 waves per SIMD, its flows formed from chunks of 8, 16
+ * or 32 group sums, and event chunks of as many whole rounds of group-sum waves as
+ * its scratch holds or of two rounds, in every colour-sum mode.  When the
+ * environment variable ME_TUNE_CACHE names a file, a result already stored there
+ * for (process, mode, nevt, device, library build) is applied without timing, and
+ * new results are appended (one JSON object per line).  best (host, may be NULL)
+ * receives the ME_TUNE_FIELDS integers (persistent, waves_per_simd, hel_per_item,
+ * target_waves, executor, split waves per SIMD, flow chunk, split rounds, colour
+ * grid; 0 in the last four = default). */
+#define ME_TUNE_FIELDS 9
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
+
+/* Split-executor variants (see me_autotune): wpe = waves per SIMD of the group-sum
+ * kernel (1 or 2), fchunk = group sums per LDS chunk of the flows kernel (8, 16, 32),
+ * rounds = events per chunk as this many whole rounds of group-sum waves (0: as many
+ * as ME_SPLIT_SCRATCH_BYTES holds), colour_grid = workgroups of the FP64 colour
+ * kernel; 0 picks the default of each.  ME_EINVAL for other values or a process
+ * without the split executor.  Results do not depend on them beyond rounding. */
+int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid);
 
 /* Uneven multi-process batch in one persistent launch (the paper evaluates one
  * process per executable; batching several is an addition).  Segment i is

@@ -25,6 +25,7 @@ ME_CS_BF16X2 = 2
 ME_EXEC_LANE = 0
 ME_EXEC_TEAM = 1
 ME_EXEC_SPLIT = 2
+ME_EXEC_BG = 3
 # per-kernel timing classes (me_kernel_times)
 ME_KT_DIAGRAM, ME_KT_FLOWS, ME_KT_COLOUR, ME_KT_REDUCE = 0, 1, 2, 3
 ME_KT_KINDS = 4
@@ -34,7 +35,7 @@ EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_compute_host', 'me_
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
            'me_compute_alphas', 'me_select', 'me_set_executor', 'me_set_kernel_timing',
-           'me_kernel_times', 'me_finalize', 'me_channel_weights', 'me_num_channels',
+           'me_kernel_times', 'me_finalize', 'me_channel_weights', 'me_num_channels', 'me_set_split',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
            'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
@@ -52,7 +53,8 @@ class MeError(RuntimeError):
 
 class me_params(ctypes.Structure):
     _fields_ = [('mt', ctypes.c_double), ('wt', ctypes.c_double), ('colorsum_mode', ctypes.c_int),
-                ('all_helicities', ctypes.c_int), ('use_graph', ctypes.c_int), ('check', ctypes.c_int)]
+                ('all_helicities', ctypes.c_int), ('use_graph', ctypes.c_int), ('check', ctypes.c_int),
+                ('autotune', ctypes.c_int)]
 
 
 class me_sur_params(ctypes.Structure):
@@ -91,6 +93,7 @@ def load(path=LIB_PATH):
                                      ctypes.POINTER(i64), ctypes.c_double, ctypes.POINTER(vp), vp]
     lib.me_compute_alphas.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.me_set_executor.argtypes = [vp, ctypes.c_int]
+    lib.me_set_split.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.me_select.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.me_finalize.argtypes = [vp]
     lib.me_channel_weights.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp]
@@ -159,7 +162,8 @@ class MatrixElement:
     """One handle of the C ABI for one process."""
 
     def __init__(self, process: str, mt: float = 173.0, all_helicities: bool = False,
-                 colorsum_mode: int = ME_CS_FP64, use_graph: bool = False, check=None, wt: float = 0.0):
+                 colorsum_mode: int = ME_CS_FP64, use_graph: bool = False, check=None, wt: float = 0.0,
+                 autotune: bool = False):
         lib = load()
         p = me_params()
         _check(lib.me_params_default(ctypes.byref(p)))
@@ -170,6 +174,7 @@ class MatrixElement:
         p.use_graph = int(use_graph)
         if check is not None:
             p.check = int(bool(check))
+        p.autotune = int(bool(autotune))
         h = ctypes.c_void_p()
         _check(lib.me_init(process.encode(), ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -241,11 +246,16 @@ class MatrixElement:
     def me_set_launch(self, persistent, waves_per_simd=1, hel_per_item=0, target_waves=4096):
         _check(load().me_set_launch(self._h, persistent, waves_per_simd, hel_per_item, target_waves))
 
+    TUNE_FIELDS = ('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves', 'executor', 'split_wpe',
+                   'split_fchunk', 'split_rounds', 'colour_grid')
+
     def me_autotune(self, momenta, nevt, alpha_s, out, stream=None):
-        best = (ctypes.c_int32 * 5)()
+        best = (ctypes.c_int32 * len(self.TUNE_FIELDS))()
         _check(load().me_autotune(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream), best))
-        return dict(zip(('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves', 'executor'),
-                        list(best)))
+        return dict(zip(self.TUNE_FIELDS, list(best)))
+
+    def me_set_split(self, wpe=0, fchunk=0, rounds=0, colour_grid=0):
+        _check(load().me_set_split(self._h, wpe, fchunk, rounds, colour_grid))
 
     def me_set_executor(self, executor):
         _check(load().me_set_executor(self._h, int(executor)))

@@ -27,6 +27,31 @@ PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg', 'gg_ttxgggg']
 # headers the generated process units include
 PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h', 'me_team.h']
 SDE_HEADERS = ['me_sde.h', 'me_sde_desc.h']
+BG_HEADERS = ['me_device.h', 'me_bg.h', 'me_bg_desc.h', 'colour_mfma.h', 'me_colour_big.h']
+
+
+def bg_unit(name, n):
+    """Source of the Berends-Giele unit of a process: the recursion kernel for n gluons
+    and the FP64 colour form of its n! flows (the matrix in LDS up to 128 flows,
+    streamed through LDS in tiles beyond)."""
+    import math
+    ncol = math.factorial(n)
+    if ncol <= 128:
+        colour = ('  constexpr int RPB = 4 * 8 * COLOUR_F64_TILES;\n'
+                  '  const int64_t tiles = (nrow + RPB - 1) / RPB;\n'
+                  f'  hipLaunchKernelGGL(colour_f64_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, COLOUR_F64_GRID)), '
+                  'dim3(256), 0, s, jt, nrow, cf64, out);\n')
+    else:
+        colour = ('  const int64_t tiles = (nrow + 32 * BIG_NT - 1) / (32 * BIG_NT);\n'
+                  f'  hipLaunchKernelGGL(colour_f64_big_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, BIG_GRID)), '
+                  'dim3(256), 0, s, jt, nrow, cf64, out);\n')
+    return (f'// Berends-Giele executor of process {name} (generated).\n'
+            '#include <algorithm>\n#include "me_bg.h"\n#include "colour_mfma.h"\n#include "me_colour_big.h"\n'
+            'namespace me {\n'
+            f'static hipError_t colour64_{name}(const double* jt, int64_t nrow, const double* cf64, double* out, '
+            'hipStream_t s) {\n' + colour + '  return hipGetLastError();\n}\n'
+            f'const BgDesc* bg_{name}() {{\n  static const BgDesc d = {{"{name}", {n}, {ncol}, &launch_bg<{n}>, '
+            f'&colour64_{name}}};\n  return &d;\n}}\n}}\n')
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',
@@ -86,6 +111,9 @@ def generate_sources(procs, build_dir):
                     f'#include "{name}.inc"\n#include "me_kernels.h"\n'
                     f'namespace me {{\nconst ProcessDesc* process_{name}() '
                     f'{{ return describe<me::{name}>(nullptr); }}\n}}\n')
+        bgpath = os.path.join(GEN, f'bg_{name}.hip')
+        _write_if_changed(bgpath, bg_unit(name, codegen.PROCESS_NPAR[name] - 2))
+        units.append((bgpath, os.path.join(OBJ, f'bg_{name}.o'), [os.path.join(CSRC, h) for h in BG_HEADERS]))
         path = os.path.join(GEN, f'proc_{name}.hip')
         _write_if_changed(path, unit)
         units.append((path, os.path.join(OBJ, f'proc_{name}.o'),
@@ -108,6 +136,9 @@ def generate_sources(procs, build_dir):
     reg += [f'const SdeDesc* sde_{n}();' for n in lane]
     reg.append('static const SdeDesc* (*const kSde[])() = {'
                + ', '.join(f'sde_{n}' if n in lane else 'nullptr' for n in procs) + '};')
+    # Berends-Giele executors, aligned with kProcesses
+    reg += [f'const BgDesc* bg_{n}();' for n in procs]
+    reg.append('static const BgDesc* (*const kBg[])() = {' + ', '.join(f'bg_{n}' for n in procs) + '};')
     batch = ['// Multi-process batch kernel over the processes of this library (generated).']
     batch += [f'#include "{n}.inc"' for n in lane]
     batch += ['#include "me_kernels.h"', 'namespace me {',
@@ -122,15 +153,20 @@ def generate_sources(procs, build_dir):
                      [os.path.join(GEN, f'{n}.inc') for n in lane] + [os.path.join(CSRC, h) for h in PROC_HEADERS]))
     units.append((os.path.join(CSRC, 'me_api.hip'), os.path.join(build_dir, 'me_api.o'),
                   [regfile, os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_process.h'),
-                   os.path.join(CSRC, 'me_error.h'), os.path.join(CSRC, 'me_sde_desc.h')]))
+                   os.path.join(CSRC, 'me_error.h'), os.path.join(CSRC, 'me_sde_desc.h'),
+                   os.path.join(CSRC, 'me_bg_desc.h'), os.path.join(CSRC, 'me_bg_tables.h')]))
     units.append((os.path.join(CSRC, 'surrogate.hip'), os.path.join(OBJ, 'surrogate.o'),
                   [os.path.join(INCLUDE, 'megpu.h'), os.path.join(CSRC, 'me_error.h')]))
     return units
 
 
-def _compile(src, obj, extra_deps, build_dir, force=False):
+def _compile(src, obj, extra_deps, build_dir, force=False, build_id=None):
     deps = [src] + list(extra_deps)
     flags = FLAGS + (['-I', build_dir] if src.endswith('me_api.hip') or src.startswith(build_dir) else [])
+    if build_id and src.endswith('me_api.hip'):
+        # the library's build identity (a hash of every source it is compiled from)
+        # keys the autotuner's result cache
+        flags = flags + [f'-DME_BUILD_ID="{build_id}"']
     # the object is reused only when the flags and the contents of every input are
     # those it was compiled from (contents, not modification times: a source edited
     # while its object was compiling must not pass for up to date)
@@ -166,9 +202,15 @@ def build(procs=None, jobs=None, verbose=True, lib=LIB, force=False):
     # the largest units first: the batch kernel and the process with most diagrams
     units.sort(key=lambda u: (not u[0].endswith('batch.hip'), 'ggg' not in u[0], -len(os.path.basename(u[0]))))
     jobs = jobs or min(8, os.cpu_count() or 4)
+    ident = hashlib.sha1()
+    for src, _, deps in sorted(units):
+        for d in [src] + sorted(deps):
+            with open(d, 'rb') as f:
+                ident.update(f.read())
+    build_id = ident.hexdigest()[:16]
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, src, obj, deps, build_dir, force): src for src, obj, deps in units}
+        futs = {ex.submit(_compile, src, obj, deps, build_dir, force, build_id): src for src, obj, deps in units}
         for f in cf.as_completed(futs):
             obj, rebuilt = f.result()
             objs.append(obj)

@@ -21,6 +21,8 @@
 #include "me_error.h"
 #include "me_process.h"
 #include "me_sde_desc.h"
+#include "me_bg_desc.h"
+#include "me_bg_tables.h"
 
 namespace me {
 #include "registry.inc"   // const ProcessDesc* (*const kProcesses[])() and kNumProcesses
@@ -169,6 +171,10 @@ struct me_ctx {
   const me::ProcessDesc* desc = nullptr;
   int proc_index = 0;         // position in the library's process list (batch kernel)
   const me::SdeDesc* sde = nullptr;  // single-diagram-enhancement kernel, or nullptr
+  const me::BgDesc* bg = nullptr;    // Berends-Giele executor
+  uint16_t* d_bg_sub = nullptr;      // its sequence tables (device)
+  uint8_t* d_bg_mask = nullptr;
+  uint8_t* d_bg_last = nullptr;
   me_params params{};
   std::vector<int> good;      // host copy of the good helicities
   int* d_hels = nullptr;      // device, good helicities (capacity nhel)
@@ -200,6 +206,12 @@ struct me_ctx {
   int hel_per_item = 0;       // helicities per work item (0: all)
   int target_waves = 4096;    // grid path: waves to aim for (helicity chunks fill the rest)
   int executor = ME_EXEC_LANE;  // FP64 path: one lane per (event, helicity), or a team of lanes
+  // split executor variants (me_set_split; 0 = default)
+  int split_wpe = 0;          // group-sum kernel compiled for 1 or 2 waves per SIMD
+  int split_fchunk = 0;       // flows kernel: group sums per LDS chunk (8, 16, 32)
+  int split_rounds = 0;       // events per chunk as whole rounds of group-sum waves (0: as many as fit)
+  int colour_grid = 0;        // workgroups of the FP64 colour kernel
+  bool tuned = false;         // me_autotune has run (or found its configuration in the cache)
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
   // captured launch sequence of the last (momenta, out, nevt, alpha_s)
@@ -302,6 +314,36 @@ int enqueue_soa(me_ctx* c, const double* momenta, int64_t nevt, hipStream_t s) {
   return ME_OK;
 }
 
+// Sequence tables of the Berends-Giele executor, uploaded on first use.
+int ensure_bg_tables(me_ctx* c) {
+  if (c->d_bg_sub) return ME_OK;
+  const me::BgHostTables t = me::bg_build_tables(c->bg->n);
+  hipError_t e = hipMalloc(&c->d_bg_sub, t.sub.size() * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&c->d_bg_mask, t.mask.size());
+  if (e == hipSuccess) e = hipMalloc(&c->d_bg_last, t.last.size());
+  if (e == hipSuccess) e = hipMemcpy(c->d_bg_sub, t.sub.data(), t.sub.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_bg_mask, t.mask.data(), t.mask.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_bg_last, t.last.data(), t.last.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (c->d_bg_sub) (void)hipFree(c->d_bg_sub);
+    if (c->d_bg_mask) (void)hipFree(c->d_bg_mask);
+    if (c->d_bg_last) (void)hipFree(c->d_bg_last);
+    c->d_bg_sub = nullptr;
+    c->d_bg_mask = c->d_bg_last = nullptr;
+    return fail(ME_ENOMEM, std::string("Berends-Giele tables: ") + hipGetErrorString(e));
+  }
+  return ME_OK;
+}
+
+// Events per chunk of the Berends-Giele executor: the dual amplitudes of a chunk
+// (2 NCOL doubles per row, nhel rows per event) fill at most ME_SPLIT_SCRATCH_BYTES.
+int64_t bg_chunk(const me_ctx* h, int64_t nevt) {
+  const size_t per_event = sizeof(double) * 2 * (size_t)h->desc->ncol * h->good.size();
+  int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
+  chunk = std::max<int64_t>(64, (chunk / 64) * 64);
+  return std::min<int64_t>(chunk, nevt);
+}
+
 // Events per chunk of the split executor: the group sums and the colour flows of a
 // chunk (2 NGROUP + 2 NCOL doubles per row, nhel rows per event) fill at most
 // ME_SPLIT_SCRATCH_BYTES.  Where the limit allows, the chunk is a whole number of
@@ -311,12 +353,15 @@ int64_t split_chunk(const me_ctx* h, int64_t nevt) {
   const int64_t nhel = (int64_t)h->good.size();
   const size_t per_event = sizeof(double) * 2 * (size_t)(h->desc->ngroup + h->desc->ncol) * (size_t)nhel;
   int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
-  const int64_t slots = (int64_t)h->simds * std::max(1, h->desc->sums_wpe);
+  const int wpe = h->split_wpe ? h->split_wpe : h->desc->sums_wpe;
+  const int64_t slots = (int64_t)h->simds * std::max(1, wpe);
   const int64_t step = 64 * (slots / std::gcd(slots, nhel));
-  if (chunk >= step)
+  if (chunk >= step) {
     chunk = (chunk / step) * step;
-  else
+    if (h->split_rounds > 0) chunk = std::min<int64_t>(chunk, (int64_t)h->split_rounds * step);
+  } else {
     chunk = std::max<int64_t>(64, (chunk / 64) * 64);
+  }
   return std::min<int64_t>(chunk, nevt);
 }
 
@@ -433,7 +478,7 @@ int build_tables(me_ctx* c, int mode) {
 // Integer colour matrix in FP64 for the split executor's matrix-core colour form:
 // [16 MB][4 KS] zero padded, MB = ceil(NCOL / 16), KS = ceil(NCOL / 4).
 int build_cf64(me_ctx* c) {
-  if (!c->desc->split) return ME_OK;
+  if (!c->desc->split && !c->bg) return ME_OK;
   const int n = c->desc->ncol;
   const int kp = ((n + 3) / 4) * 4, mp = ((n + 15) / 16) * 16;
   std::vector<double> t((size_t)mp * kp, 0.0);
@@ -505,6 +550,7 @@ int me_params_default(me_params* p) {
   p->colorsum_mode = ME_CS_FP64;
   p->all_helicities = 0;
   p->use_graph = 0;
+  p->autotune = 0;
   const char* env = std::getenv("ME_CHECK");
   p->check = (env && std::strcmp(env, "1") == 0) ? 1 : 0;
   return ME_OK;
@@ -534,6 +580,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
   c->desc = desc;
   c->proc_index = proc_index;
   c->sde = me::kSde[proc_index] ? me::kSde[proc_index]() : nullptr;
+  c->bg = me::kBg[proc_index]();
   c->params = prm;
   if (!desc->launch) c->executor = ME_EXEC_TEAM;
   c->good.resize(desc->nhel);
@@ -624,6 +671,9 @@ int me_finalize(me_handle h) {
   if (h->d_counter) (void)hipFree(h->d_counter);
   if (h->d_check) (void)hipFree(h->d_check);
   if (h->d_soa) (void)hipFree(h->d_soa);
+  if (h->d_bg_sub) (void)hipFree(h->d_bg_sub);
+  if (h->d_bg_mask) (void)hipFree(h->d_bg_mask);
+  if (h->d_bg_last) (void)hipFree(h->d_bg_last);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   free_tables(h);
@@ -767,6 +817,16 @@ namespace {
 // Size the scratch of one me_compute call (outside any capture).
 int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
+  if (h->executor == ME_EXEC_BG) {
+    // dual amplitudes of an event chunk [2 NCOL][rows] in the split scratch, then
+    // one colour sum per row
+    int rc = ensure_bg_tables(h);
+    if (rc) return rc;
+    const int64_t chunk = bg_chunk(h, nevt);
+    rc = ensure_sums(h, (size_t)chunk * nhel * 2 * h->desc->ncol);
+    if (rc) return rc;
+    return ensure_partial(h, (size_t)chunk * nhel);
+  }
   if (h->desc->launch) {
     // the one-lane kernels (lane and split executors) read the momenta as a
     // structure of arrays
@@ -824,6 +884,41 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
             hipStream_t s, const double* alphas = nullptr) {
   const int nhel = (int)h->good.size();
   const double g = coupling(alpha_s);
+  if (h->executor == ME_EXEC_BG) {
+    // event chunks: dual amplitudes of every (helicity, event) row by the recursion,
+    // the colour form of every row (FP64 on the matrix cores, or split FP16 / BF16),
+    // then the fixed-order helicity sum of the chunk
+    const int64_t chunk = bg_chunk(h, nevt);
+    const int npar = h->desc->npar;
+    const bool fp64 = h->params.colorsum_mode == ME_CS_FP64;
+    const double scale = fp64 ? 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den) : 1.0 / h->desc->iden;
+    for (int64_t off = 0; off < nevt; off += chunk) {
+      const int64_t n = std::min<int64_t>(chunk, nevt - off);
+      me::BgArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_bg_sub, h->d_bg_mask,
+                   h->d_bg_last, alphas ? alphas + off : nullptr, h->d_sums, s};
+      KernelMark kd(h, ME_KT_DIAGRAM, s);
+      hipError_t e = h->bg->launch(a);
+      if (e != hipSuccess) return hip_fail(e, "Berends-Giele kernel launch");
+      kd.done();
+      KernelMark kc(h, ME_KT_COLOUR, s);
+      if (fp64) {
+        e = h->bg->colour64(h->d_sums, n * nhel, h->d_cf64, h->d_partial, s);
+      } else {
+        me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
+                          h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
+        e = h->desc->colour(ca);
+      }
+      if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+      kc.done();
+      KernelMark kr(h, ME_KT_REDUCE, s);
+      hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
+                         nhel, n, scale, out_me2 + off);
+      kr.done();
+      e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    }
+    return ME_OK;
+  }
   if (h->desc->launch && !(h->params.colorsum_mode == ME_CS_FP64 && h->executor == ME_EXEC_TEAM)) {
     int rc = enqueue_soa(h, momenta, nevt, s);
     if (rc) return rc;
@@ -840,6 +935,9 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
       me::SplitArgs a{h->d_soa + off, nevt, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
                       h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}};
+      a.wpe = h->split_wpe;
+      a.fchunk = h->split_fchunk;
+      a.colour_grid = h->colour_grid;
       // with timing on, the launcher records a.ev[k] before kernel k (sums, flows,
       // colour form) and a.ev[3] after the last; the events are marked here (taken
       // from the pool) and re-recorded at their place in the launcher
@@ -930,6 +1028,8 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       double* jt = h->d_sums + (size_t)chunk * nhel * 2 * h->desc->ngroup;
       me::SplitArgs a{h->d_soa + off, nevt, n, g, h->params.mt, h->d_hels, nhel, h->d_sums, jt,
                       h->d_cf64, h->d_partial, alphas ? alphas + off : nullptr, s, {}, 1};
+      a.wpe = h->split_wpe;
+      a.fchunk = h->split_fchunk;
       if (h->timing)
         for (int k = 0; k < 3; ++k) a.ev[k] = mark_event(h, s);
       hipError_t e = h->desc->split(a);
@@ -1006,6 +1106,11 @@ int me_compute(me_handle h, const double* momenta, int64_t nevt, double alpha_s,
   }
   if (!h->filtered) {
     rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
+    if (rc) return rc;
+  }
+  if (h->params.autotune && !h->tuned) {
+    // tune once, on (at most 65536 of) this call's events, before computing them
+    rc = me_autotune(h, momenta, std::min<int64_t>(nevt, 65536), alpha_s, out_me2, stream, nullptr);
     if (rc) return rc;
   }
   rc = prepare(h, nevt);
@@ -1357,6 +1462,114 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
   return ME_OK;
 }
 
+int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!h->desc->split) return fail(ME_EINVAL, std::string(h->desc->name) + " has no split executor");
+  if (!(wpe == 0 || wpe == 1 || wpe == 2) || !(fchunk == 0 || fchunk == 8 || fchunk == 16 || fchunk == 32) ||
+      rounds < 0 || colour_grid < 0)
+    return fail(ME_EINVAL, "bad split configuration");
+  h->split_wpe = wpe;
+  h->split_fchunk = fchunk;
+  h->split_rounds = rounds;
+  h->colour_grid = colour_grid;
+  drop_graph(h);
+  return ME_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+#ifndef ME_BUILD_ID
+#define ME_BUILD_ID "unversioned"
+#endif
+
+// One autotuner candidate: launch configuration, executor and split variants.
+struct TuneCand {
+  int v[ME_TUNE_FIELDS];   // persistent, waves/SIMD, hel/item, target waves, executor, wpe, fchunk, rounds, grid
+};
+
+void apply_cand(me_ctx* h, const TuneCand& c, int default_tw) {
+  h->persistent = c.v[0];
+  h->waves_per_simd = c.v[1];
+  h->hel_per_item = c.v[2];
+  h->target_waves = c.v[3] > 0 ? c.v[3] : default_tw;
+  h->executor = c.v[4];
+  h->split_wpe = c.v[5];
+  h->split_fchunk = c.v[6];
+  h->split_rounds = c.v[7];
+  h->colour_grid = c.v[8];
+}
+
+TuneCand current_cand(const me_ctx* h) {
+  return TuneCand{{h->persistent, h->waves_per_simd, h->hel_per_item, h->target_waves, h->executor, h->split_wpe,
+                   h->split_fchunk, h->split_rounds, h->colour_grid}};
+}
+
+// Key of a tuning result: process, colour-sum mode, batch size, device and library build.
+std::string tune_key(const me_ctx* h, int64_t nevt) {
+  std::string dev = "unknown";
+  int cus = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+    dev = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& ch : dev)
+    if (ch == '"' || ch == '\\') ch = '_';
+  return std::string(h->desc->name) + "|mode" + std::to_string(h->params.colorsum_mode) + "|nevt" +
+         std::to_string(nevt) + "|" + dev + "|cu" + std::to_string(cus) + "|" + ME_BUILD_ID;
+}
+
+// The cache file (ME_TUNE_CACHE) holds one JSON object per line:
+//   {"key": "<key>", "config": [9 integers], "ms": <time>}
+// The last line with a key wins; lines that do not parse are skipped.
+bool cache_lookup(const std::string& key, TuneCand* out) {
+  const char* path = std::getenv("ME_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string pat = "{\"key\": \"" + key + "\", \"config\": [";
+  while (std::fgets(line, sizeof line, f)) {
+    if (std::strncmp(line, pat.c_str(), pat.size()) != 0) continue;
+    TuneCand c;
+    const char* q = line + pat.size();
+    int k = 0;
+    for (; k < ME_TUNE_FIELDS; ++k) {
+      char* end = nullptr;
+      const long v = std::strtol(q, &end, 10);
+      if (end == q) break;
+      c.v[k] = (int)v;
+      q = end;
+      while (*q == ',' || *q == ' ') ++q;
+    }
+    if (k == ME_TUNE_FIELDS && *q == ']') {
+      *out = c;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, const TuneCand& c, float ms) {
+  const char* path = std::getenv("ME_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"config\": [", key.c_str());
+  for (int k = 0; k < ME_TUNE_FIELDS; ++k) std::fprintf(f, "%s%d", k ? ", " : "", c.v[k]);
+  std::fprintf(f, "], \"ms\": %.4f}\n", ms);
+  std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best) {
   int rc = check_handle(h);
@@ -1367,31 +1580,58 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     rc = me_filter_helicities(h, momenta, nevt, alpha_s, stream);
     if (rc) return rc;
   }
-  struct Cand { int p, w, hpi, tw, x; };
-  std::vector<Cand> cands;
-  if (h->desc->launch)
-    cands = {{0, 1, 0, 1024, 0}, {0, 1, 0, 4096, 0}, {0, 1, 0, 16384, 0}, {1, 1, 0, 0, 0},
-             {1, 1, 8, 0, 0},    {1, 2, 8, 0, 0},    {1, 1, 1, 0, 0},     {1, 2, 1, 0, 0}};
-  if (h->params.colorsum_mode == ME_CS_FP64) {
-    for (int tw : {1024, 262144, 1048576}) cands.push_back({0, 1, 0, tw, 1});
-    if (h->desc->split) cands.push_back({0, 1, 0, 4096, ME_EXEC_SPLIT});
+  const std::string key = tune_key(h, nevt);
+  TuneCand hit;
+  if (cache_lookup(key, &hit) && (hit.v[4] != ME_EXEC_SPLIT || h->desc->split) &&
+      (hit.v[4] != ME_EXEC_LANE || h->desc->launch)) {
+    apply_cand(h, hit, h->target_waves);
+    drop_graph(h);
+    h->tuned = true;
+    if (best)
+      for (int k = 0; k < ME_TUNE_FIELDS; ++k) best[k] = current_cand(h).v[k];
+    return ME_OK;
   }
-  const int save_p = h->persistent, save_w = h->waves_per_simd, save_hpi = h->hel_per_item,
-            save_tw = h->target_waves, save_graph = h->params.use_graph, save_x = h->executor;
+  const bool fp64 = h->params.colorsum_mode == ME_CS_FP64;
+  std::vector<TuneCand> cands;
+  if (h->desc->launch) {
+    if (fp64) {
+      const int lane[8][4] = {{0, 1, 0, 1024}, {0, 1, 0, 4096}, {0, 1, 0, 16384}, {1, 1, 0, 0},
+                              {1, 1, 8, 0},    {1, 2, 8, 0},    {1, 1, 1, 0},     {1, 2, 1, 0}};
+      for (const auto& l : lane) cands.push_back(TuneCand{{l[0], l[1], l[2], l[3], ME_EXEC_LANE, 0, 0, 0, 0}});
+    } else {
+      // the matrix-core modes stage one helicity per chunk: the launch fields do not matter
+      cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_LANE, 0, 0, 0, 0}});
+    }
+  }
+  if (fp64) {
+    for (int tw : {1024, 262144, 1048576}) cands.push_back(TuneCand{{0, 1, 0, tw, ME_EXEC_TEAM, 0, 0, 0, 0}});
+  } else if (!h->desc->launch) {
+    cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_TEAM, 0, 0, 0, 0}});
+  }
+  cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0}});
+  if (h->desc->split) {
+    // group-sum kernel variants (waves per SIMD), flow chunk sizes and event chunks
+    // (as many whole rounds of group-sum waves as fit the scratch, or two rounds)
+    for (int wpe : {1, 2})
+      for (int fch : {8, 16, 32})
+        for (int rounds : {0, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_SPLIT, wpe, fch, rounds, 0}});
+  }
+  const TuneCand saved = current_cand(h);
+  const int save_graph = h->params.use_graph;
   const bool save_timing = h->timing;
   h->params.use_graph = 0;
   h->timing = false;   // the candidates' launches are not part of a timed measurement
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    h->params.use_graph = save_graph;
+    h->timing = save_timing;
     return fail(ME_EHIP, "hipEventCreate");
+  }
   float best_ms = 0.0f;
   int best_i = -1;
   for (size_t i = 0; i < cands.size() && rc == ME_OK; ++i) {
-    h->persistent = cands[i].p;
-    h->waves_per_simd = cands[i].w;
-    h->hel_per_item = cands[i].hpi;
-    h->target_waves = cands[i].tw > 0 ? cands[i].tw : save_tw;
-    h->executor = cands[i].x;
+    apply_cand(h, cands[i], saved.v[3]);
     rc = prepare(h, nevt);
     if (rc == ME_OK) rc = enqueue(h, momenta, nevt, alpha_s, out_me2, s);   // warm-up
     if (rc) break;
@@ -1412,18 +1652,12 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   h->timing = save_timing;
   drop_graph(h);
   if (rc || best_i < 0) {
-    h->persistent = save_p;
-    h->waves_per_simd = save_w;
-    h->hel_per_item = save_hpi;
-    h->target_waves = save_tw;
-    h->executor = save_x;
+    apply_cand(h, saved, saved.v[3]);
     return rc ? rc : fail(ME_EHIP, "autotune found no configuration");
   }
-  h->persistent = cands[best_i].p;
-  h->waves_per_simd = cands[best_i].w;
-  h->hel_per_item = cands[best_i].hpi;
-  h->target_waves = cands[best_i].tw > 0 ? cands[best_i].tw : save_tw;
-  h->executor = cands[best_i].x;
+  apply_cand(h, cands[best_i], saved.v[3]);
+  h->tuned = true;
+  cache_store(key, current_cand(h), best_ms);
   // scratch that only a losing candidate needed is released (the split executor's
   // group sums alone can take ME_SPLIT_SCRATCH_BYTES); the next me_compute sizes
   // what the winner needs
@@ -1438,11 +1672,8 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     h->jamps_cap = 0;
   }
   if (best) {
-    best[0] = h->persistent;
-    best[1] = h->waves_per_simd;
-    best[2] = h->hel_per_item;
-    best[3] = h->target_waves;
-    best[4] = h->executor;
+    const TuneCand c = current_cand(h);
+    for (int k = 0; k < ME_TUNE_FIELDS; ++k) best[k] = c.v[k];
   }
   return ME_OK;
 }
@@ -1450,7 +1681,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
 int me_set_executor(me_handle h, int executor) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM && executor != ME_EXEC_SPLIT)
+  if (executor != ME_EXEC_LANE && executor != ME_EXEC_TEAM && executor != ME_EXEC_SPLIT && executor != ME_EXEC_BG)
     return fail(ME_EINVAL, "unknown executor");
   if ((executor == ME_EXEC_LANE && !h->desc->launch) || (executor == ME_EXEC_SPLIT && !h->desc->split))
     return fail(ME_EINVAL, std::string(h->desc->name) + " has only the team executor");

@@ -1,0 +1,44 @@
+// Host-side description of a process's Berends-Giele executor (kernels in
+// me_bg.h): its launcher and the FP64 colour form of its dual amplitudes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+// Tables shared by every row (device, read-only; built by bg_build_tables).
+struct BgTables {
+  const uint16_t* sub;   // [nslot][T]: slot of s[a:b] at entry b (b - 1) / 2 + a, T = N (N + 1) / 2
+  const uint8_t* mask;   // [nslot]: gluon subset of each sequence (bit = gluon slot)
+  const uint8_t* last;   // [nslot]: last gluon of each sequence
+};
+
+// One chunk of rows (row = k n + e: good helicity k, event e of the chunk).
+struct BgArgs {
+  const double* mom;     // device, [n][npar][4] (the chunk's events)
+  int64_t n;
+  double g, mt;
+  const int* hels;       // device, good helicities
+  int nhel;
+  const uint16_t* sub;   // device tables (BgTables)
+  const uint8_t* mask;
+  const uint8_t* last;
+  const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
+  double* jt;            // device, dual amplitudes [2 NCOL][n nhel]
+  hipStream_t stream;
+};
+
+using BgLauncher = hipError_t (*)(const BgArgs&);
+// FP64 colour form of rows jt[2 NCOL][nrow] into out[nrow] (times the denominator)
+using Colour64Launcher = hipError_t (*)(const double* jt, int64_t nrow, const double* cf64, double* out,
+                                        hipStream_t stream);
+
+struct BgDesc {
+  const char* name;
+  int n;                 // gluons
+  int ncol;              // orderings = colour flows
+  BgLauncher launch;
+  Colour64Launcher colour64;
+};
+
+}  // namespace me

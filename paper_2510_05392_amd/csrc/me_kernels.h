@@ -202,8 +202,8 @@ hipError_t launch_colour(const ColourArgs& a) {
 //    through LDS in chunks of FCHUNK groups (each sum read from HBM once); wave w
 //    keeps its quarter of the colour flows in registers and writes them out;
 //  colour_f64_kernel: the colour form of every row on the FP64 matrix cores.
-template <class P, int K>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P::SUMS_WPE, P::SUMS_WPE)))
+template <class P, int K, int W>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W, W)))
 sums_kernel(const double* __restrict__ mom, int64_t mstride, int64_t n, double g, double mt,
             const int* __restrict__ hels, int nhel, double* __restrict__ sums, const double* __restrict__ alphas) {
   const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
@@ -218,25 +218,33 @@ sums_kernel(const double* __restrict__ mom, int64_t mstride, int64_t n, double g
   P::template group_sums_part<K>(p, lam, g, mt, sums + (int64_t)k * n + e, rows);
 }
 
-// the group-sum kernels of parts K, K + 1, ..., NPART - 1, in order
-template <class P, int K = 0>
-hipError_t launch_sums(const SplitArgs& a) {
+// the group-sum kernels of parts K, K + 1, ..., NPART - 1, in order, compiled for W
+// waves per SIMD (the variants are 1 and 2; a.wpe picks one, 0 the process default)
+template <class P, int W, int K = 0>
+hipError_t launch_sums_w(const SplitArgs& a) {
   if constexpr (K == P::NPART) {
     return hipSuccess;
   } else {
-    hipLaunchKernelGGL((sums_kernel<P, K>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0,
+    hipLaunchKernelGGL((sums_kernel<P, K, W>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.nhel), dim3(64), 0,
                        a.stream, a.soa, a.mstride, a.n, a.g, a.mt, a.hels, a.nhel, a.sums, a.alphas);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_sums<P, K + 1>(a);
+    return launch_sums_w<P, W, K + 1>(a);
   }
 }
 
-// sums: [2 NGROUP][rows]; jt: [2 NCOL][rows] (real, imaginary part of each flow).
 template <class P>
+hipError_t launch_sums(const SplitArgs& a) {
+  const int w = a.wpe ? a.wpe : P::SUMS_WPE;
+  if (w == 1) return launch_sums_w<P, 1>(a);
+  if (w == 2) return launch_sums_w<P, 2>(a);
+  return hipErrorInvalidValue;
+}
+
+// sums: [2 NGROUP][rows]; jt: [2 NCOL][rows] (real, imaginary part of each flow).
+template <class P, int CH>
 __global__ void __launch_bounds__(256) flows_kernel(const double* __restrict__ sums, int64_t rows,
                                                     double* __restrict__ jt) {
-  constexpr int CH = P::FCHUNK;
   constexpr int NCH = (P::NGROUP + CH - 1) / CH;
   constexpr int PER = CH / 2;   // doubles of a chunk (2 CH x 64) each of the 256 threads stages
   static_assert(CH % 2 == 0, "chunk of group sums must split evenly over 256 threads");
@@ -272,7 +280,7 @@ __global__ void __launch_bounds__(256) flows_kernel(const double* __restrict__ s
 #pragma unroll
     for (int i = 0; i < PER; ++i) st2[i] = st[i];
     if (c + 2 < NCH) load(c + 2);
-    P::flow_chunk(w, c, &buf[c & 1][lane], acc);
+    P::template flow_chunk_t<CH>(w, c, &buf[c & 1][lane], acc);
     if (c + 1 < NCH) {
 #pragma unroll
       for (int i = 0; i < PER; ++i) buf[(c + 1) & 1][(w + 4 * i) * 64 + lane] = st2[i];
@@ -297,15 +305,26 @@ hipError_t launch_split(const SplitArgs& a) {
   hipError_t e = launch_sums<P>(a);
   if (e != hipSuccess) return e;
   if (a.ev[1]) (void)hipEventRecord(a.ev[1], a.stream);
-  hipLaunchKernelGGL(flows_kernel<P>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, a.stream, a.sums, rows,
-                     a.jt);
+  // flows in chunks of CH group sums (the compiled sizes 8, 16, 32; a.fchunk picks
+  // one, 0 the process default)
+  const int ch = a.fchunk ? a.fchunk : P::FCHUNK;
+  const dim3 fgrid((unsigned)((rows + 63) / 64));
+  if (ch == 8)
+    hipLaunchKernelGGL((flows_kernel<P, 8>), fgrid, dim3(256), 0, a.stream, a.sums, rows, a.jt);
+  else if (ch == 16)
+    hipLaunchKernelGGL((flows_kernel<P, 16>), fgrid, dim3(256), 0, a.stream, a.sums, rows, a.jt);
+  else if (ch == 32)
+    hipLaunchKernelGGL((flows_kernel<P, 32>), fgrid, dim3(256), 0, a.stream, a.sums, rows, a.jt);
+  else
+    return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.ev[2]) (void)hipEventRecord(a.ev[2], a.stream);
   if (a.flows_only) return hipSuccess;
   constexpr int RPB = 4 * 8 * COLOUR_F64_TILES;   // rows per tile of the colour kernel
   const int64_t tiles = (rows + RPB - 1) / RPB;
-  hipLaunchKernelGGL(colour_f64_kernel<P::NCOL>, dim3((unsigned)std::min<int64_t>(tiles, COLOUR_F64_GRID)),
+  const int64_t grid = a.colour_grid > 0 ? a.colour_grid : COLOUR_F64_GRID;
+  hipLaunchKernelGGL(colour_f64_kernel<P::NCOL>, dim3((unsigned)std::min<int64_t>(tiles, grid)),
                      dim3(256), 0, a.stream, a.jt, rows, a.cf64, a.partial);
   e = hipGetLastError();
   if (e == hipSuccess && a.ev[3]) (void)hipEventRecord(a.ev[3], a.stream);

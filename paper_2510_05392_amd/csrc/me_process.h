@@ -92,6 +92,9 @@ struct SplitArgs {
   hipStream_t stream;
   hipEvent_t ev[4];      // recorded before the first, between, and after the last kernel, or nullptr
   int flows_only;        // stop after the flows (a matrix-core colour sum of jt follows)
+  int wpe = 0;           // group-sum kernel variant: waves per SIMD 1 or 2 (0: the process default)
+  int fchunk = 0;        // flows kernel variant: group sums per LDS chunk 8, 16 or 32 (0: default)
+  int colour_grid = 0;   // workgroups of the FP64 colour kernel (0: its default)
 };
 
 using SplitLauncher = hipError_t (*)(const SplitArgs&);

@@ -377,6 +377,10 @@ def colour_sum_code(cf, ncol):
 # contiguous quarter of the colour flows) and colour groups per LDS chunk.
 FLOW_WAVES = 4
 FLOW_CHUNK = 16
+# chunk sizes compiled for the autotuner (each a flow_chunk_<CH> function)
+FLOW_CHUNKS = (8, 16, 32)
+# waves per SIMD of the group-sum kernel variants compiled for the autotuner
+SUMS_WPE_VARIANTS = (1, 2)
 
 # Split executor's group-sum kernels: the groups (in scheduled order) are cut into
 # SUMS_PARTS contiguous ranges, one kernel each, each computing only the currents
@@ -460,7 +464,7 @@ def generate(name, sums_parts=None, sums_wpe=None, remat=None):
     wpe = sums_wpe or SUMS_WPE.get(name, 1)
     parts = [Emitter(name, plan, remat=remat).amplitudes(split=True, groups=r)
              for r in part_ranges(ngroup, nparts)] if lane else []
-    assemble = Emitter(name, plan).flow_chunks(FLOW_WAVES, FLOW_CHUNK) if lane else []
+    assemble = {ch: Emitter(name, plan).flow_chunks(FLOW_WAVES, ch) for ch in FLOW_CHUNKS} if lane else {}
     team_src, _ = team_gen.emit(name, plan)
     out = []
     out.append(f"// Generated for process {name}: {plan.ndiagrams} Feynman diagrams, "
@@ -508,10 +512,22 @@ def generate(name, sums_parts=None, sums_wpe=None, remat=None):
             kw = 'if' if k == 0 else 'else if'
             out.append(f"    {kw} constexpr (K == {k}) group_sums_{k}(p, lam, g, mt, sout, sstride);")
         out.append("  }")
-        out.append(f"  static constexpr int FCHUNK = {FLOW_CHUNK};   // group sums per LDS chunk")
+        out.append(f"  static constexpr int FCHUNK = {FLOW_CHUNK};   // group sums per LDS chunk (default)")
         out.append(f"  static constexpr int FPW = {-(-ncol // FLOW_WAVES)};   // colour flows per wave")
+        for ch, lines in assemble.items():
+            out.append(f"  static __device__ __forceinline__ void flow_chunk_{ch}(int w, int c, const double* b, "
+                       "double* acc) {")
+            out.extend('  ' + l for l in lines)
+            out.append("  }")
+        out.append("  // wave w's flow updates from chunk c of CH group sums (CH one of the compiled sizes)")
+        out.append("  template <int CH>")
+        out.append("  static __device__ __forceinline__ void flow_chunk_t(int w, int c, const double* b, double* acc) {")
+        for k, ch in enumerate(FLOW_CHUNKS):
+            kw = 'if' if k == 0 else 'else if'
+            out.append(f"    {kw} constexpr (CH == {ch}) flow_chunk_{ch}(w, c, b, acc);")
+        out.append("  }")
         out.append("  static __device__ __forceinline__ void flow_chunk(int w, int c, const double* b, double* acc) {")
-        out.extend('  ' + l for l in assemble)
+        out.append("    flow_chunk_t<FCHUNK>(w, c, b, acc);")
         out.append("  }")
     out.append("};")
     out.append("}  // namespace me")

@@ -67,8 +67,9 @@ class Harness:
                                    ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
         return meh
 
-    def split_eval(self, mom, g, mt, hels):
-        """Per-helicity colour sums from the split evaluation (group sums, then flows)."""
+    def split_eval(self, mom, g, mt, hels, chunk=16):
+        """Per-helicity colour sums from the split evaluation (group sums, then flows
+        formed from chunks of `chunk` group sums: 8, 16 or 32)."""
         mom = np.ascontiguousarray(mom, dtype=np.float64)
         nevt = mom.shape[0]
         hels = np.ascontiguousarray(hels, dtype=np.int32)
@@ -76,7 +77,7 @@ class Harness:
         dp = ctypes.POINTER(ctypes.c_double)
         self.lib.harness_split_eval(mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
                                     ctypes.c_double(mt), hels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                                    ctypes.c_int(len(hels)), meh.ctypes.data_as(dp))
+                                    ctypes.c_int(len(hels)), meh.ctypes.data_as(dp), ctypes.c_int(chunk))
         return meh
 
 
@@ -170,3 +171,36 @@ class CountHarness:
 
     def routine(self, which):
         return self.lib.count_routine(which)
+
+
+def build_bg(opt='-O2'):
+    """Host build of the Berends-Giele executor's device functions (all gluon counts)."""
+    os.makedirs(OUT, exist_ok=True)
+    lib = os.path.join(OUT, 'bg_harness.so')
+    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bg_desc.h', 'me_bg_tables.h')]
+    deps.append(os.path.join(HERE, 'bg_harness.cpp'))
+    if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
+        cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE), '-I', CSRC,
+               os.path.join(HERE, 'bg_harness.cpp'), '-o', lib + '.tmp']
+        subprocess.run(cmd, check=True)
+        os.replace(lib + '.tmp', lib)
+    return BgHarness(lib)
+
+
+class BgHarness:
+    def __init__(self, path):
+        self.lib = ctypes.CDLL(path)
+
+    def jamps(self, n, mom, g, mt, hels):
+        """Dual amplitudes [nh][nevt][n!] (complex) of n-gluon events."""
+        import math
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        out = np.zeros((len(hels), nevt, math.factorial(n), 2))
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        rc = self.lib.harness_bg_eval(ctypes.c_int(n), mom.ctypes.data_as(dp), ctypes.c_int(nevt), ctypes.c_double(g),
+                                      ctypes.c_double(mt), hels.ctypes.data_as(ip), ctypes.c_int(len(hels)),
+                                      out.ctypes.data_as(dp))
+        assert rc == 0
+        return out[..., 0] + 1j * out[..., 1]

@@ -41,13 +41,13 @@ void sums_parts(const double (*p)[4], const int* lam, double g, double mt, doubl
 // Split evaluation: group sums of each (event, helicity) row (every part), then the flows
 // formed chunk by chunk from the sums staged as the LDS buffer holds them (this
 // row at lane 0), each wave's share of the flows separately, then the colour form.
-template <class P>
+template <class P, int CH>
 void split_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h) {
   using namespace me;
-  constexpr int NPAR = P::NPAR, NCOL = P::NCOL, CH = P::FCHUNK, FPW = P::FPW;
+  constexpr int NPAR = P::NPAR, NCOL = P::NCOL, FPW = P::FPW;
   constexpr int NCH = (P::NGROUP + CH - 1) / CH;
   static double sums[2 * P::NGROUP];
-  static double buf[2 * CH * 64];
+  static double buf[2 * 32 * 64];
   for (int e = 0; e < nevt; ++e) {
     double p[NPAR][4];
     for (int q = 0; q < NPAR; ++q)
@@ -62,7 +62,7 @@ void split_eval(const double* mom, int nevt, double g, double mt, const int* hel
           const int gq = 2 * CH * c + q;
           buf[q * 64] = gq < 2 * P::NGROUP ? sums[gq] : 0.0;
         }
-        for (int w = 0; w < 4; ++w) P::flow_chunk(w, c, buf, acc[w]);
+        for (int w = 0; w < 4; ++w) P::template flow_chunk_t<CH>(w, c, buf, acc[w]);
       }
       cx jamp[NCOL];
       for (int c = 0; c < NCOL; ++c) jamp[c] = cx{acc[c / FPW][2 * (c % FPW)], acc[c / FPW][2 * (c % FPW) + 1]};
@@ -72,13 +72,18 @@ void split_eval(const double* mom, int nevt, double g, double mt, const int* hel
 }
 
 template <class P>
-void split_dispatch(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h) {
-  if constexpr (P::LANE) split_eval<P>(mom, nevt, g, mt, hels, nh, me_h);
+void split_dispatch(const double* mom, int nevt, double g, double mt, const int* hels, int nh, double* me_h,
+                    int ch) {
+  if constexpr (P::LANE) {
+    if (ch == 8) split_eval<P, 8>(mom, nevt, g, mt, hels, nh, me_h);
+    else if (ch == 32) split_eval<P, 32>(mom, nevt, g, mt, hels, nh, me_h);
+    else split_eval<P, 16>(mom, nevt, g, mt, hels, nh, me_h);
+  }
 }
 
 extern "C" void harness_split_eval(const double* mom, int nevt, double g, double mt, const int* hels, int nh,
-                                   double* me_h) {
-  split_dispatch<me::PROC>(mom, nevt, g, mt, hels, nh, me_h);
+                                   double* me_h, int ch) {
+  split_dispatch<me::PROC>(mom, nevt, g, mt, hels, nh, me_h, ch);
 }
 
 template <class P>

@@ -12,3 +12,6 @@ using std::sqrt;
 struct uint4 {
   unsigned x, y, z, w;
 };
+// runtime handle types named by the host-side descriptor headers
+typedef struct ihipStream_t* hipStream_t;
+typedef int hipError_t;

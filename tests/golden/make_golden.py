@@ -123,7 +123,44 @@ def wide_c4b():
     _save('batch_first1024.npz', **out)
 
 
-GENERATORS = {'ggttggg': ggttggg, 'ggttgggg': ggttgggg, 'sde_ggttggg': sde_ggttggg,
+def _kappa_chunk(args):
+    """Condition number of the colour sum of each event: with J = A + iB per helicity,
+    kappa = sum_h (|A|^T |C| |A| + |B|^T |C| |B|) / sum_h (A^T C A + B^T C B)."""
+    npar, mom = args
+    if npar not in _PROC:
+        _PROC[npar] = me.process(npar)
+    proc = _PROC[npar]
+    cf = np.asarray(proc.cf, dtype=np.float64)
+    acf = np.abs(cf)
+    num = np.zeros(mom.shape[0])
+    den = np.zeros(mom.shape[0])
+    for h in range(proc.nhel):
+        j = me.jamps(proc, mom, h, AS)
+        for part in (j.real, j.imag):
+            num += np.einsum('ei,ij,ej->e', np.abs(part), acf, np.abs(part))
+            den += np.einsum('ei,ij,ej->e', part, cf, part)
+    return num / den
+
+
+def kappa():
+    # colour-sum condition numbers for the per-event mixed-precision bounds:
+    # gg -> tt (first 512 events of seed 1001), gg -> ttgg (first 256 of seed 1002),
+    # gg -> ttggg (the 64 sampled events of the 262144-event workload)
+    import multiprocessing as mp
+    workers = len(os.sched_getaffinity(0))
+    out = {}
+    full = rambo.generate(7, 262144, 1003)
+    idx = np.load(os.path.join(HERE, 'gg_ttxggg_seed1003_n262144_sampled.npz'))['index']
+    sets = {'gg_ttx': (4, rambo.generate(4, 512, 1001)), 'gg_ttxgg': (6, rambo.generate(6, 256, 1002)),
+            'gg_ttxggg': (7, full[idx])}
+    with mp.get_context('fork').Pool(workers) as pool:
+        for name, (npar, mom) in sets.items():
+            parts = [(npar, mom[i:i + 8]) for i in range(0, len(mom), 8)]
+            out[name] = np.concatenate(pool.map(_kappa_chunk, parts, chunksize=1))
+    _save('colour_kappa.npz', **out)
+
+
+GENERATORS = {'kappa': kappa, 'ggttggg': ggttggg, 'ggttgggg': ggttgggg, 'sde_ggttggg': sde_ggttggg,
               'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4b': wide_c4b}
 
 

@@ -164,19 +164,20 @@ def test_team_program_slots_and_schedule():
                 assert a1 > b0, (s, rs)
 
 
-@pytest.mark.parametrize('name,npar,nevt,opt,hels,parts,remat', [
-    ('gg_ttx', 4, 16, '-O1', None, None, None), ('gg_ttxg', 5, 8, '-O1', None, None, None),
-    ('gg_ttxgg', 6, 4, '-O1', None, None, None), ('gg_ttxgg', 6, 4, '-O1', None, 3, None),
-    ('gg_ttxgg', 6, 4, '-O1', None, None, True),
-    ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127), None, None)])
-def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels, parts, remat):
+@pytest.mark.parametrize('name,npar,nevt,opt,hels,parts,remat,chunk', [
+    ('gg_ttx', 4, 16, '-O1', None, None, None, 16), ('gg_ttxg', 5, 8, '-O1', None, None, None, 8),
+    ('gg_ttxgg', 6, 4, '-O1', None, None, None, 16), ('gg_ttxgg', 6, 4, '-O1', None, 3, None, 32),
+    ('gg_ttxgg', 6, 4, '-O1', None, None, True, 8),
+    ('gg_ttxggg', 7, 2, '-O0', (0, 17, 64, 100, 127), None, None, 16),
+    ('gg_ttxggg', 7, 1, '-O0', (3, 99), None, None, 8), ('gg_ttxggg', 7, 1, '-O0', (5, 77), None, None, 32)])
+def test_split_evaluation_on_host_vs_oracle(name, npar, nevt, opt, hels, parts, remat, chunk):
     # colour-group sums stored per row (by the group-sum parts in turn, with momentum
     # sums kept or recomputed at each use), then the flows formed from them chunk by
     # chunk, compiled for the host
     h = harness.build(name, opt, sums_parts=parts, remat=remat)
     mom = rambo.generate(npar, nevt, 7)
     hels = list(range(2 ** npar)) if hels is None else list(hels)
-    meh = h.split_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels)
+    meh = h.split_eval(mom, math.sqrt(4 * math.pi * AS), 173.0, hels, chunk)
     ref = ome.me_helicities(ome.process(npar), mom, AS, hels)
     assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
 
@@ -219,3 +220,28 @@ def test_sde_channel_sums_on_host_vs_oracle(name, npar, nevt, hels):
         assert np.max(np.abs(den[k] - rden) / scale) < 1e-12
         rnum = np.where(ids > 0, ref[np.maximum(ids, 1) - 1, np.arange(nevt)], 0.0)
         assert np.max(np.abs(num[k] - rnum) / scale) < 1e-12
+
+
+@pytest.mark.parametrize('name,npar,nevt,hels', [('gg_ttx', 4, 16, None), ('gg_ttxg', 5, 8, None),
+                                                 ('gg_ttxgg', 6, 4, None), ('gg_ttxggg', 7, 2, (0, 17, 64, 100, 127)),
+                                                 ('gg_ttxgggg', 8, 1, (0, 77, 255))])
+def test_berends_giele_on_host_vs_oracle_and_lane_code(name, npar, nevt, hels):
+    """The Berends-Giele executor's device functions (host build, one row at a time,
+    every level in turn): per-helicity colour sums against the oracle, and its dual
+    amplitudes identical (to rounding) to the one-lane diagram code's, flow by flow:
+    the recursion reaches the same colour-ordered amplitudes, not only the same |M|^2."""
+    h = harness.build_bg()
+    mom = rambo.generate(npar, nevt, 8)
+    proc = ome.process(npar)
+    hels = list(range(2 ** npar)) if hels is None else list(hels)
+    g = math.sqrt(4 * math.pi * AS)
+    jb = h.jamps(npar - 2, mom, g, 173.0, hels)
+    cf = np.asarray(proc.cf)
+    meh = np.einsum('hei,ij,hej->he', jb.conj(), cf, jb).real
+    ref = ome.me_helicities(proc, mom, AS, hels)
+    assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
+    if npar <= 7:
+        lane = harness.build(name, '-O1' if npar < 7 else '-O0')
+        _, jl = lane.eval(mom, g, 173.0, hels, want_jamps=True)
+        scale = np.abs(jl).max(axis=(0, 2))
+        assert np.max(np.abs(jb - jl).max(axis=(0, 2)) / scale) < 1e-12

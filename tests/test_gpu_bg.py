@@ -1,0 +1,92 @@
+"""The colour-ordered Berends-Giele executor on the GPU against the oracle: every
+process, FP64 within 1e-12 per event (extended-precision adjudication), the
+split-precision colour sums within their bound, and gg -> tt gggg at its full
+32768-event size on the stored oracle values."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import closed_form, me as ome
+from paper_2510_05392_amd import rambo
+from test_gpu_parity import AS, GOLDEN, MT, NPAR, _say, assert_parity
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+NPAR8 = dict(NPAR, gg_ttxgggg=8)
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2510_05392_amd import binding as b
+    b.load()
+    return b
+
+
+def _bg(binding, name, mom, mode=0):
+    m = binding.MatrixElement(name, colorsum_mode=mode)
+    m.me_set_executor(binding.ME_EXEC_BG)
+    d = torch.from_numpy(mom).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = m.compute(d, AS)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), time.perf_counter() - t0
+
+
+@pytest.mark.parametrize('name,nevt,seed', [('gg_ttx', 8192, 1001), ('gg_ttxg', 64 * 3 + 17, 1004),
+                                            ('gg_ttxgg', 64 * 3 + 5, 1006), ('gg_ttx', 1, 5)])
+def test_bg_vs_oracle(binding, name, nevt, seed):
+    _say(f'case bg {name} nevt={nevt} seed={seed}')
+    npar = NPAR8[name]
+    mom = rambo.generate(npar, nevt, seed)
+    gpu, _ = _bg(binding, name, mom)
+    assert_parity(gpu, mom, npar)
+    if name == 'gg_ttx':
+        assert np.max(np.abs(gpu / closed_form.gg_ttx(mom, AS, MT) - 1)) < 1e-12
+
+
+def test_bg_ggttggg_golden(binding):
+    _say('case bg gg_ttxggg golden 197 events; split FP16 / BF16 colour sums')
+    g = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_first197.npz'))
+    gpu, _ = _bg(binding, 'gg_ttxggg', g['momenta'])
+    assert_parity(gpu, g['momenta'], 7, me64=g['me'], me_ext=g['me_ext'])
+    for mode, bound in ((1, 1e-5), (2, 2e-4)):
+        mixed, _ = _bg(binding, 'gg_ttxggg', g['momenta'], mode)
+        rel = np.abs(mixed / g['me'] - 1)
+        _say(f'  mode {mode}: max rel err {rel.max():.3e}')
+        assert rel.max() < bound
+
+
+def test_bg_ggttgggg_full_size(binding):
+    _say('case bg gg_ttxgggg 32768 events (the full workload), sampled golden events')
+    s = np.load(os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_n32768_sampled.npz'))
+    mom = rambo.generate(8, 32768, 1005)
+    gpu, dt = _bg(binding, 'gg_ttxgggg', mom)
+    _say(f'  {32768 / dt:.0f} ME/s (first call, including set-up)')
+    assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
+    idx = s['index']
+    assert np.array_equal(mom[idx], s['momenta'])
+    assert_parity(gpu[idx], mom[idx], 8, me64=s['me'], me_ext=s['me_ext'], nrot=0)
+    path = os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first256.npz')
+    if os.path.exists(path):
+        g = np.load(path)
+        n = len(g['me'])
+        assert_parity(gpu[:n], mom[:n], 8, me64=g['me'], me_ext=g['me'], nrot=0)
+    mixed, _ = _bg(binding, 'gg_ttxgggg', mom[:2048], 1)
+    rel = np.abs(mixed / gpu[:2048] - 1)
+    _say(f'  split FP16 colour sum vs FP64: max rel {rel.max():.3e}')
+    assert rel.max() < 1e-5
+
+
+def test_bg_matches_team_program_ggttgggg(binding):
+    _say('case bg vs team program gg_ttxgggg 130 events')
+    mom = rambo.generate(8, 130, 77)
+    bg, _ = _bg(binding, 'gg_ttxgggg', mom)
+    m = binding.MatrixElement('gg_ttxgggg')
+    team = m.compute(torch.from_numpy(mom).cuda(), AS).cpu().numpy()
+    assert np.max(np.abs(bg / team - 1)) < 1e-10

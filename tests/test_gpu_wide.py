@@ -1,0 +1,163 @@
+"""The wide parity sets: whole workloads (or long prefixes of them) on the GPU
+against oracle values stored by tests/golden/make_golden.py, in the launch
+configurations the benchmark uses.
+
+  gg -> tt gg      every event of the 524288-event workload (seed 1002), FP64 on
+                   the lane and split executors, and the split FP16 / BF16
+                   colour sums;
+  gg -> tt ggg     the first 16384 events of the 262144-event workload (seed
+                   1003), FP64 (split executor) and split FP16;
+  gg -> tt gggg    the first 256 events of the 32768-event workload (seed 1005),
+                   FP64 and split FP16 (team program);
+  uneven batch     the first 1024 events of each segment, one persistent launch.
+
+FP64 is held to 1e-12 relative per event with extended-precision adjudication
+(tests/test_gpu_parity.py::assert_parity).  The split colour sums are held to a
+per-event bound derived from their arithmetic, on the events whose colour-sum
+condition number kappa the oracle stored:
+
+  rel. error <= 2 (u^2 + K 2^-24) kappa,   kappa = sum_h (|A|^T|C||A| + |B|^T|C||B|)
+                                                   / sum_h (A^T C A + B^T C B),
+
+with J = A + iB the dual amplitudes, C the colour matrix, u the unit roundoff of
+the split format (hi + lo keeps 2p bits: u^2 = 2^-22 for FP16, 2^-16 for BF16),
+K = ncol FP32 accumulations per product row (gamma_K bound), and a factor 2 for
+the real and imaginary rows and the FP64 outer products.  On every other event
+they are held to the largest bound seen on the kappa events times 10.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_05392_amd import rambo
+from test_gpu_parity import AS, GOLDEN, NPAR, _say, assert_parity
+
+torch = pytest.importorskip('torch')
+pytestmark = pytest.mark.gpu
+
+U2 = {1: 2.0 ** -22, 2: 2.0 ** -16}      # colour-sum modes: 1 = FP16 x2, 2 = BF16 x2
+NCOL = {'gg_ttx': 2, 'gg_ttxgg': 24, 'gg_ttxggg': 120, 'gg_ttxgggg': 720}
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2510_05392_amd import binding as b
+    b.load()
+    return b
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f'missing golden file {path}: run tests/golden/make_golden.py')
+    return np.load(path)
+
+
+def _run(binding, name, mom, executor=None, mode=0):
+    m = binding.MatrixElement(name, colorsum_mode=mode)
+    if executor is not None:
+        m.me_set_executor(executor)
+    out = m.compute(torch.from_numpy(mom).cuda(), AS)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def mixed_bound(name, mode, kappa):
+    return 2.0 * (U2[mode] + NCOL[name] * 2.0 ** -24) * kappa
+
+
+def _check_mixed(name, mode, gpu, ref, kappa_idx, kappa):
+    rel = np.abs(gpu / ref - 1)
+    b = mixed_bound(name, mode, kappa)
+    worst = float(np.max(rel[kappa_idx] / b))
+    _say(f'  mode {mode}: max rel err {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}; kappa events: '
+         f'bound median {np.median(b):.2e}, max {b.max():.2e}, largest err/bound {worst:.3f}')
+    assert np.all(rel[kappa_idx] <= b), worst
+    assert rel.max() <= 10 * b.max(), rel.max()
+
+
+@pytest.mark.parametrize('executor', [0, 2])
+def test_ggttgg_every_event_fp64(binding, executor):
+    _say(f'case wide gg_ttxgg all 524288 events, executor {executor}')
+    g = _golden('gg_ttxgg_seed1002_n524288.npz')
+    mom = rambo.generate(6, 524288, 1002)
+    gpu = _run(binding, 'gg_ttxgg', mom, executor)
+    assert np.all(np.isfinite(gpu)) and np.all(gpu > 0)
+    ill = assert_parity(gpu, mom, 6, me64=g['me'])
+    _say(f'  ill-conditioned events: {ill}')
+
+
+@pytest.mark.parametrize('mode', [1, 2])
+def test_ggttgg_every_event_mixed(binding, mode):
+    _say(f'case wide gg_ttxgg all 524288 events, split colour sum mode {mode}')
+    g = _golden('gg_ttxgg_seed1002_n524288.npz')
+    k = _golden('colour_kappa.npz')['gg_ttxgg']
+    mom = rambo.generate(6, 524288, 1002)
+    for executor in (0, 2):
+        gpu = _run(binding, 'gg_ttxgg', mom, executor, mode)
+        _check_mixed('gg_ttxgg', mode, gpu, g['me'], np.arange(len(k)), k)
+
+
+def test_ggtt_mixed_bound(binding):
+    _say('case gg_ttx split colour sums, per-event bound on 512 events')
+    k = _golden('colour_kappa.npz')['gg_ttx']
+    mom = rambo.generate(4, 8192, 1001)
+    ref = _run(binding, 'gg_ttx', mom)
+    for mode in (1, 2):
+        gpu = _run(binding, 'gg_ttx', mom, None, mode)
+        _check_mixed('gg_ttx', mode, gpu, ref, np.arange(len(k)), k)
+
+
+def test_ggttggg_first16384(binding):
+    _say('case wide gg_ttxggg first 16384 of 262144 events (split executor), FP64 and split FP16')
+    g = _golden('gg_ttxggg_seed1003_first16384.npz')
+    s = _golden('gg_ttxggg_seed1003_n262144_sampled.npz')
+    k = _golden('colour_kappa.npz')['gg_ttxggg']
+    mom = rambo.generate(7, 262144, 1003)
+    gpu = _run(binding, 'gg_ttxggg', mom, 2)
+    n = len(g['me'])
+    ill = assert_parity(gpu[:n], mom[:n], 7, me64=g['me'], me_ext=g['me_ext'])
+    ill += assert_parity(gpu[s['index']], mom[s['index']], 7, me64=s['me'], me_ext=s['me_ext'])
+    _say(f'  ill-conditioned events: {ill}')
+    mixed = _run(binding, 'gg_ttxggg', mom, 2, 1)
+    idx = np.concatenate([np.arange(n), s['index']])
+    ref = np.concatenate([g['me'], s['me']])
+    _check_mixed('gg_ttxggg', 1, mixed[idx], ref, np.arange(n, n + len(k)), k)
+
+
+def test_ggttgggg_first256(binding):
+    _say('case wide gg_ttxgggg first 256 of 32768 events (team program), FP64; split FP16 on the first 1024')
+    g = _golden('gg_ttxgggg_seed1005_first256.npz')
+    s = _golden('gg_ttxgggg_seed1005_n32768_sampled.npz')
+    mom = rambo.generate(8, 32768, 1005)
+    gpu = _run(binding, 'gg_ttxgggg', mom)
+    n = len(g['me'])
+    # no extended-precision values are stored for these 256 events: each must agree
+    # with the FP64 oracle itself to 1e-12
+    assert_parity(gpu[:n], mom[:n], 8, me64=g['me'], me_ext=g['me'])
+    assert_parity(gpu[s['index']], mom[s['index']], 8, me64=s['me'], me_ext=s['me_ext'])
+    mixed = _run(binding, 'gg_ttxgggg', mom[:1024], None, 1)
+    rel = np.abs(mixed / gpu[:1024] - 1)
+    _say(f'  split FP16 vs FP64: max rel {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}')
+    assert rel.max() < 1e-5
+
+
+def test_uneven_batch_first1024(binding):
+    _say('case wide uneven batch, first 1024 events of each segment')
+    g = _golden('batch_first1024.npz')
+    names = ['gg_ttxg', 'gg_ttxgg', 'gg_ttxggg']
+    sizes = [8192, 65536, 16384]
+    seeds = [1004, 1006, 1007]
+    hs = [binding.MatrixElement(n) for n in names]
+    moms = [rambo.generate(NPAR[n], k, sd) for n, k, sd in zip(names, sizes, seeds)]
+    outs = [torch.empty(k, dtype=torch.float64, device='cuda') for k in sizes]
+    binding.me_compute_batch(hs, [torch.from_numpy(m).cuda() for m in moms], sizes, AS, outs)
+    torch.cuda.synchronize()
+    for n, mom, out in zip(names, moms, outs):
+        gpu = out.cpu().numpy()[:1024]
+        ext = g[f'{n}_me_ext'] if f'{n}_me_ext' in g else None
+        ill = assert_parity(gpu, mom[:1024], NPAR[n], me64=g[f'{n}_me'], me_ext=ext)
+        _say(f'  {n}: 1024 events within 1e-12 (ill-conditioned {ill})')
