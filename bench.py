@@ -262,7 +262,7 @@ def main():
             m.me_set_launch(p_, w_, h_, t_)
             m.me_set_executor(x_)
             tuned = {'persistent': p_, 'waves_per_simd': w_, 'hel_per_item': h_, 'target_waves': t_,
-                     'executor': x_, 'split_wpe': 0, 'split_fchunk': 0, 'split_rounds': 0, 'colour_grid': 0}
+                     'executor': x_, 'split_wpe': 0, 'split_fchunk': 0, 'split_rounds': 0, 'colour_grid': 0, 'bg_variant': 0}
         elif args.autotune:
             nt = min(nevt, 65536)
             print(f'# bench autotune on {nt} events (mode {mode})', file=sys.stderr, flush=True)
@@ -332,8 +332,8 @@ def main():
         key = (process, nevt, tuple(tuned[k] for k in TRAFFIC_KEY))
         traffic = MEASURED_TRAFFIC.get(key)
     executor = (tuned or {}).get('executor', 0)
-    kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>'}.get(executor,
-                                                                              f'me_kernel<{process}>')
+    kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>',
+             3: f'bg_kernel<{NPAR[process] - 2}>'}.get(executor, f'me_kernel<{process}>')
     # the dominant kernel is the diagram kernel; its algorithmic flops per (event, helicity)
     f_unit = flops.diagram_kernel(process, executor)
     tot_ms, launches = ktimes
@@ -343,7 +343,8 @@ def main():
                       'ms_per_launch': tot_ms[k] / launches[k] if launches[k] else None}
                for k, name in ((binding.ME_KT_DIAGRAM, kname),
                                (binding.ME_KT_FLOWS, f'flows_kernel<{process}>'),
-                               (binding.ME_KT_COLOUR, 'colour_f64_kernel'),
+                               (binding.ME_KT_COLOUR, 'colour_f64_big_kernel' if process == 'gg_ttxgggg'
+                                else 'colour_f64_kernel'),
                                (binding.ME_KT_REDUCE, 'reduce_chunks_kernel')) if launches[k]}
     line = {
         'metric': 'ME evals/s', 'value': value, 'unit': 'ME evals/s', 'n_gpus': 1,

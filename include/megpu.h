@@ -306,8 +306,9 @@ int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
  * new results are appended (one JSON object per line).  best (host, may be NULL)
  * receives the ME_TUNE_FIELDS integers (persistent, waves_per_simd, hel_per_item,
  * target_waves, executor, split waves per SIMD, flow chunk, split rounds, colour
- * grid; 0 in the last four = default). */
-#define ME_TUNE_FIELDS 9
+ * grid, Berends-Giele launch shape; 0 in the last five = default).  The
+ * Berends-Giele executor is a candidate in its three launch shapes. */
+#define ME_TUNE_FIELDS 10
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
 
@@ -318,6 +319,11 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
  * kernel; 0 picks the default of each.  ME_EINVAL for other values or a process
  * without the split executor.  Results do not depend on them beyond rounding. */
 int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid);
+
+/* Launch shape of the Berends-Giele executor: 0 = default rows and threads per
+ * workgroup, 1 = half of both, 2 = twice both (see me_autotune).  ME_EINVAL for
+ * other values.  Results do not depend on it. */
+int me_set_bg(me_handle h, int variant);
 
 /* Uneven multi-process batch in one persistent launch (the paper evaluates one
  * process per executable; batching several is an addition).  Segment i is

@@ -35,7 +35,7 @@ EXPORTS = ['me_params_default', 'me_init', 'me_compute', 'me_compute_host', 'me_
            'me_good_helicities', 'me_info', 'me_colour_matrix', 'me_helicity_sums',
            'me_jamps', 'me_set_colorsum_mode', 'me_set_launch', 'me_autotune', 'me_compute_batch',
            'me_compute_alphas', 'me_select', 'me_set_executor', 'me_set_kernel_timing',
-           'me_kernel_times', 'me_finalize', 'me_channel_weights', 'me_num_channels', 'me_set_split',
+           'me_kernel_times', 'me_finalize', 'me_channel_weights', 'me_num_channels', 'me_set_split', 'me_set_bg',
            'me_sur_init', 'me_sur_finalize', 'me_sur_num_params', 'me_sur_get_params',
            'me_sur_set_params', 'me_sur_get_grads', 'me_sur_set_normalisation', 'me_sur_features',
            'me_sur_predict', 'me_sur_grads', 'me_sur_adam', 'me_sur_train_step',
@@ -94,6 +94,7 @@ def load(path=LIB_PATH):
     lib.me_compute_alphas.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.me_set_executor.argtypes = [vp, ctypes.c_int]
     lib.me_set_split.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.me_set_bg.argtypes = [vp, ctypes.c_int]
     lib.me_select.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     lib.me_finalize.argtypes = [vp]
     lib.me_channel_weights.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp]
@@ -247,12 +248,15 @@ class MatrixElement:
         _check(load().me_set_launch(self._h, persistent, waves_per_simd, hel_per_item, target_waves))
 
     TUNE_FIELDS = ('persistent', 'waves_per_simd', 'hel_per_item', 'target_waves', 'executor', 'split_wpe',
-                   'split_fchunk', 'split_rounds', 'colour_grid')
+                   'split_fchunk', 'split_rounds', 'colour_grid', 'bg_variant')
 
     def me_autotune(self, momenta, nevt, alpha_s, out, stream=None):
         best = (ctypes.c_int32 * len(self.TUNE_FIELDS))()
         _check(load().me_autotune(self._h, _ptr(momenta), nevt, alpha_s, _ptr(out), _stream(stream), best))
         return dict(zip(self.TUNE_FIELDS, list(best)))
+
+    def me_set_bg(self, variant=0):
+        _check(load().me_set_bg(self._h, variant))
 
     def me_set_split(self, wpe=0, fchunk=0, rounds=0, colour_grid=0):
         _check(load().me_set_split(self._h, wpe, fchunk, rounds, colour_grid))

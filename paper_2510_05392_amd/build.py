@@ -32,26 +32,28 @@ BG_HEADERS = ['me_device.h', 'me_bg.h', 'me_bg_desc.h', 'colour_mfma.h', 'me_col
 
 def bg_unit(name, n):
     """Source of the Berends-Giele unit of a process: the recursion kernel for n gluons
-    and the FP64 colour form of its n! flows (the matrix in LDS up to 128 flows,
-    streamed through LDS in tiles beyond)."""
+    and the FP64 colour form of its n! flows (the full matrix held in LDS up to 128
+    flows, the block-triangular form streamed through LDS beyond)."""
     import math
     ncol = math.factorial(n)
     if ncol <= 128:
+        # the full matrix fits in LDS: the split executor's colour kernel
         colour = ('  constexpr int RPB = 4 * 8 * COLOUR_F64_TILES;\n'
                   '  const int64_t tiles = (nrow + RPB - 1) / RPB;\n'
-                  f'  hipLaunchKernelGGL(colour_f64_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, COLOUR_F64_GRID)), '
-                  'dim3(256), 0, s, jt, nrow, cf64, out);\n')
+                  f'  hipLaunchKernelGGL(colour_f64_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, '
+                  'COLOUR_F64_GRID)), dim3(256), 0, s, jt, nrow, cf64, out);\n')
     else:
         colour = ('  const int64_t tiles = (nrow + 32 * BIG_NT - 1) / (32 * BIG_NT);\n'
-                  f'  hipLaunchKernelGGL(colour_f64_big_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, BIG_GRID)), '
-                  'dim3(256), 0, s, jt, nrow, cf64, out);\n')
+                  f'  hipLaunchKernelGGL(colour_f64_tri_kernel<{ncol}>, dim3((unsigned)std::min<int64_t>(tiles, '
+                  'BIG_GRID)), dim3(256), 0, s, jt, nrow, cf64, out);\n')
+    tri = 0 if ncol <= 128 else 1
     return (f'// Berends-Giele executor of process {name} (generated).\n'
             '#include <algorithm>\n#include "me_bg.h"\n#include "colour_mfma.h"\n#include "me_colour_big.h"\n'
             'namespace me {\n'
             f'static hipError_t colour64_{name}(const double* jt, int64_t nrow, const double* cf64, double* out, '
             'hipStream_t s) {\n' + colour + '  return hipGetLastError();\n}\n'
             f'const BgDesc* bg_{name}() {{\n  static const BgDesc d = {{"{name}", {n}, {ncol}, &launch_bg<{n}>, '
-            f'&colour64_{name}}};\n  return &d;\n}}\n}}\n')
+            f'&colour64_{name}, {tri}}};\n  return &d;\n}}\n}}\n')
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',

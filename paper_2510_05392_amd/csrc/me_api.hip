@@ -186,6 +186,7 @@ struct me_ctx {
   double* d_sums = nullptr;   // colour-group sums, then colour flows, of the split executor
   size_t sums_cap = 0;        // doubles
   double* d_cf64 = nullptr;   // colour matrix for the split executor's FP64 matrix-core colour form
+  double* d_cf64_tri = nullptr;  // its block-triangular form for the Berends-Giele executor's
   int device = 0;             // device current at me_init
   double* d_static = nullptr; // this device's static scratch array (me_compute_noalloc)
   double* d_soa = nullptr;    // structure-of-arrays copy of the momenta [npar][4][nevt]
@@ -211,6 +212,7 @@ struct me_ctx {
   int split_fchunk = 0;       // flows kernel: group sums per LDS chunk (8, 16, 32)
   int split_rounds = 0;       // events per chunk as whole rounds of group-sum waves (0: as many as fit)
   int colour_grid = 0;        // workgroups of the FP64 colour kernel
+  int bg_variant = 0;         // launch shape of the Berends-Giele kernel (0, 1, 2)
   bool tuned = false;         // me_autotune has run (or found its configuration in the cache)
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
@@ -481,19 +483,27 @@ int build_cf64(me_ctx* c) {
   if (!c->desc->split && !c->bg) return ME_OK;
   const int n = c->desc->ncol;
   const int kp = ((n + 3) / 4) * 4, mp = ((n + 15) / 16) * 16;
-  std::vector<double> t((size_t)mp * kp, 0.0);
+  // full matrix (split executor) and block-triangular form (Berends-Giele executor:
+  // the diagonal 16 x 16 blocks as they are, twice the blocks above, zero below)
+  std::vector<double> t((size_t)mp * kp, 0.0), tri((size_t)mp * kp, 0.0);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < n; ++k) {
       const int v = c->desc->cf_int[i * n + k];
-      // the colour kernel holds the matrix in FP32
+      // the colour kernels hold the matrix in FP32
       if (v >= (1 << 24) || v <= -(1 << 24)) return fail(ME_EINVAL, "colour matrix entry not exact in FP32");
       t[(size_t)i * kp + k] = (double)v;
+      const int bi = i / 16, bk = k / 16;
+      tri[(size_t)i * kp + k] = bk > bi ? 2.0 * v : (bk == bi ? (double)v : 0.0);
     }
   hipError_t e = hipMalloc(&c->d_cf64, t.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->d_cf64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_cf64_tri, tri.size() * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_cf64_tri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (c->d_cf64) (void)hipFree(c->d_cf64);
-    c->d_cf64 = nullptr;
+    if (c->d_cf64_tri) (void)hipFree(c->d_cf64_tri);
+    c->d_cf64 = c->d_cf64_tri = nullptr;
     return hip_fail(e, "FP64 colour-matrix table");
   }
   return ME_OK;
@@ -599,6 +609,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
     (void)hipFree(c->d_hels);
     (void)hipFree(c->d_scratch_hels);
     if (c->d_cf64) (void)hipFree(c->d_cf64);
+    if (c->d_cf64_tri) (void)hipFree(c->d_cf64_tri);
     free_tables(c);
     delete c;
     return rc;
@@ -623,6 +634,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
           (void)hipFree(c->d_hels);
           (void)hipFree(c->d_scratch_hels);
           if (c->d_cf64) (void)hipFree(c->d_cf64);
+          if (c->d_cf64_tri) (void)hipFree(c->d_cf64_tri);
           free_tables(c);
           delete c;
           return hip_fail(e, "hipGetSymbolAddress(scratch)");
@@ -640,6 +652,7 @@ int me_init(const char* process, const me_params* p, me_handle* out) {
     if (c->d_counter) (void)hipFree(c->d_counter);
     if (c->d_check) (void)hipFree(c->d_check);
     if (c->d_cf64) (void)hipFree(c->d_cf64);
+    if (c->d_cf64_tri) (void)hipFree(c->d_cf64_tri);
     free_tables(c);
     delete c;
     return fail(ME_ENOMEM, "work counter / capture stream");
@@ -665,6 +678,7 @@ int me_finalize(me_handle h) {
   if (h->d_jamps) (void)hipFree(h->d_jamps);
   if (h->d_sums) (void)hipFree(h->d_sums);
   if (h->d_cf64) (void)hipFree(h->d_cf64);
+  if (h->d_cf64_tri) (void)hipFree(h->d_cf64_tri);
   for (hipEvent_t e : h->ev_used) (void)hipEventSynchronize(e);
   release_timed(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -896,13 +910,14 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       const int64_t n = std::min<int64_t>(chunk, nevt - off);
       me::BgArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_bg_sub, h->d_bg_mask,
                    h->d_bg_last, alphas ? alphas + off : nullptr, h->d_sums, s};
+      a.variant = h->bg_variant;
       KernelMark kd(h, ME_KT_DIAGRAM, s);
       hipError_t e = h->bg->launch(a);
       if (e != hipSuccess) return hip_fail(e, "Berends-Giele kernel launch");
       kd.done();
       KernelMark kc(h, ME_KT_COLOUR, s);
       if (fp64) {
-        e = h->bg->colour64(h->d_sums, n * nhel, h->d_cf64, h->d_partial, s);
+        e = h->bg->colour64(h->d_sums, n * nhel, h->bg->colour_tri ? h->d_cf64_tri : h->d_cf64, h->d_partial, s);
       } else {
         me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
                           h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
@@ -1462,6 +1477,15 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
   return ME_OK;
 }
 
+int me_set_bg(me_handle h, int variant) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (variant < 0 || variant > 2) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
+  h->bg_variant = variant;
+  drop_graph(h);
+  return ME_OK;
+}
+
 int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid) {
   int rc = check_handle(h);
   if (rc) return rc;
@@ -1487,7 +1511,8 @@ namespace {
 
 // One autotuner candidate: launch configuration, executor and split variants.
 struct TuneCand {
-  int v[ME_TUNE_FIELDS];   // persistent, waves/SIMD, hel/item, target waves, executor, wpe, fchunk, rounds, grid
+  int v[ME_TUNE_FIELDS];   // persistent, waves/SIMD, hel/item, target waves, executor, wpe, fchunk, rounds, grid,
+                           // Berends-Giele launch shape
 };
 
 void apply_cand(me_ctx* h, const TuneCand& c, int default_tw) {
@@ -1500,11 +1525,12 @@ void apply_cand(me_ctx* h, const TuneCand& c, int default_tw) {
   h->split_fchunk = c.v[6];
   h->split_rounds = c.v[7];
   h->colour_grid = c.v[8];
+  h->bg_variant = c.v[9];
 }
 
 TuneCand current_cand(const me_ctx* h) {
   return TuneCand{{h->persistent, h->waves_per_simd, h->hel_per_item, h->target_waves, h->executor, h->split_wpe,
-                   h->split_fchunk, h->split_rounds, h->colour_grid}};
+                   h->split_fchunk, h->split_rounds, h->colour_grid, h->bg_variant}};
 }
 
 // Key of a tuning result: process, colour-sum mode, batch size, device and library build.
@@ -1597,24 +1623,24 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     if (fp64) {
       const int lane[8][4] = {{0, 1, 0, 1024}, {0, 1, 0, 4096}, {0, 1, 0, 16384}, {1, 1, 0, 0},
                               {1, 1, 8, 0},    {1, 2, 8, 0},    {1, 1, 1, 0},     {1, 2, 1, 0}};
-      for (const auto& l : lane) cands.push_back(TuneCand{{l[0], l[1], l[2], l[3], ME_EXEC_LANE, 0, 0, 0, 0}});
+      for (const auto& l : lane) cands.push_back(TuneCand{{l[0], l[1], l[2], l[3], ME_EXEC_LANE, 0, 0, 0, 0, 0}});
     } else {
       // the matrix-core modes stage one helicity per chunk: the launch fields do not matter
-      cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_LANE, 0, 0, 0, 0}});
+      cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_LANE, 0, 0, 0, 0, 0}});
     }
   }
   if (fp64) {
-    for (int tw : {1024, 262144, 1048576}) cands.push_back(TuneCand{{0, 1, 0, tw, ME_EXEC_TEAM, 0, 0, 0, 0}});
+    for (int tw : {1024, 262144, 1048576}) cands.push_back(TuneCand{{0, 1, 0, tw, ME_EXEC_TEAM, 0, 0, 0, 0, 0}});
   } else if (!h->desc->launch) {
-    cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_TEAM, 0, 0, 0, 0}});
+    cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_TEAM, 0, 0, 0, 0, 0}});
   }
-  cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0}});
+  for (int v : {0, 1, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
   if (h->desc->split) {
     // group-sum kernel variants (waves per SIMD), flow chunk sizes and event chunks
     // (as many whole rounds of group-sum waves as fit the scratch, or two rounds)
     for (int wpe : {1, 2})
       for (int fch : {8, 16, 32})
-        for (int rounds : {0, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_SPLIT, wpe, fch, rounds, 0}});
+        for (int rounds : {0, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_SPLIT, wpe, fch, rounds, 0, 0}});
   }
   const TuneCand saved = current_cand(h);
   const int save_graph = h->params.use_graph;

@@ -19,13 +19,19 @@
 //         R(()) = ubar,  R(p) = S(p3 - P(p)) . sum_j R(p[:j]) (i g gamma.J(p[j:]))
 //   A(sigma) = Q . J(sigma) + sum_{j>=1} R(sigma[:j]) (i g gamma.J(sigma[j:])) v,
 //         Q^mu = i g ubar gamma^mu v
+// Q . J(sigma) is formed from the splits already contracted with Q: with
+// q(s) = Q . J(s) kept beside every stored current,
+//   Q.V(a, b) = q(a) ((k - pa).b) + (a.b) (Q.(pa - pb)) + q(b) ((pb - k).a),
+//   Q.W(a, b, c) = q(a) (b.c) - 2 q(b) (a.c) + q(c) (a.b),
+// so that the currents of length N are never formed.
 //
 // Layout of one row in LDS (doubles): the momentum sums P(mask) of every subset of
 // gluons [2^N][4]; ubar, v and Q; the currents of every sequence of length
 // 1 .. N-1 (slot = its rank among sequences, shorter first, lexicographic within a
 // length); the row spinors of every prefix of length 1 .. N-2.  Currents of length
 // N and row spinors of length N-1 are used once, by the amplitude of their own
-// ordering, and are not stored.  Slots are BG_SLOT doubles apart.
+// ordering, and are not stored.  Slots are BG_SLOT doubles apart; q = Q.J of every
+// stored current follows, two doubles per current.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -57,7 +63,8 @@ struct BgShape {
   static constexpr int SPOFF = 4 << N;               // ubar, v, Q
   static constexpr int JOFF = SPOFF + 3 * BG_SLOT;
   static constexpr int ROFF = JOFF + NJ * BG_SLOT;
-  static constexpr int FRAME = ROFF + NR * BG_SLOT;  // doubles per row
+  static constexpr int QOFF = ROFF + NR * BG_SLOT;   // Q.J of the stored currents [NJ][2]
+  static constexpr int FRAME = QOFF + 2 * NJ;        // doubles per row
 };
 
 __device__ __forceinline__ int bg_tri(int a, int b) { return b * (b - 1) / 2 + a; }
@@ -153,6 +160,88 @@ __device__ __forceinline__ void bg_current(const double* F, const BgTables& t, i
   for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
 }
 
+// Current of stored sequence `slot` (length 2 .. N-1) and its contraction with Q,
+// written to its slot.
+template <int N>
+__device__ __forceinline__ void bg_current_store(double* F, const BgTables& t, int slot, int L, double g) {
+  using S = BgShape<N>;
+  cx j[4], q[4];
+  bg_current<N>(F, t, slot, L, g, j);
+  bg_store(F, S::JOFF + slot * BG_SLOT, j);
+  bg_load(F, S::SPOFF + 2 * BG_SLOT, q);
+  const cx qj = vdot(q, j);
+  F[S::QOFF + 2 * slot] = qj.r;
+  F[S::QOFF + 2 * slot + 1] = qj.i;
+}
+
+// Q.J of the external gluon b (slot b).
+template <int N>
+__device__ __forceinline__ void bg_external_q(double* F, int b) {
+  using S = BgShape<N>;
+  cx e[4], q[4];
+  bg_load(F, S::JOFF + b * BG_SLOT, e);
+  bg_load(F, S::SPOFF + 2 * BG_SLOT, q);
+  const cx qj = vdot(q, e);
+  F[S::QOFF + 2 * b] = qj.r;
+  F[S::QOFF + 2 * b + 1] = qj.i;
+}
+
+template <int N>
+__device__ __forceinline__ cx bg_q(const double* F, int slot) {
+  return cx{F[BgShape<N>::QOFF + 2 * slot], F[BgShape<N>::QOFF + 2 * slot + 1]};
+}
+
+// Q . J(sigma) of a full ordering (length N), from its splits contracted with Q.
+template <int N>
+__device__ __forceinline__ cx bg_qcurrent(const double* F, const BgTables& t, int slot, double g) {
+  using S = BgShape<N>;
+  const uint16_t* sub = t.sub + (int64_t)slot * S::T;
+  cx q[4];
+  bg_load(F, S::SPOFF + 2 * BG_SLOT, q);
+  cx a3{0.0, 0.0}, a4{0.0, 0.0};
+#pragma unroll 1
+  for (int j = 1; j < N; ++j) {
+    const int s1 = sub[bg_tri(0, j)], s2 = sub[bg_tri(j, N)];
+    const int o1 = S::JOFF + s1 * BG_SLOT, o2 = S::JOFF + s2 * BG_SLOT;
+    cx ja[4], jb[4];
+    double pa[4], pb[4], kma[4], pbk[4], pamb[4];
+    bg_load(F, o1, ja);
+    bg_load(F, o2, jb);
+    bg_mom(F, t.mask[s1], pa);
+    bg_mom(F, t.mask[s2], pb);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double k = -(pa[u] + pb[u]);
+      kma[u] = k - pa[u];
+      pbk[u] = pb[u] - k;
+      pamb[u] = pa[u] - pb[u];
+    }
+    const cx c1 = rdot(kma, jb), c2 = vdot(ja, jb), c3 = rdot(pbk, ja), qp = rdot(pamb, q);
+    a3 = a3 + (bg_q<N>(F, s1) * c1 + c2 * qp + bg_q<N>(F, s2) * c3);
+  }
+#pragma unroll 1
+  for (int j = 1; j + 1 < N; ++j) {
+    const int s1 = sub[bg_tri(0, j)];
+    cx ja[4];
+    bg_load(F, S::JOFF + s1 * BG_SLOT, ja);
+    const cx qa = bg_q<N>(F, s1);
+#pragma unroll 1
+    for (int l = j + 1; l < N; ++l) {
+      const int s2 = sub[bg_tri(j, l)], s3 = sub[bg_tri(l, N)];
+      cx jb[4], jc[4];
+      bg_load(F, S::JOFF + s2 * BG_SLOT, jb);
+      bg_load(F, S::JOFF + s3 * BG_SLOT, jc);
+      const cx bc = vdot(jb, jc), ac = vdot(ja, jc), ab = vdot(ja, jb);
+      a4 = a4 + ((qa * bc - bg_q<N>(F, s2) * (2.0 * ac)) + bg_q<N>(F, s3) * ab);
+    }
+  }
+  double p[4];
+  bg_mom(F, t.mask[slot], p);
+  const double inv = 1.0 / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
+  const double f3 = -g * inv, f4 = -g * g * inv;
+  return f3 * a3 + f4 * a4;
+}
+
 // Row spinor of the prefix s[:i] of sequence `slot` (1 <= i), not stored.
 template <int N>
 __device__ __forceinline__ void bg_row(const double* F, const BgTables& t, const double* p3, int slot, int i,
@@ -184,11 +273,9 @@ __device__ __forceinline__ cx bg_amplitude(const double* F, const BgTables& t, c
                                            double mt) {
   using S = BgShape<N>;
   const uint16_t* sub = t.sub + (int64_t)slot * S::T;
-  cx j[4], q[4], v[4];
-  bg_current<N>(F, t, slot, N, g, j);
-  bg_load(F, S::SPOFF + 2 * BG_SLOT, q);
+  cx v[4];
   bg_load(F, S::SPOFF + BG_SLOT, v);
-  cx amp = vdot(q, j);
+  cx amp = bg_qcurrent<N>(F, t, slot, g);
   // blocks after a stored prefix: R(sigma[:j]) (i g gamma.J(sigma[j:])) v
 #pragma unroll 1
   for (int k = 1; k + 1 < N; ++k) {
@@ -279,15 +366,16 @@ __global__ void __launch_bounds__(THREADS) bg_kernel(const double* __restrict__ 
     bg_setup_item<N>(lds + r * S::FRAME, pm[r], lam_s[r], g_s[r], mt, i);
   }
   __syncthreads();
-  // currents of lengths 2 .. N-1
+  // Q.J of the external gluons
+  for (int it = threadIdx.x; it < ROWS * N; it += THREADS) bg_external_q<N>(lds + (it / N) * S::FRAME, it % N);
+  __syncthreads();
+  // currents of lengths 2 .. N-1 (with their Q.J)
 #pragma unroll 1
   for (int L = 2; L < N; ++L) {
     const int cnt = S::count(L), off = S::off(L);
     for (int it = threadIdx.x; it < ROWS * cnt; it += THREADS) {
       const int r = it / cnt, slot = off + it % cnt;
-      cx j[4];
-      bg_current<N>(lds + r * S::FRAME, t, slot, L, g_s[r], j);
-      bg_store(lds + r * S::FRAME, S::JOFF + slot * BG_SLOT, j);
+      bg_current_store<N>(lds + r * S::FRAME, t, slot, L, g_s[r]);
     }
     __syncthreads();
   }
@@ -320,6 +408,8 @@ __global__ void __launch_bounds__(THREADS) bg_kernel(const double* __restrict__ 
 
 // Rows per workgroup and threads per workgroup by gluon count: as many rows as
 // keep a few workgroups' frames within the 160 KB of LDS of a compute unit.
+// Variant 1 halves both, variant 2 doubles them (gluon count 6: one row of twice
+// or half the threads); the autotuner picks among them.
 template <int N> struct BgLaunchShape;
 template <> struct BgLaunchShape<2> { static constexpr int ROWS = 32, THREADS = 256; };
 template <> struct BgLaunchShape<3> { static constexpr int ROWS = 32, THREADS = 256; };
@@ -327,10 +417,17 @@ template <> struct BgLaunchShape<4> { static constexpr int ROWS = 8, THREADS = 2
 template <> struct BgLaunchShape<5> { static constexpr int ROWS = 2, THREADS = 256; };
 template <> struct BgLaunchShape<6> { static constexpr int ROWS = 1, THREADS = 512; };
 
-template <int N>
-hipError_t launch_bg(const BgArgs& a) {
+template <int N, int V>
+struct BgVariant {
+  static constexpr int R0 = BgLaunchShape<N>::ROWS, T0 = BgLaunchShape<N>::THREADS;
+  static constexpr int ROWS = V == 0 ? R0 : V == 1 ? (R0 > 1 ? R0 / 2 : 1) : (N < 6 ? 2 * R0 : R0);
+  static constexpr int THREADS = V == 0 ? T0 : V == 1 ? T0 / 2 : 2 * T0;
+};
+
+template <int N, int V>
+hipError_t launch_bg_v(const BgArgs& a) {
   using S = BgShape<N>;
-  constexpr int ROWS = BgLaunchShape<N>::ROWS, THREADS = BgLaunchShape<N>::THREADS;
+  constexpr int ROWS = BgVariant<N, V>::ROWS, THREADS = BgVariant<N, V>::THREADS;
   const size_t lds = (size_t)ROWS * S::FRAME * sizeof(double);
   static const hipError_t attr = hipFuncSetAttribute((const void*)bg_kernel<N, ROWS, THREADS>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -341,6 +438,13 @@ hipError_t launch_bg(const BgArgs& a) {
   hipLaunchKernelGGL((bg_kernel<N, ROWS, THREADS>), dim3((unsigned)((rows + ROWS - 1) / ROWS)), dim3(THREADS), lds,
                      a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.alphas, a.jt);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_bg(const BgArgs& a) {
+  if (a.variant == 1) return launch_bg_v<N, 1>(a);
+  if (a.variant == 2) return launch_bg_v<N, 2>(a);
+  return launch_bg_v<N, 0>(a);
 }
 #endif
 

@@ -26,6 +26,7 @@ struct BgArgs {
   const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
   double* jt;            // device, dual amplitudes [2 NCOL][n nhel]
   hipStream_t stream;
+  int variant = 0;       // launch shape (rows and threads per workgroup): 0, 1 or 2
 };
 
 using BgLauncher = hipError_t (*)(const BgArgs&);
@@ -39,6 +40,7 @@ struct BgDesc {
   int ncol;              // orderings = colour flows
   BgLauncher launch;
   Colour64Launcher colour64;
+  int colour_tri;        // 1: colour64 takes the block-triangular matrix, 0: the full one
 };
 
 }  // namespace me

@@ -1,14 +1,19 @@
-// FP64 colour form for many colour flows (the 720 of g g -> t tbar g g g g), on
-// the matrix cores:
+// FP64 colour form on the matrix cores for the Berends-Giele executor, any number
+// of colour flows (up to the 720 of g g -> t tbar g g g g):
 //     out[row] = sum_ik CF[i][k] (A_i A_k + B_i B_k),   J = A + iB,
-// with the integer colour matrix (exact in FP64; entries below 2^24 in magnitude,
-// so the FP32 copies staged in LDS are exact too), not yet divided by its
-// denominator.  As colour_f64_kernel, but the matrix does not fit in LDS: the
-// flows are taken in groups of BIG_MG blocks of 16 and, for each group, the
-// matrix is streamed through LDS in tiles of BIG_KT columns shared by the
-// workgroup's four waves; each wave keeps the products of its 2 x 8 rows for one
-// group in registers and adds their row dots before the next group.
-// Layouts as colour_f64_kernel: jt [2 NCOL][nrow]; cf [16 MB][4 KS] FP64 zero padded.
+// with the integer colour matrix, not yet divided by its denominator, taken in
+// block-triangular form: cf holds, per 16 x 16 block, CF itself on the diagonal
+// blocks, 2 CF above them and zeros below (the matrix is symmetric), so that the
+// products of the zero blocks are skipped (about half of the matrix-core work).
+// Entries are exact in FP64 and, below 2^24 in magnitude, in the FP32 copies
+// staged in LDS.  The flows are taken in groups of BIG_MG blocks of 16; for each
+// group the matrix is streamed through LDS in tiles of BIG_KT columns (from the
+// group's first block on) shared by the workgroup's four waves; each wave keeps
+// the products of its 2 x 8 rows for one group in registers and adds their row
+// dots before the next group.
+// Layouts (v_mfma_f64_16x16x4f64, wave64): A[i][k]: i = l % 16, k = l / 16;
+// B[k][j]: j = l % 16, k = l / 16; D[i][j]: j = l % 16, i = 4 v + l / 16.
+// jt [2 NCOL][nrow]; cf [16 MB][4 KS] FP64 zero padded.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,7 +27,7 @@ constexpr int BIG_NT = 2;     // 8-row tiles per wave
 constexpr int BIG_GRID = 1024;
 
 template <int NCOL>
-__global__ void __launch_bounds__(256) colour_f64_big_kernel(const double* __restrict__ jt, int64_t nrow,
+__global__ void __launch_bounds__(256) colour_f64_tri_kernel(const double* __restrict__ jt, int64_t nrow,
                                                              const double* __restrict__ cf,
                                                              double* __restrict__ out) {
   constexpr int KS = (NCOL + 3) / 4;
@@ -55,7 +60,9 @@ __global__ void __launch_bounds__(256) colour_f64_big_kernel(const double* __res
       for (int t = 0; t < BIG_NT; ++t)
 #pragma unroll
         for (int m = 0; m < BIG_MG; ++m) acc[t][m] = f64x4b{0.0, 0.0, 0.0, 0.0};
-      for (int kt = 0; kt < NKT; ++kt) {
+      // blocks below the diagonal are zero: the group's K range starts at its first block
+      const int kt0 = (16 * BIG_MG * g) / BIG_KT;
+      for (int kt = kt0; kt < NKT; ++kt) {
         __syncthreads();   // the previous tile is no longer read
         for (int i = threadIdx.x; i < 16 * BIG_MG * BIG_KT; i += 256) {
           const int r = i / BIG_KT, c = i % BIG_KT;
@@ -69,8 +76,10 @@ __global__ void __launch_bounds__(256) colour_f64_big_kernel(const double* __res
           double b[BIG_NT];
 #pragma unroll
           for (int t = 0; t < BIG_NT; ++t) b[t] = (cc < NCOL && valid[t]) ? x[t][(int64_t)(2 * cc) * nrow] : 0.0;
+          const int kb = (BIG_KT * kt + 4 * ks) / 16;   // 16-column block of this K step
 #pragma unroll
           for (int m = 0; m < BIG_MG; ++m) {
+            if (kb < BIG_MG * g + m) continue;            // below the diagonal: zero block
             const double a = (double)tile[(16 * m + j) * TS + 4 * ks + kq];
 #pragma unroll
             for (int t = 0; t < BIG_NT; ++t)

@@ -108,14 +108,62 @@ def flow_updates(plan):
     return sum(len(key) for key, _ in plan.colour_groups())
 
 
+# Berends-Giele executor (csrc/me_bg.h): counts of its building blocks, read off
+# the code at the same rules and pinned, with the totals below, by compiling it
+# for the host with the operation-counting scalar (tests/test_generator.py)
+BG = {
+    'sum_bit': 8,      # one gluon momentum into one subset sum: sign times p, added (4 components)
+    'line': 80,        # Q = line_current(ubar, v)
+    'v3': 154,         # bg_v3: one split of a three-gluon vertex, accumulated
+    'v4': 188,         # bg_v4: one split of a four-gluon vertex, accumulated
+    'close': 35,       # 1 / P^2, the two couplings and their combination into the current
+    'row_term': 88,    # row_vertex of one block, accumulated
+    'row_close': 98,   # q = p3 - P and the top propagator
+    'amp_term': 112,   # row_vertex, sdot with v, accumulated
+    'q_dot': 30,       # Q . J of a stored current (kept beside it)
+    'v3q': 112,        # one split of a three-gluon vertex contracted with Q, accumulated
+    'v4q': 116,        # one split of a four-gluon vertex contracted with Q, accumulated
+    'qclose': 17,      # 1 / P^2, the couplings and their combination into Q . J(sigma)
+}
+
+
+def bg_row(n):
+    """FP64 flops of one (event, helicity) row of the Berends-Giele executor with n
+    gluons (beams along +-z; the spinor branch for pz < 0 not included, as ROUTINE)."""
+    import math
+    cnt = [0] + [math.perm(n, L) for L in range(1, n + 1)]
+
+    def current(L):
+        return (L - 1) * BG['v3'] + math.comb(L - 1, 2) * BG['v4'] + BG['close']
+
+    def row(i):
+        return i * BG['row_term'] + BG['row_close']
+
+    def qcurrent(L):
+        return (L - 1) * BG['v3q'] + math.comb(L - 1, 2) * BG['v4q'] + BG['qclose']
+
+    setup = 8 * n * 2 ** (n - 1) + 2 * ROUTINE['Gbeam'] + (n - 2) * ROUTINE['G'] + ROUTINE['U'] + ROUTINE['V'] \
+        + BG['line']
+    # stored currents with their Q.J, and Q.J of the external gluons
+    currents = n * BG['q_dot'] + sum(cnt[L] * (current(L) + BG['q_dot']) for L in range(2, n))
+    rows = sum(cnt[L] * row(L) for L in range(1, n - 1))
+    amps = cnt[n] * (qcurrent(n) + (n - 2) * BG['amp_term'] + row(n - 1) + BG['amp_term'])
+    return {'setup': setup, 'currents': currents, 'rows': rows, 'amplitudes': amps,
+            'total': setup + currents + rows + amps}
+
+
 def diagram_kernel(name, executor):
     """FP64 flops per (event, helicity) of the kernel that evaluates the diagrams:
     everything for the one-lane and team executors (flows and colour form are fused
     into it; the team program runs the same routines), the group sums alone for the
     split executor (executor 2), whose flows and colour form run in kernels of their
-    own."""
+    own, the recursion alone for the Berends-Giele executor (executor 3), whose
+    colour form is a kernel of its own."""
     if executor == 2:
         return group_sums_flops(name) + QUARK_BRANCH_MEAN
+    if executor == 3:
+        from .gen import codegen
+        return bg_row(codegen.PROCESS_NPAR[name] - 2)['total'] + QUARK_BRANCH_MEAN
     return per_event_helicity(name) + QUARK_BRANCH_MEAN
 
 

@@ -22,12 +22,9 @@ void bg_eval(const double* mom, int nevt, double g, double mt, const int* hels, 
       int lam[NPAR];
       for (int q = 0; q < NPAR; ++q) lam[q] = (hels[k] >> (NPAR - 1 - q)) & 1 ? 1 : -1;
       for (int i = 0; i < (1 << N) + N + 1; ++i) bg_setup_item<N>(F.data(), p, lam, g, mt, i);
+      for (int b = 0; b < N; ++b) bg_external_q<N>(F.data(), b);
       for (int L = 2; L < N; ++L)
-        for (int c = 0; c < S::count(L); ++c) {
-          cx j[4];
-          bg_current<N>(F.data(), t, S::off(L) + c, L, g, j);
-          bg_store(F.data(), S::JOFF + (S::off(L) + c) * BG_SLOT, j);
-        }
+        for (int c = 0; c < S::count(L); ++c) bg_current_store<N>(F.data(), t, S::off(L) + c, L, g);
       for (int L = 1; L + 1 < N; ++L)
         for (int c = 0; c < S::count(L); ++c) {
           cx r[4];

@@ -204,3 +204,24 @@ class BgHarness:
                                       out.ctypes.data_as(dp))
         assert rc == 0
         return out[..., 0] + 1j * out[..., 1]
+
+
+def build_count_bg(opt='-O1'):
+    """Host build of the Berends-Giele device functions with the operation-counting scalar."""
+    os.makedirs(OUT, exist_ok=True)
+    lib = os.path.join(OUT, 'count_bg_harness.so')
+    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bg_desc.h', 'me_bg_tables.h')]
+    deps.append(os.path.join(HERE, 'count_bg_harness.cpp'))
+    if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
+        cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE), '-I', CSRC,
+               os.path.join(HERE, 'count_bg_harness.cpp'), '-o', lib + '.tmp']
+        subprocess.run(cmd, check=True)
+        os.replace(lib + '.tmp', lib)
+    lib = ctypes.CDLL(lib)
+
+    def count(n, mom, hel):
+        m = np.ascontiguousarray(mom, dtype=np.float64)
+        out = (ctypes.c_longlong * 4)()
+        assert lib.count_bg_row(n, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hel, out) == 0
+        return list(out)
+    return count

@@ -245,3 +245,19 @@ def test_berends_giele_on_host_vs_oracle_and_lane_code(name, npar, nevt, hels):
         _, jl = lane.eval(mom, g, 173.0, hels, want_jamps=True)
         scale = np.abs(jl).max(axis=(0, 2))
         assert np.max(np.abs(jb - jl).max(axis=(0, 2)) / scale) < 1e-12
+
+
+@pytest.mark.parametrize('n', [2, 3, 4, 5, 6])
+def test_berends_giele_flops_equal_the_counted_operations(n):
+    """The Berends-Giele figures of the roofline (flops.bg_row: building-block counts
+    summed over the recursion's levels) equal the operations its device functions
+    perform, counted on the host with the operation-counting scalar, part by part."""
+    count = harness.build_count_bg()
+    f = flops.bg_row(n)
+    mom = rambo.generate(n + 2, 4, 1003)
+    for e in range(mom.shape[0]):
+        neg = int((mom[e, 2:4, 3] < 0).sum())
+        for hel in (0, 5, 2 ** (n + 2) - 1):
+            setup, currents, rows, amps = count(n, mom[e], hel)
+            assert setup == f['setup'] + neg
+            assert (currents, rows, amps) == (f['currents'], f['rows'], f['amplitudes'])

@@ -37,6 +37,7 @@ def test_every_candidate_matches_the_oracle(binding):
             (1, 1, 1, 4096), (1, 2, 1, 4096)]
     cases = [('lane',) + c for c in lane] + [('team', 0, 1, 0, tw) for tw in (1024, 262144, 1048576)]
     cases += [('split', w, f, r) for w in (1, 2) for f in (8, 16, 32) for r in (0, 2)]
+    cases += [('bg', v) for v in (0, 1, 2)]
     for c in cases:
         m = binding.MatrixElement('gg_ttxggg')
         if c[0] == 'lane':
@@ -44,9 +45,12 @@ def test_every_candidate_matches_the_oracle(binding):
         elif c[0] == 'team':
             m.me_set_executor(binding.ME_EXEC_TEAM)
             m.me_set_launch(*c[1:])
-        else:
+        elif c[0] == 'split':
             m.me_set_executor(binding.ME_EXEC_SPLIT)
             m.me_set_split(c[1], c[2], c[3], 0)
+        else:
+            m.me_set_executor(binding.ME_EXEC_BG)
+            m.me_set_bg(c[1])
         gpu = m.compute(d, AS).cpu().numpy()
         assert_parity(gpu, mom, 7, me64=me64, me_ext=ext)
     # the split variants in a matrix-core mode agree with each other to rounding
@@ -63,6 +67,8 @@ def test_every_candidate_matches_the_oracle(binding):
         binding.MatrixElement('gg_ttxggg').me_set_split(3, 0, 0, 0)
     with pytest.raises(binding.MeError):
         binding.MatrixElement('gg_ttxgggg').me_set_split(1, 16, 0, 0)
+    with pytest.raises(binding.MeError):
+        binding.MatrixElement('gg_ttxggg').me_set_bg(3)
 
 
 def test_autotune_cache_and_parameter(binding, tmp_path, monkeypatch):
