@@ -28,9 +28,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # the work items (persistent, helicities/item, executor; the persistent grid's size does not change
 # what an item reads and writes); the numbers and the commands are in the named profile and hold
 # only for the kernel they were taken on.
-# key: (process, nevt, (persistent, hel_per_item, executor, split_wpe, split_rounds)) as me_autotune
+# key: (process, nevt, (persistent, hel_per_item, executor, split_wpe, split_rounds, bg_variant)) as me_autotune
 # reports them; no entry yet for the kernels as they are now (the momentum loads changed).
-TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds')
+TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds', 'bg_variant')
 MEASURED_TRAFFIC = {
 }
 
@@ -223,8 +223,8 @@ def main():
                     help='pick the FP64 launch configuration with the library autotuner first')
     ap.add_argument('--no-graph', action='store_true', help='do not replay me_compute from a hipGraph')
     ap.add_argument('--launch', default=None,
-                    help='fixed FP64 launch "persistent,waves_per_simd,hel_per_item,target_waves,executor" '
-                         'instead of autotuning (profiling runs)')
+                    help='fixed FP64 launch "persistent,waves_per_simd,hel_per_item,target_waves,executor'
+                         '[,bg_variant]" instead of autotuning (profiling runs)')
     ap.add_argument('--surrogate', action=argparse.BooleanOptionalAction, default=True,
                     help='also measure mixed precision + surrogate two-stage unweighting')
     ap.add_argument('--sur-train', type=int, default=131072)
@@ -258,11 +258,15 @@ def main():
         m = binding.MatrixElement(process, colorsum_mode=mode, use_graph=not args.no_graph)
         tuned = None
         if args.launch and mode == binding.ME_CS_FP64:
-            p_, w_, h_, t_, x_ = (int(v) for v in args.launch.split(','))
+            p_, w_, h_, t_, x_, *v_ = (int(v) for v in args.launch.split(','))
+            v_ = v_[0] if v_ else 0
             m.me_set_launch(p_, w_, h_, t_)
             m.me_set_executor(x_)
+            if x_ == binding.ME_EXEC_BG:
+                m.me_set_bg(v_)
             tuned = {'persistent': p_, 'waves_per_simd': w_, 'hel_per_item': h_, 'target_waves': t_,
-                     'executor': x_, 'split_wpe': 0, 'split_fchunk': 0, 'split_rounds': 0, 'colour_grid': 0, 'bg_variant': 0}
+                     'executor': x_, 'split_wpe': 0, 'split_fchunk': 0, 'split_rounds': 0, 'colour_grid': 0,
+                     'bg_variant': v_}
         elif args.autotune:
             nt = min(nevt, 65536)
             print(f'# bench autotune on {nt} events (mode {mode})', file=sys.stderr, flush=True)
@@ -332,10 +336,15 @@ def main():
         key = (process, nevt, tuple(tuned[k] for k in TRAFFIC_KEY))
         traffic = MEASURED_TRAFFIC.get(key)
     executor = (tuned or {}).get('executor', 0)
+    bg_variant = (tuned or {}).get('bg_variant', 0)
     kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>',
-             3: f'bg_kernel<{NPAR[process] - 2}>'}.get(executor, f'me_kernel<{process}>')
+             3: f'bg{"h" if bg_variant == 3 else ""}_kernel<{NPAR[process] - 2}>'}.get(executor,
+                                                                                    f'me_kernel<{process}>')
+    ncol = {'gg_ttx': 2, 'gg_ttxg': 6, 'gg_ttxgg': 24, 'gg_ttxggg': 120, 'gg_ttxgggg': 720}[process]
+    cname = (f'colour_f64_tri_kernel<{ncol}>' if ncol > 128 else f'colour_f64_kernel<{ncol}>') \
+        if executor in (2, 3) else 'colour_mfma_kernel'
     # the dominant kernel is the diagram kernel; its algorithmic flops per (event, helicity)
-    f_unit = flops.diagram_kernel(process, executor)
+    f_unit = flops.diagram_kernel(process, executor, bg_variant)
     tot_ms, launches = ktimes
     kms = tot_ms[binding.ME_KT_DIAGRAM]
     achieved = f_unit * nhel * nevt * args.steps / (kms * 1e-3) / 1e12
@@ -343,9 +352,9 @@ def main():
                       'ms_per_launch': tot_ms[k] / launches[k] if launches[k] else None}
                for k, name in ((binding.ME_KT_DIAGRAM, kname),
                                (binding.ME_KT_FLOWS, f'flows_kernel<{process}>'),
-                               (binding.ME_KT_COLOUR, 'colour_f64_big_kernel' if process == 'gg_ttxgggg'
-                                else 'colour_f64_kernel'),
-                               (binding.ME_KT_REDUCE, 'reduce_chunks_kernel')) if launches[k]}
+                               (binding.ME_KT_COLOUR, cname),
+                               (binding.ME_KT_REDUCE, 'reduce_rows_kernel' if executor == 3 and bg_variant == 3
+                                else 'reduce_chunks_kernel')) if launches[k]}
     line = {
         'metric': 'ME evals/s', 'value': value, 'unit': 'ME evals/s', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': ms,

@@ -320,9 +320,14 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
  * without the split executor.  Results do not depend on them beyond rounding. */
 int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid);
 
-/* Launch shape of the Berends-Giele executor: 0 = default rows and threads per
- * workgroup, 1 = half of both, 2 = twice both (see me_autotune).  ME_EINVAL for
- * other values.  Results do not depend on it. */
+/* Kernel of the Berends-Giele executor (paper, Discussion: the recursion for many
+ * gluons): 0 = one (event, helicity) row per item with the default rows and
+ * threads per workgroup, 1 = half of both, 2 = twice both; 3 = helicity
+ * recycling (four and five gluons: one workgroup per event(s), every current and
+ * row spinor formed once per helicity assignment of its own particles, the full
+ * orderings walked in rotation cycles).  See me_autotune.  ME_EINVAL for other
+ * values, and for 3 on other processes.  Results do not depend on it beyond
+ * rounding. */
 int me_set_bg(me_handle h, int variant);
 
 /* Uneven multi-process batch in one persistent launch (the paper evaluates one

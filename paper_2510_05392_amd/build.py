@@ -27,7 +27,7 @@ PROCESSES = ['gg_ttx', 'gg_ttxg', 'gg_ttxgg', 'gg_ttxggg', 'gg_ttxgggg']
 # headers the generated process units include
 PROC_HEADERS = ['me_device.h', 'me_kernels.h', 'me_process.h', 'colour_mfma.h', 'me_team.h']
 SDE_HEADERS = ['me_sde.h', 'me_sde_desc.h']
-BG_HEADERS = ['me_device.h', 'me_bg.h', 'me_bg_desc.h', 'colour_mfma.h', 'me_colour_big.h']
+BG_HEADERS = ['me_device.h', 'me_bg.h', 'me_bgh.h', 'me_bg_desc.h', 'colour_mfma.h', 'me_colour_big.h']
 
 
 def bg_unit(name, n):
@@ -48,12 +48,12 @@ def bg_unit(name, n):
                   'BIG_GRID)), dim3(256), 0, s, jt, nrow, cf64, out);\n')
     tri = 0 if ncol <= 128 else 1
     return (f'// Berends-Giele executor of process {name} (generated).\n'
-            '#include <algorithm>\n#include "me_bg.h"\n#include "colour_mfma.h"\n#include "me_colour_big.h"\n'
+            '#include <algorithm>\n#include "me_bgh.h"\n#include "colour_mfma.h"\n#include "me_colour_big.h"\n'
             'namespace me {\n'
             f'static hipError_t colour64_{name}(const double* jt, int64_t nrow, const double* cf64, double* out, '
             'hipStream_t s) {\n' + colour + '  return hipGetLastError();\n}\n'
             f'const BgDesc* bg_{name}() {{\n  static const BgDesc d = {{"{name}", {n}, {ncol}, &launch_bg<{n}>, '
-            f'&colour64_{name}, {tri}}};\n  return &d;\n}}\n}}\n')
+            f'&colour64_{name}, {tri}, {int(n in (4, 5))}}};\n  return &d;\n}}\n}}\n')
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',

@@ -70,6 +70,16 @@ __global__ void reduce_chunks_kernel(const double* __restrict__ partial, int nch
   out[e] = scale * acc;
 }
 
+// The same sum over event-major rows (row = e nhel + k), in the same order.
+__global__ void reduce_rows_kernel(const double* __restrict__ partial, int nhel, int64_t nevt, double scale,
+                                   double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double acc = 0.0;
+  for (int k = 0; k < nhel; ++k) acc += partial[e * nhel + k];
+  out[e] = scale * acc;
+}
+
 __global__ void zero_counter_kernel(int* c) { *c = 0; }
 
 // Caller layout [nevt][np4] -> structure of arrays [np4][nevt] (np4 = 4 npar);
@@ -175,6 +185,9 @@ struct me_ctx {
   uint16_t* d_bg_sub = nullptr;      // its sequence tables (device)
   uint8_t* d_bg_mask = nullptr;
   uint8_t* d_bg_last = nullptr;
+  uint16_t* d_bg_cyc = nullptr;      // rotation-cycle tables of the helicity-recycling kernel
+  int n_bg_cyc = 0;                  // [seg | cbase | rbase] sizes
+  int n_bg_slot = 0;
   me_params params{};
   std::vector<int> good;      // host copy of the good helicities
   int* d_hels = nullptr;      // device, good helicities (capacity nhel)
@@ -212,7 +225,7 @@ struct me_ctx {
   int split_fchunk = 0;       // flows kernel: group sums per LDS chunk (8, 16, 32)
   int split_rounds = 0;       // events per chunk as whole rounds of group-sum waves (0: as many as fit)
   int colour_grid = 0;        // workgroups of the FP64 colour kernel
-  int bg_variant = 0;         // launch shape of the Berends-Giele kernel (0, 1, 2)
+  int bg_variant = 0;         // Berends-Giele kernel: launch shape 0, 1, 2; 3 = helicity recycling
   bool tuned = false;         // me_autotune has run (or found its configuration in the cache)
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
@@ -326,12 +339,24 @@ int ensure_bg_tables(me_ctx* c) {
   if (e == hipSuccess) e = hipMemcpy(c->d_bg_sub, t.sub.data(), t.sub.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_bg_mask, t.mask.data(), t.mask.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_bg_last, t.last.data(), t.last.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && c->bg->recycle) {
+    const me::BgCycleHostTables cy = me::bg_build_cycles(c->bg->n);
+    std::vector<uint16_t> all(cy.seg);
+    all.insert(all.end(), cy.cbase.begin(), cy.cbase.end());
+    all.insert(all.end(), cy.rbase.begin(), cy.rbase.end());
+    c->n_bg_cyc = (int)cy.seg.size();
+    c->n_bg_slot = (int)cy.cbase.size();
+    e = hipMalloc(&c->d_bg_cyc, all.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(c->d_bg_cyc, all.data(), all.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     if (c->d_bg_sub) (void)hipFree(c->d_bg_sub);
     if (c->d_bg_mask) (void)hipFree(c->d_bg_mask);
     if (c->d_bg_last) (void)hipFree(c->d_bg_last);
+    if (c->d_bg_cyc) (void)hipFree(c->d_bg_cyc);
     c->d_bg_sub = nullptr;
     c->d_bg_mask = c->d_bg_last = nullptr;
+    c->d_bg_cyc = nullptr;
     return fail(ME_ENOMEM, std::string("Berends-Giele tables: ") + hipGetErrorString(e));
   }
   return ME_OK;
@@ -688,6 +713,7 @@ int me_finalize(me_handle h) {
   if (h->d_bg_sub) (void)hipFree(h->d_bg_sub);
   if (h->d_bg_mask) (void)hipFree(h->d_bg_mask);
   if (h->d_bg_last) (void)hipFree(h->d_bg_last);
+  if (h->d_bg_cyc) (void)hipFree(h->d_bg_cyc);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   free_tables(h);
@@ -911,6 +937,8 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       me::BgArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_bg_sub, h->d_bg_mask,
                    h->d_bg_last, alphas ? alphas + off : nullptr, h->d_sums, s};
       a.variant = h->bg_variant;
+      if (h->d_bg_cyc)
+        a.cyc = me::BgCycles{h->d_bg_cyc, h->d_bg_cyc + h->n_bg_cyc, h->d_bg_cyc + h->n_bg_cyc + h->n_bg_slot};
       KernelMark kd(h, ME_KT_DIAGRAM, s);
       hipError_t e = h->bg->launch(a);
       if (e != hipSuccess) return hip_fail(e, "Berends-Giele kernel launch");
@@ -926,8 +954,12 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
       kc.done();
       KernelMark kr(h, ME_KT_REDUCE, s);
-      hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
-                         nhel, n, scale, out_me2 + off);
+      if (h->bg_variant == 3)   // event-major rows
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
+                           nhel, n, scale, out_me2 + off);
+      else
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
+                           nhel, n, scale, out_me2 + off);
       kr.done();
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
@@ -1480,7 +1512,9 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
 int me_set_bg(me_handle h, int variant) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (variant < 0 || variant > 2) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
+  if (variant < 0 || variant > 3) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
+  if (variant == 3 && !h->bg->recycle)
+    return fail(ME_EINVAL, "helicity recycling is built for four and five gluons only");
   h->bg_variant = variant;
   drop_graph(h);
   return ME_OK;
@@ -1635,6 +1669,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_TEAM, 0, 0, 0, 0, 0}});
   }
   for (int v : {0, 1, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
+  if (h->bg->recycle) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, 3}});
   if (h->desc->split) {
     // group-sum kernel variants (waves per SIMD), flow chunk sizes and event chunks
     // (as many whole rounds of group-sum waves as fit the scratch, or two rounds)

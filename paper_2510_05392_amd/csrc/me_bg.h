@@ -440,12 +440,6 @@ hipError_t launch_bg_v(const BgArgs& a) {
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t launch_bg(const BgArgs& a) {
-  if (a.variant == 1) return launch_bg_v<N, 1>(a);
-  if (a.variant == 2) return launch_bg_v<N, 2>(a);
-  return launch_bg_v<N, 0>(a);
-}
 #endif
 
 }  // namespace me

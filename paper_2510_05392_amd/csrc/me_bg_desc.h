@@ -13,7 +13,16 @@ struct BgTables {
   const uint8_t* last;   // [nslot]: last gluon of each sequence
 };
 
-// One chunk of rows (row = k n + e: good helicity k, event e of the chunk).
+// Rotation-cycle tables of the helicity-recycling kernel (device, read-only; built
+// by bg_build_cycles, gluon counts >= 4).
+struct BgCycles {
+  const uint16_t* seg;   // [(n-1)!][n][n]: slot of each cyclic segment of each cycle
+  const uint16_t* cbase; // [nslot]: first helicity variant of each stored current
+  const uint16_t* rbase; // [nslot]: first helicity variant of each stored row spinor
+};
+
+// One chunk of rows: row = k n + e (good helicity k, event e of the chunk) for
+// variants 0 .. 2, row = e nhel + k for variant 3 (helicity recycling).
 struct BgArgs {
   const double* mom;     // device, [n][npar][4] (the chunk's events)
   int64_t n;
@@ -26,7 +35,8 @@ struct BgArgs {
   const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
   double* jt;            // device, dual amplitudes [2 NCOL][n nhel]
   hipStream_t stream;
-  int variant = 0;       // launch shape (rows and threads per workgroup): 0, 1 or 2
+  int variant = 0;       // 0, 1, 2: one row per item, launch shapes; 3: helicity recycling
+  BgCycles cyc{nullptr, nullptr, nullptr};   // variant 3 only
 };
 
 using BgLauncher = hipError_t (*)(const BgArgs&);
@@ -41,6 +51,7 @@ struct BgDesc {
   BgLauncher launch;
   Colour64Launcher colour64;
   int colour_tri;        // 1: colour64 takes the block-triangular matrix, 0: the full one
+  int recycle;           // 1: launch variant 3 (helicity recycling) is built
 };
 
 }  // namespace me

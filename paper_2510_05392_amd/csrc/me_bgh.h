@@ -1,0 +1,508 @@
+// Berends-Giele executor with helicity recycling: one workgroup evaluates every
+// good helicity of EV events.  An ordered current depends only on the helicities
+// of its own gluons, so a current of length L is formed for its 2^L helicity
+// variants instead of once per helicity row, and a row spinor of length L for its
+// 2 x 2^L variants (top helicity and its gluons).  Recursion and conventions are
+// those of me_bg.h; the dual amplitudes are the same numbers (to rounding).
+//
+// Per event, in LDS: momentum sums of every gluon subset, ubar and v of both
+// helicities and Q = i g ubar gamma v of the four (ubar, v) pairs, the currents of
+// every sequence of length 1 .. N-2 with their variants, the row spinors of every
+// prefix of length 1 .. N-3 with theirs (about 56 KB for five gluons).
+//
+// The full orderings fall into (N-1)! cycles under rotation.  For sigma_i = the
+// i-th rotation of a cycle's representative, the current of length N-1 that starts
+// sigma_i (its prefix) is the current that ends sigma_{i-1} (its suffix), so one
+// work item = (cycle, gluon helicities) walks the N rotations keeping two of these
+// currents in registers and forms each once.  Per ordering it forms the full
+// current J(sigma), the row spinors R(sigma[:N-2]) and R(sigma[:N-1]) of each top
+// helicity, W = sum_{k>=1} R(sigma[:k]) (i g gamma.J(sigma[k:])), and the
+// amplitudes Q.J(sigma) + W v of the four quark helicity pairs.
+#pragma once
+#include "me_bg.h"
+
+namespace me {
+
+// bits of x at the set bits of m, packed from bit 0 (gluon counts <= 6)
+__device__ __forceinline__ int bg_pext(int x, int m) {
+  int r = 0, k = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if ((m >> b) & 1) {
+      r |= ((x >> b) & 1) << k;
+      ++k;
+    }
+  return r;
+}
+
+// the low bits of x deposited at the set bits of m
+__device__ __forceinline__ int bg_pdep(int x, int m) {
+  int r = 0, k = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if ((m >> b) & 1) {
+      r |= ((x >> k) & 1) << b;
+      ++k;
+    }
+  return r;
+}
+
+template <int N>
+struct BghShape {
+  using B = BgShape<N>;
+  static constexpr int NPAR = N + 2;
+  static constexpr int LC = N - 2;   // stored current lengths 1 .. LC
+  static constexpr int LR = N - 3;   // stored row-spinor lengths 1 .. LR
+  static constexpr int cvar(int L) {
+    int o = 0;
+    for (int l = 1; l < L; ++l) o += B::count(l) << l;
+    return o;
+  }
+  static constexpr int rvar(int L) {
+    int o = 0;
+    for (int l = 1; l < L; ++l) o += B::count(l) << (l + 1);
+    return o;
+  }
+  static constexpr int NCV = cvar(LC + 1);   // stored current variants
+  static constexpr int NRV = rvar(LR + 1);   // stored row-spinor variants
+  static constexpr int NCYC = B::NCOL / N;
+  static constexpr int ITEMS = NCYC << N;    // cycle items per event
+  static constexpr int NSET = (1 << N) + 2 * N + 8;
+  static constexpr int PSOFF = 0;                        // momentum sums [2^N][4]
+  static constexpr int SPOFF = 4 << N;                   // ubar[2], v[2], Q[2][2]
+  static constexpr int COFF = SPOFF + 8 * BG_SLOT;       // currents
+  static constexpr int ROFF = COFF + NCV * BG_SLOT;      // row spinors
+  static constexpr int MOFF = ROFF + NRV * BG_SLOT;      // momenta [NPAR][4]
+  static constexpr int GOFF = MOFF + 4 * NPAR;           // coupling
+  static constexpr int FRAME = GOFF + 2;                 // doubles per event
+};
+
+template <int N>
+__device__ __forceinline__ int bgh_caddr(const BgTables& t, const BgCycles& cy, int slot, int gh) {
+  return BghShape<N>::COFF + (cy.cbase[slot] + bg_pext(gh, t.mask[slot])) * BG_SLOT;
+}
+
+template <int N>
+__device__ __forceinline__ int bgh_raddr(const BgTables& t, const BgCycles& cy, int slot, int L, int u, int gh) {
+  return BghShape<N>::ROFF + (cy.rbase[slot] + (u << L) + bg_pext(gh, t.mask[slot])) * BG_SLOT;
+}
+
+// Set-up item i of one event (0 <= i < NSET): momentum sums, the polarisation
+// vectors of both helicities of every gluon, ubar and v of both helicities, the
+// four Q.  Momenta and coupling are in the frame.
+template <int N>
+__device__ __forceinline__ void bgh_setup_item(double* F, const BgCycles& cy, double mt, int i) {
+  using H = BghShape<N>;
+  const double(*p)[4] = reinterpret_cast<const double(*)[4]>(F + H::MOFF);
+  if (i < (1 << N)) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < N; ++b)
+      if ((i >> b) & 1) {
+        const int q = b < 2 ? b : b + 2;
+        const double sg = b < 2 ? 1.0 : -1.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += sg * p[q][u];
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) F[H::PSOFF + 4 * i + u] = s[u];
+  } else if (i < (1 << N) + 2 * N) {
+    const int j = i - (1 << N), b = j >> 1, bit = j & 1;
+    const int q = b < 2 ? b : b + 2;
+    cx e[4];
+    ext_gluon(p[q], bit ? 1 : -1, b >= 2, e);
+    bg_store(F, H::COFF + (cy.cbase[b] + bit) * BG_SLOT, e);
+  } else {
+    const int j = i - (1 << N) - 2 * N;   // 0, 1: ubar; 2, 3: v; 4 + 2 u + v: Q
+    cx w[4];
+    if (j < 2) {
+      ext_ubar(p[2], j ? 1 : -1, mt, w);
+    } else if (j < 4) {
+      ext_v(p[3], (j - 2) ? 1 : -1, mt, w);
+    } else {
+      cx ub[4], v[4];
+      ext_ubar(p[2], ((j - 4) >> 1) ? 1 : -1, mt, ub);
+      ext_v(p[3], ((j - 4) & 1) ? 1 : -1, mt, v);
+      line_current(ub, v, F[H::GOFF], w);
+    }
+    bg_store(F, H::SPOFF + j * BG_SLOT, w);
+  }
+}
+
+// Stored current of sequence `slot` (length L, 2 <= L <= N-2), helicity variant hv.
+template <int N>
+__device__ __forceinline__ void bgh_current_item(double* F, const BgTables& t, const BgCycles& cy, int slot, int L,
+                                                 int hv) {
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  const uint16_t* sub = t.sub + (int64_t)slot * S::T;
+  const int gh = bg_pdep(hv, t.mask[slot]);
+  const double g = F[H::GOFF];
+  cx a3[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+  cx a4[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+#pragma unroll 1
+  for (int j = 1; j < L; ++j) {
+    const int s1 = sub[bg_tri(0, j)], s2 = sub[bg_tri(j, L)];
+    cx ja[4], jb[4];
+    double pa[4], pb[4];
+    bg_load(F, bgh_caddr<N>(t, cy, s1, gh), ja);
+    bg_load(F, bgh_caddr<N>(t, cy, s2, gh), jb);
+    bg_mom(F, t.mask[s1], pa);
+    bg_mom(F, t.mask[s2], pb);
+    bg_v3(ja, pa, jb, pb, a3);
+  }
+#pragma unroll 1
+  for (int j = 1; j + 1 < L; ++j) {
+    cx ja[4];
+    bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(0, j)], gh), ja);
+#pragma unroll 1
+    for (int l = j + 1; l < L; ++l) {
+      cx jb[4], jc[4];
+      bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(j, l)], gh), jb);
+      bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(l, L)], gh), jc);
+      bg_v4(ja, jb, jc, a4);
+    }
+  }
+  double p[4];
+  bg_mom(F, t.mask[slot], p);
+  const double inv = 1.0 / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
+  const double f3 = -g * inv, f4 = -g * g * inv;
+  cx out[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
+  bg_store(F, H::COFF + (cy.cbase[slot] + hv) * BG_SLOT, out);
+}
+
+// Stored row spinor of prefix `slot` (length L, 1 <= L <= N-3), top helicity u,
+// gluon helicity variant hv.
+template <int N>
+__device__ __forceinline__ void bgh_row_item(double* F, const BgTables& t, const BgCycles& cy, int slot, int L, int u,
+                                             int hv, double mt) {
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  const uint16_t* sub = t.sub + (int64_t)slot * S::T;
+  const int gh = bg_pdep(hv, t.mask[slot]);
+  const double g = F[H::GOFF];
+  cx acc[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+#pragma unroll 1
+  for (int j = 0; j < L; ++j) {
+    cx r[4], jj[4], v[4];
+    bg_load(F, j == 0 ? H::SPOFF + u * BG_SLOT : bgh_raddr<N>(t, cy, sub[bg_tri(0, j)], j, u, gh), r);
+    bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(j, L)], gh), jj);
+    row_vertex(r, jj, g, v);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) acc[w] = acc[w] + v[w];
+  }
+  double q[4];
+  bg_mom(F, t.mask[slot], q);
+  const double* p3 = F + H::MOFF + 8;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) q[w] = p3[w] - q[w];
+  cx out[4];
+  row_prop(acc, q, mt, out);
+  bg_store(F, H::ROFF + (cy.rbase[slot] + (u << L) + hv) * BG_SLOT, out);
+}
+
+__device__ __forceinline__ void bgh_copy(const cx* a, cx* b) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) b[u] = a[u];
+}
+
+// acc += R (i g gamma.J)
+__device__ __forceinline__ void bgh_rv_acc(const cx* r, const cx* j, double g, cx* acc) {
+  cx v[4];
+  row_vertex(r, j, g, v);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = acc[u] + v[u];
+}
+
+template <int N>
+__device__ __forceinline__ int bg_mod(int a) { return a >= N ? a - N : a; }
+
+// Lookup tables of one cycle item (cycle z, gluon helicities gh), in LDS.  Segment
+// (a, len) = the len gluons from position a (mod N) of the cycle's representative.
+//   tab[(a LC + len - 1) stride]        frame offset of the stored current of
+//                                       segment (a, len), len <= LC
+//   tab[(N LC + a LR + len - 1) stride] frame offset of the stored row spinor of
+//                                       segment (a, len), len <= LR, top helicity -
+//                                       (helicity + is 2^len slots further)
+//   sm[a N + len - 1]                   gluon subset of segment (a, len)
+template <int N>
+struct BghItem {
+  const uint16_t* tab;
+  int stride;
+  const uint8_t* sm;
+  __device__ __forceinline__ int cur(int a, int len) const { return tab[(a * (N - 2) + len - 1) * stride]; }
+  __device__ __forceinline__ int row(int a, int len) const {
+    return tab[(N * (N - 2) + a * (N - 3) + len - 1) * stride];
+  }
+  __device__ __forceinline__ int mask(int a, int len) const { return sm[a * N + len - 1]; }
+};
+
+template <int N>
+__device__ __forceinline__ void bgh_fill_item(uint16_t* tab, int stride, const BgTables& t, const BgCycles& cy, int z,
+                                              int gh) {
+  constexpr int LC = N - 2, LR = N - 3;
+  const uint16_t* seg = cy.seg + (int64_t)z * N * N;
+#pragma unroll 1
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int l = 1; l <= LC; ++l) tab[(a * LC + l - 1) * stride] = (uint16_t)bgh_caddr<N>(t, cy, seg[a * N + l - 1], gh);
+#pragma unroll
+    for (int l = 1; l <= LR; ++l)
+      tab[(N * LC + a * LR + l - 1) * stride] = (uint16_t)bgh_raddr<N>(t, cy, seg[a * N + l - 1], l, 0, gh);
+  }
+}
+
+// Current of segment (s, L), L = N-1 or N.  L = N-1: every split is stored.  L = N:
+// the splits (N-1, 1) and (1, N-1) take pre = J(s, N-1) and suf = J(s+1, N-1).
+template <int N, int L>
+__device__ __forceinline__ void bgh_item_current(const double* F, const BghItem<N>& it, int s, const cx* pre,
+                                                 const cx* suf, double g, cx* out) {
+  cx a3[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+  cx a4[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+  if constexpr (L == N) {
+    cx ja[4], jb[4];
+    double pa[4], pb[4];
+    const int b1 = bg_mod<N>(s + 1), bl = bg_mod<N>(s + N - 1);
+    bg_load(F, it.cur(s, 1), ja);
+    bg_mom(F, it.mask(s, 1), pa);
+    bg_mom(F, it.mask(b1, N - 1), pb);
+    bg_v3(ja, pa, suf, pb, a3);
+    bg_load(F, it.cur(bl, 1), jb);
+    bg_mom(F, it.mask(s, N - 1), pa);
+    bg_mom(F, it.mask(bl, 1), pb);
+    bg_v3(pre, pa, jb, pb, a3);
+  }
+  constexpr int JLO = L == N ? 2 : 1, JHI = L == N ? N - 2 : L - 1;
+#pragma unroll 1
+  for (int j = JLO; j <= JHI; ++j) {
+    const int b = bg_mod<N>(s + j);
+    cx ja[4], jb[4];
+    double pa[4], pb[4];
+    bg_load(F, it.cur(s, j), ja);
+    bg_load(F, it.cur(b, L - j), jb);
+    bg_mom(F, it.mask(s, j), pa);
+    bg_mom(F, it.mask(b, L - j), pb);
+    bg_v3(ja, pa, jb, pb, a3);
+  }
+#pragma unroll 1
+  for (int j = 1; j + 1 < L; ++j) {
+    cx ja[4];
+    bg_load(F, it.cur(s, j), ja);
+#pragma unroll 1
+    for (int l = j + 1; l < L; ++l) {
+      cx jb[4], jc[4];
+      bg_load(F, it.cur(bg_mod<N>(s + j), l - j), jb);
+      bg_load(F, it.cur(bg_mod<N>(s + l), L - l), jc);
+      bg_v4(ja, jb, jc, a4);
+    }
+  }
+  double p[4];
+  bg_mom(F, it.mask(s, L), p);
+  const double inv = 1.0 / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
+  const double f3 = -g * inv, f4 = -g * g * inv;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
+}
+
+// One work item: cycle z, gluon helicities gh (bit b = helicity + of gluon b), the
+// N rotations sigma_i (segment (i, N)) and the four quark helicity pairs.
+// krow[2 u + v] = good-helicity row of (gh, u, v) or -1; the amplitude of flow c
+// goes to jt[2 c][row0 + k] (real) and jt[2 c + 1][row0 + k] (imaginary), row0 =
+// this event's first row.
+template <int N>
+__device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& cy, const BghItem<N>& it, int z,
+                                               const int* krow, double mt, double* __restrict__ jt, int64_t rows,
+                                               int64_t row0) {
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  constexpr int LR = H::LR;
+  const uint16_t* seg = cy.seg + (int64_t)z * N * N;
+  const double g = F[H::GOFF];
+  const double* p3 = F + H::MOFF + 8;
+  cx cfirst[4], ccur[4], cnext[4];
+  bgh_item_current<N, N - 1>(F, it, 0, nullptr, nullptr, g, ccur);
+  bgh_copy(ccur, cfirst);
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) {
+    if (i + 1 < N) bgh_item_current<N, N - 1>(F, it, i + 1, nullptr, nullptr, g, cnext);
+    else bgh_copy(cfirst, cnext);
+    cx jf[4];
+    bgh_item_current<N, N>(F, it, i, ccur, cnext, g, jf);
+    const int col = seg[i * N + N - 1] - S::off(N);
+#pragma unroll 1
+    for (int u = 0; u < 2; ++u) {
+      const int ka = u ? krow[2] : krow[0], kb = u ? krow[3] : krow[1];
+      if (ka < 0 && kb < 0) continue;
+      cx acc[4], rr[4], jj[4], rn2[4], w[4];
+      double q[4];
+      // R(sigma[:N-2]) = S . sum_{j < N-2} R(sigma[:j]) (i g gamma.J(sigma[j:N-2]))
+      bg_load(F, H::SPOFF + u * BG_SLOT, rr);
+      bg_load(F, it.cur(i, N - 2), jj);
+      row_vertex(rr, jj, g, acc);
+#pragma unroll 1
+      for (int j = 1; j <= LR; ++j) {
+        bg_load(F, it.row(i, j) + (u << j) * BG_SLOT, rr);
+        bg_load(F, it.cur(bg_mod<N>(i + j), N - 2 - j), jj);
+        bgh_rv_acc(rr, jj, g, acc);
+      }
+      bg_mom(F, it.mask(i, N - 2), q);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) q[x] = p3[x] - q[x];
+      row_prop(acc, q, mt, rn2);
+      // W = sum_{k >= 1} R(sigma[:k]) (i g gamma.J(sigma[k:])), from k = N-2
+      bg_load(F, it.cur(bg_mod<N>(i + N - 2), 2), jj);
+      row_vertex(rn2, jj, g, w);
+      // R(sigma[:N-1]) = S . (R() (i g gamma.J(sigma[:N-1])) + sum_{1 <= j <= N-2} ...)
+      bg_load(F, H::SPOFF + u * BG_SLOT, rr);
+      row_vertex(rr, ccur, g, acc);
+#pragma unroll 1
+      for (int j = 1; j <= LR; ++j) {
+        bg_load(F, it.row(i, j) + (u << j) * BG_SLOT, rr);
+        bg_load(F, it.cur(bg_mod<N>(i + j), N - 1 - j), jj);
+        bgh_rv_acc(rr, jj, g, acc);
+      }
+      bg_load(F, it.cur(bg_mod<N>(i + N - 2), 1), jj);
+      bgh_rv_acc(rn2, jj, g, acc);
+      bg_mom(F, it.mask(i, N - 1), q);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) q[x] = p3[x] - q[x];
+      row_prop(acc, q, mt, rr);   // rr = R(sigma[:N-1])
+      bg_load(F, it.cur(bg_mod<N>(i + N - 1), 1), jj);
+      bgh_rv_acc(rr, jj, g, w);
+      // k = 1 (its current is cnext) and 2 <= k <= N-3 (stored rows)
+      bg_load(F, it.row(i, 1) + (u << 1) * BG_SLOT, rr);
+      bgh_rv_acc(rr, cnext, g, w);
+#pragma unroll 1
+      for (int k = 2; k <= LR; ++k) {
+        bg_load(F, it.row(i, k) + (u << k) * BG_SLOT, rr);
+        bg_load(F, it.cur(bg_mod<N>(i + k), N - k), jj);
+        bgh_rv_acc(rr, jj, g, w);
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int k = v ? kb : ka;
+        if (k < 0) continue;
+        cx qv[4], vs[4];
+        bg_load(F, H::SPOFF + (4 + 2 * u + v) * BG_SLOT, qv);
+        bg_load(F, H::SPOFF + (2 + v) * BG_SLOT, vs);
+        const cx a = vdot(qv, jf) + sdot(w, vs);
+        jt[(int64_t)(2 * col) * rows + row0 + k] = a.r;
+        jt[(int64_t)(2 * col + 1) * rows + row0 + k] = a.i;
+      }
+    }
+    bgh_copy(cnext, ccur);
+  }
+}
+
+// Good-helicity rows of the four quark helicity pairs of gluon helicities gh.
+template <int N>
+__device__ __forceinline__ void bgh_krow(const int* hrow, int gh, int* krow) {
+  constexpr int NPAR = N + 2;
+  int hg = 0;
+#pragma unroll
+  for (int b = 0; b < N; ++b) hg |= ((gh >> b) & 1) << (NPAR - 1 - (b < 2 ? b : b + 2));
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) krow[2 * u + v] = hrow[hg | (u << (NPAR - 3)) | (v << (NPAR - 4))];
+}
+
+#ifdef __HIPCC__
+// One workgroup: events blockIdx.x EV .. + EV - 1 of the chunk, all good
+// helicities; rows event-major (row = e nhel + k).  Levels: set-up, then for
+// L = 2 .. N-2 the currents of length L with the row spinors of length L - 1,
+// then the cycle items; barriers between levels.  Dynamic LDS: the EV frames,
+// the segment masks of every cycle, each thread's item table.
+template <int N, int EV, int THREADS>
+__global__ void __launch_bounds__(THREADS) bgh_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt,
+                                                      const int* __restrict__ hels, int nhel, BgTables t, BgCycles cy,
+                                                      const double* __restrict__ alphas, double* __restrict__ jt) {
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  constexpr int NPAR = N + 2;
+  extern __shared__ double lds[];
+  uint8_t* sm = reinterpret_cast<uint8_t*>(lds + EV * H::FRAME);
+  uint16_t* tabs = reinterpret_cast<uint16_t*>(sm + ((H::NCYC * N * N + 15) & ~15));
+  __shared__ int hrow[1 << NPAR];
+  const int64_t e0 = (int64_t)blockIdx.x * EV;
+  const int nev = (int)(n - e0 < EV ? n - e0 : EV);
+  const int64_t rows = n * nhel;
+  for (int i = threadIdx.x; i < (1 << NPAR); i += THREADS) hrow[i] = -1;
+  for (int i = threadIdx.x; i < nev * NPAR * 4; i += THREADS)
+    lds[(i / (NPAR * 4)) * H::FRAME + H::MOFF + i % (NPAR * 4)] = mom[e0 * NPAR * 4 + i];
+  for (int i = threadIdx.x; i < nev; i += THREADS)
+    lds[i * H::FRAME + H::GOFF] = alphas ? sqrt(4.0 * 3.14159265358979323846 * alphas[e0 + i]) : g0;
+  for (int i = threadIdx.x; i < H::NCYC * N * N; i += THREADS) sm[i] = t.mask[cy.seg[i]];
+  __syncthreads();
+  for (int k = threadIdx.x; k < nhel; k += THREADS) hrow[hels[k]] = k;
+  for (int it = threadIdx.x; it < nev * H::NSET; it += THREADS)
+    bgh_setup_item<N>(lds + (it / H::NSET) * H::FRAME, cy, mt, it % H::NSET);
+  __syncthreads();
+#pragma unroll 1
+  for (int L = 2; L <= H::LC; ++L) {
+    const int nc = S::count(L) << L;
+    const int nr = L - 1 <= H::LR ? S::count(L - 1) << L : 0;
+    for (int it = threadIdx.x; it < nev * (nc + nr); it += THREADS) {
+      const int ev = it / (nc + nr), w = it % (nc + nr);
+      double* F = lds + ev * H::FRAME;
+      if (w < nc) {
+        bgh_current_item<N>(F, t, cy, S::off(L) + (w >> L), L, w & ((1 << L) - 1));
+      } else {
+        const int x = w - nc, Lr = L - 1;   // x = (rank, u, hv)
+        bgh_row_item<N>(F, t, cy, S::off(Lr) + (x >> (Lr + 1)), Lr, (x >> Lr) & 1, x & ((1 << Lr) - 1), mt);
+      }
+    }
+    __syncthreads();
+  }
+  uint16_t* tab = tabs + threadIdx.x;
+  for (int it = threadIdx.x; it < nev * H::ITEMS; it += THREADS) {
+    const int ev = it / H::ITEMS, w = it % H::ITEMS;
+    const int z = w >> N, gh = w & ((1 << N) - 1);
+    int krow[4];
+    bgh_krow<N>(hrow, gh, krow);
+    if (krow[0] < 0 && krow[1] < 0 && krow[2] < 0 && krow[3] < 0) continue;
+    bgh_fill_item<N>(tab, THREADS, t, cy, z, gh);
+    const BghItem<N> item{tab, THREADS, sm + z * N * N};
+    bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, (e0 + ev) * nhel);
+  }
+}
+
+// Events per workgroup and threads: the frames of EV events within about 56 KB.
+template <int N> struct BghLaunchShape;
+template <> struct BghLaunchShape<4> { static constexpr int EV = 8, THREADS = 256; };
+template <> struct BghLaunchShape<5> { static constexpr int EV = 1, THREADS = 256; };
+
+template <int N>
+hipError_t launch_bgh(const BgArgs& a) {
+  using H = BghShape<N>;
+  constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
+  const size_t lds = (size_t)EV * H::FRAME * sizeof(double) + ((H::NCYC * N * N + 15) & ~15) +
+                     (size_t)N * (H::LC + H::LR) * THREADS * sizeof(uint16_t);
+  static const hipError_t attr = hipFuncSetAttribute((const void*)bgh_kernel<N, EV, THREADS>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  if (!a.cyc.seg) return hipErrorInvalidValue;
+  if (a.n == 0 || a.nhel == 0) return hipSuccess;
+  const BgTables t{a.sub, a.mask, a.last};
+  hipLaunchKernelGGL((bgh_kernel<N, EV, THREADS>), dim3((unsigned)((a.n + EV - 1) / EV)), dim3(THREADS), lds,
+                     a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt);
+  return hipGetLastError();
+}
+
+// Launch of the executor's kernel in the chosen variant (3: helicity recycling,
+// built for four and five gluons).
+template <int N>
+hipError_t launch_bg(const BgArgs& a) {
+  if constexpr (N == 4 || N == 5) {
+    if (a.variant == 3) return launch_bgh<N>(a);
+  } else {
+    if (a.variant == 3) return hipErrorInvalidValue;
+  }
+  if (a.variant == 1) return launch_bg_v<N, 1>(a);
+  if (a.variant == 2) return launch_bg_v<N, 2>(a);
+  return launch_bg_v<N, 0>(a);
+}
+#endif
+
+}  // namespace me

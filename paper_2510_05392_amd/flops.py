@@ -152,18 +152,51 @@ def bg_row(n):
             'total': setup + currents + rows + amps}
 
 
-def diagram_kernel(name, executor):
+def bgh_event(n):
+    """FP64 flops of one event of the helicity-recycling Berends-Giele kernel with n
+    gluons (n = 4, 5) and every helicity good: currents of length L <= n-2 once per
+    helicity variant of their gluons (2^L), row spinors of length L <= n-3 once per
+    variant (2^(L+1)), and (n-1)! 2^n cycle items, each forming the n currents of
+    length n-1 along its rotation cycle and, per ordering, the full current, the two
+    row spinors and W of each top helicity, and four amplitudes (beams along +-z; the
+    spinor branch for pz < 0 not included)."""
+    import math
+    cnt = [0] + [math.perm(n, L) for L in range(1, n + 1)]
+
+    def current(L):
+        return (L - 1) * BG['v3'] + math.comb(L - 1, 2) * BG['v4'] + BG['close']
+
+    setup = 8 * n * 2 ** (n - 1) + 2 * (2 * ROUTINE['Gbeam'] + (n - 2) * ROUTINE['G']) \
+        + 6 * (ROUTINE['U'] + ROUTINE['V']) + 4 * BG['line']
+    currents = sum(cnt[L] * 2 ** L * current(L) for L in range(2, n - 1))
+    rows = sum(cnt[L] * 2 ** (L + 1) * (L * BG['row_term'] + BG['row_close']) for L in range(1, n - 2))
+    # the first term of each row spinor and of W is assigned, not accumulated (-8)
+    per_u = ((n - 2) * BG['row_term'] - 8 + BG['row_close']) + ((n - 1) * BG['row_term'] - 8 + BG['row_close']) \
+        + ((n - 1) * BG['row_term'] - 8)
+    per_order = current(n) + 2 * per_u + 4 * (2 * ROUTINE['vdot'] + 2)
+    items = cnt[n] // n * 2 ** n * (n * current(n - 1) + n * per_order)
+    return {'setup': setup, 'currents': currents, 'rows': rows, 'items': items,
+            'total': setup + currents + rows + items}
+
+
+def diagram_kernel(name, executor, bg_variant=0):
     """FP64 flops per (event, helicity) of the kernel that evaluates the diagrams:
     everything for the one-lane and team executors (flows and colour form are fused
     into it; the team program runs the same routines), the group sums alone for the
     split executor (executor 2), whose flows and colour form run in kernels of their
     own, the recursion alone for the Berends-Giele executor (executor 3), whose
-    colour form is a kernel of its own."""
+    colour form is a kernel of its own; with helicity recycling (launch variant 3)
+    the kernel's flops per event divided by the 2^npar helicity rows (every helicity
+    of these processes is good)."""
     if executor == 2:
         return group_sums_flops(name) + QUARK_BRANCH_MEAN
     if executor == 3:
         from .gen import codegen
-        return bg_row(codegen.PROCESS_NPAR[name] - 2)['total'] + QUARK_BRANCH_MEAN
+        npar = codegen.PROCESS_NPAR[name]
+        if bg_variant == 3:
+            # per event over every helicity, shared out over the 2^npar rows
+            return (bgh_event(npar - 2)['total'] + 6 * QUARK_BRANCH_MEAN) / 2 ** npar
+        return bg_row(npar - 2)['total'] + QUARK_BRANCH_MEAN
     return per_event_helicity(name) + QUARK_BRANCH_MEAN
 
 

@@ -177,7 +177,7 @@ def build_bg(opt='-O2'):
     """Host build of the Berends-Giele executor's device functions (all gluon counts)."""
     os.makedirs(OUT, exist_ok=True)
     lib = os.path.join(OUT, 'bg_harness.so')
-    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bg_desc.h', 'me_bg_tables.h')]
+    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bgh.h', 'me_bg_desc.h', 'me_bg_tables.h')]
     deps.append(os.path.join(HERE, 'bg_harness.cpp'))
     if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
         cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE), '-I', CSRC,
@@ -205,12 +205,26 @@ class BgHarness:
         assert rc == 0
         return out[..., 0] + 1j * out[..., 1]
 
+    def jamps_recycled(self, n, mom, g, mt, hels):
+        """The same dual amplitudes from the helicity-recycling kernel's work (n = 4, 5)."""
+        import math
+        mom = np.ascontiguousarray(mom, dtype=np.float64)
+        nevt = mom.shape[0]
+        hels = np.ascontiguousarray(hels, dtype=np.int32)
+        out = np.zeros((len(hels), nevt, math.factorial(n), 2))
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        rc = self.lib.harness_bgh_eval(ctypes.c_int(n), mom.ctypes.data_as(dp), ctypes.c_int(nevt),
+                                       ctypes.c_double(g), ctypes.c_double(mt), hels.ctypes.data_as(ip),
+                                       ctypes.c_int(len(hels)), out.ctypes.data_as(dp))
+        assert rc == 0
+        return out[..., 0] + 1j * out[..., 1]
+
 
 def build_count_bg(opt='-O1'):
     """Host build of the Berends-Giele device functions with the operation-counting scalar."""
     os.makedirs(OUT, exist_ok=True)
     lib = os.path.join(OUT, 'count_bg_harness.so')
-    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bg_desc.h', 'me_bg_tables.h')]
+    deps = [os.path.join(CSRC, h) for h in ('me_device.h', 'me_bg.h', 'me_bgh.h', 'me_bg_desc.h', 'me_bg_tables.h')]
     deps.append(os.path.join(HERE, 'count_bg_harness.cpp'))
     if not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(d) for d in deps):
         cmd = ['g++', opt, '-std=c++17', '-shared', '-fPIC', '-I', os.path.join(HERE), '-I', CSRC,
@@ -219,9 +233,15 @@ def build_count_bg(opt='-O1'):
         os.replace(lib + '.tmp', lib)
     lib = ctypes.CDLL(lib)
 
-    def count(n, mom, hel):
+    def count(n, mom, hel=None):
+        """hel given: one row of the row kernels; hel None: one event of the
+        helicity-recycling kernel (every helicity good)."""
         m = np.ascontiguousarray(mom, dtype=np.float64)
         out = (ctypes.c_longlong * 4)()
-        assert lib.count_bg_row(n, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hel, out) == 0
+        ptr = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if hel is None:
+            assert lib.count_bgh_event(n, ptr, out) == 0
+        else:
+            assert lib.count_bg_row(n, ptr, hel, out) == 0
         return list(out)
     return count

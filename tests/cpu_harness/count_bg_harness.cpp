@@ -1,7 +1,7 @@
 // Operation count of the Berends-Giele executor's device functions (test-only):
-// the FP64 type becomes a counting scalar (see count_harness.cpp), one row is
-// evaluated at every level as the kernel does, and the counted operations are
-// returned.
+// the FP64 type becomes a counting scalar (see count_harness.cpp), one row (or,
+// for the helicity-recycling kernel, one event with every helicity) is evaluated
+// at every level as the kernel does, and the counted operations are returned.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -38,7 +38,7 @@ using cnt::sqrt;
 #define double CD
 #define volatile
 #define asm(...) (void)0
-#include "me_bg.h"
+#include "me_bgh.h"
 #undef asm
 #undef volatile
 #undef double
@@ -78,6 +78,66 @@ void count_row(const double* mom, int hel, long long* out) {
   cnt::flops = 0;
   for (int c = 0; c < S::NCOL; ++c) (void)bg_amplitude<N>(F.data(), t, p[2], S::off(N) + c, g, mt);
   out[3] = cnt::flops;
+}
+
+// Counted operations of one event of the helicity-recycling kernel with every
+// helicity good: set-up, stored currents, stored row spinors, cycle items.
+template <int N>
+void count_event(const double* mom, long long* out) {
+  using namespace me;
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  constexpr int NPAR = N + 2;
+  const BgHostTables ht = bg_build_tables(N);
+  const BgCycleHostTables hc = bg_build_cycles(N);
+  const BgTables t{ht.sub.data(), ht.mask.data(), ht.last.data()};
+  const BgCycles cy{hc.seg.data(), hc.cbase.data(), hc.rbase.data()};
+  std::vector<CD> F(H::FRAME);
+  std::vector<uint8_t> sm(hc.seg.size());
+  for (size_t i = 0; i < sm.size(); ++i) sm[i] = t.mask[hc.seg[i]];
+  std::vector<uint16_t> tab(N * (H::LC + H::LR));
+  std::vector<int> hrow(1 << NPAR);
+  for (int k = 0; k < (1 << NPAR); ++k) hrow[k] = k;
+  std::vector<CD> jt((size_t)2 * S::NCOL * (1 << NPAR));
+  for (int i = 0; i < NPAR * 4; ++i) F[H::MOFF + i] = CD(mom[i]);
+  F[H::GOFF] = CD(1.2);
+  const CD mt(173.0);
+  cnt::flops = 0;
+  for (int i = 0; i < H::NSET; ++i) bgh_setup_item<N>(F.data(), cy, mt, i);
+  out[0] = cnt::flops;
+  long long cur = 0, row = 0;
+  for (int L = 2; L <= H::LC; ++L) {
+    cnt::flops = 0;
+    for (int w = 0; w < (S::count(L) << L); ++w)
+      bgh_current_item<N>(F.data(), t, cy, S::off(L) + (w >> L), L, w & ((1 << L) - 1));
+    cur += cnt::flops;
+    cnt::flops = 0;
+    const int Lr = L - 1;
+    if (Lr <= H::LR)
+      for (int x = 0; x < (S::count(Lr) << L); ++x)
+        bgh_row_item<N>(F.data(), t, cy, S::off(Lr) + (x >> (Lr + 1)), Lr, (x >> Lr) & 1, x & ((1 << Lr) - 1), mt);
+    row += cnt::flops;
+  }
+  out[1] = cur;
+  out[2] = row;
+  cnt::flops = 0;
+  for (int w = 0; w < H::ITEMS; ++w) {
+    const int z = w >> N, gh = w & ((1 << N) - 1);
+    int krow[4];
+    bgh_krow<N>(hrow.data(), gh, krow);
+    bgh_fill_item<N>(tab.data(), 1, t, cy, z, gh);
+    const BghItem<N> item{tab.data(), 1, sm.data() + z * N * N};
+    bgh_cycle_item<N>(F.data(), cy, item, z, krow, mt, jt.data(), 1 << NPAR, 0);
+  }
+  out[3] = cnt::flops;
+}
+
+extern "C" int count_bgh_event(int n, const double* mom, long long* out) {
+  switch (n) {
+    case 4: count_event<4>(mom, out); return 0;
+    case 5: count_event<5>(mom, out); return 0;
+    default: return -1;
+  }
 }
 
 extern "C" int count_bg_row(int n, const double* mom, int hel, long long* out) {

@@ -247,6 +247,46 @@ def test_berends_giele_on_host_vs_oracle_and_lane_code(name, npar, nevt, hels):
         assert np.max(np.abs(jb - jl).max(axis=(0, 2)) / scale) < 1e-12
 
 
+@pytest.mark.parametrize('npar,nevt,hels', [(6, 3, None), (7, 1, None), (7, 2, (0, 5, 64, 100, 127))])
+def test_helicity_recycling_on_host_vs_row_kernel_and_oracle(npar, nevt, hels):
+    """The helicity-recycling kernel's work (host build: set-up, stored currents and
+    row spinors per helicity variant, then every rotation-cycle item) gives the same
+    dual amplitudes as the row kernel, flow by flow and helicity by helicity, also
+    when only some helicities are good; per-helicity colour sums against the oracle
+    on a few helicities."""
+    h = harness.build_bg()
+    mom = rambo.generate(npar, nevt, 8)
+    hl = list(range(2 ** npar)) if hels is None else list(hels)
+    g = math.sqrt(4 * math.pi * AS)
+    rec = h.jamps_recycled(npar - 2, mom, g, 173.0, hl)
+    row = h.jamps(npar - 2, mom, g, 173.0, hl)
+    scale = np.abs(row).max(axis=(0, 2))
+    assert np.max(np.abs(rec - row).max(axis=(0, 2)) / scale) < 1e-13
+    pick = [0, len(hl) // 3, len(hl) - 1]
+    proc = ome.process(npar)
+    cf = np.asarray(proc.cf)
+    meh = np.einsum('hei,ij,hej->he', rec[pick].conj(), cf, rec[pick]).real
+    ref = ome.me_helicities(proc, mom, AS, [hl[k] for k in pick])
+    assert np.max(np.abs(meh - ref) / ref.max(axis=0)) < 1e-12
+
+
+@pytest.mark.parametrize('n', [4, 5])
+def test_helicity_recycling_flops_equal_the_counted_operations(n):
+    """flops.bgh_event (building-block counts over the recycling kernel's levels and
+    cycle items) equals the operations its device functions perform for one event,
+    counted on the host with the operation-counting scalar, part by part; the six
+    spinor evaluations of the set-up take one more operation each for a quark with
+    pz < 0."""
+    count = harness.build_count_bg()
+    f = flops.bgh_event(n)
+    mom = rambo.generate(n + 2, 3, 1003)
+    for e in range(mom.shape[0]):
+        neg = int((mom[e, 2:4, 3] < 0).sum())
+        setup, currents, rows, items = count(n, mom[e])
+        assert setup == f['setup'] + 6 * neg
+        assert (currents, rows, items) == (f['currents'], f['rows'], f['items'])
+
+
 @pytest.mark.parametrize('n', [2, 3, 4, 5, 6])
 def test_berends_giele_flops_equal_the_counted_operations(n):
     """The Berends-Giele figures of the roofline (flops.bg_row: building-block counts

@@ -1,7 +1,9 @@
 """The colour-ordered Berends-Giele executor on the GPU against the oracle: every
 process, FP64 within 1e-12 per event (extended-precision adjudication), the
-split-precision colour sums within their bound, and gg -> tt gggg at its full
-32768-event size on the stored oracle values."""
+split-precision colour sums within their bound, gg -> tt gggg at its full
+32768-event size on the stored oracle values, and the helicity-recycling kernel
+(launch variant 3) on gg -> tt gg and gg -> tt ggg, up to the full 262144-event
+workload."""
 import os
 import time
 
@@ -27,9 +29,11 @@ def binding():
     return b
 
 
-def _bg(binding, name, mom, mode=0):
+def _bg(binding, name, mom, mode=0, variant=None):
     m = binding.MatrixElement(name, colorsum_mode=mode)
     m.me_set_executor(binding.ME_EXEC_BG)
+    if variant is not None:
+        m.me_set_bg(variant)
     d = torch.from_numpy(mom).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -90,3 +94,41 @@ def test_bg_matches_team_program_ggttgggg(binding):
     m = binding.MatrixElement('gg_ttxgggg')
     team = m.compute(torch.from_numpy(mom).cuda(), AS).cpu().numpy()
     assert np.max(np.abs(bg / team - 1)) < 1e-10
+
+
+@pytest.mark.parametrize('name,nevt,seed', [('gg_ttxgg', 64 * 3 + 5, 1006), ('gg_ttxgg', 1, 9),
+                                            ('gg_ttxgg', 8 * 512 + 3, 1002), ('gg_ttxggg', 3, 1003)])
+def test_bg_recycling_vs_oracle(binding, name, nevt, seed):
+    _say(f'case bg recycling {name} nevt={nevt} seed={seed}')
+    npar = NPAR8[name]
+    mom = rambo.generate(npar, nevt, seed)
+    gpu, _ = _bg(binding, name, mom, variant=3)
+    assert_parity(gpu, mom, npar)
+
+
+def test_bg_recycling_ggttggg_golden_and_mixed(binding):
+    _say('case bg recycling gg_ttxggg golden 197 events; split FP16 / BF16 colour sums')
+    g = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_first197.npz'))
+    gpu, _ = _bg(binding, 'gg_ttxggg', g['momenta'], variant=3)
+    assert_parity(gpu, g['momenta'], 7, me64=g['me'], me_ext=g['me_ext'])
+    for mode, bound in ((1, 1e-5), (2, 2e-4)):
+        mixed, _ = _bg(binding, 'gg_ttxggg', g['momenta'], mode, variant=3)
+        rel = np.abs(mixed / g['me'] - 1)
+        _say(f'  mode {mode}: max rel err {rel.max():.3e}')
+        assert rel.max() < bound
+
+
+def test_bg_recycling_ggttggg_full_size(binding):
+    _say('case bg recycling gg_ttxggg 262144 events (the full workload): sampled golden events, '
+         'every event against the row kernel')
+    s = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_n262144_sampled.npz'))
+    mom = rambo.generate(7, 262144, 1003)
+    rec, dt = _bg(binding, 'gg_ttxggg', mom, variant=3)
+    _say(f'  {262144 / dt:.0f} ME/s (first call, including set-up)')
+    assert np.all(np.isfinite(rec)) and np.all(rec > 0)
+    idx = s['index']
+    assert_parity(rec[idx], mom[idx], 7, me64=s['me'], me_ext=s['me_ext'])
+    row, _ = _bg(binding, 'gg_ttxggg', mom, variant=0)
+    rel = np.abs(rec / row - 1)
+    _say(f'  recycling vs row kernel, all events: max rel {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}')
+    assert rel.max() < 1e-11
