@@ -5,8 +5,8 @@ from the HIP path.  Run from the repository root:
 
     python tests/golden/make_golden.py [ggttggg] [ggttgggg] [sde_ggttggg] [wide_c1] ...
 
-(the wide_* sets run the oracle on every host core; wide_c2 takes about an hour
-of eight cores)
+(the wide_* sets run the oracle on every host core; wide_c2 takes about ten
+minutes of eight cores, wide_c4a about four minutes per eight events)
 """
 import os
 import sys
@@ -100,10 +100,10 @@ def wide_c1():
 
 def wide_c2():
     # g g -> t tbar g g g, the first 16384 events of the 262144-event workload (seed
-    # 1003), FP64 and extended precision
+    # 1003), FP64 oracle values (the tests take extended-precision values of the few
+    # events they need to adjudicate from the oracle at run time)
     mom = rambo.generate(7, 16384, 1003)
-    _save('gg_ttxggg_seed1003_first16384.npz', me=pooled_values(7, mom),
-          me_ext=pooled_values(7, mom, ext=True, chunk=64))
+    _save('gg_ttxggg_seed1003_first16384.npz', me=pooled_values(7, mom))
 
 
 def wide_c4a(n=256):

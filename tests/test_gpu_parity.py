@@ -364,4 +364,14 @@ def test_autotune_keeps_results(binding):
     _say(f'  chosen {best}')
     assert best['persistent'] in (0, 1)
     got = m.compute(d, AS).cpu().numpy()
-    assert np.max(np.abs(got / ref - 1)) < 1e-14
+    # the chosen executor may run another algorithm than the default one-lane code
+    # (the Berends-Giele recursion, each candidate held to the oracle on its own in
+    # test_gpu_tune): the same |M|^2 to rounding, and to the oracle's tolerance
+    if best['executor'] == binding.ME_EXEC_LANE:
+        assert np.max(np.abs(got / ref - 1)) < 1e-14
+    else:
+        rel = np.abs(got / ref - 1)
+        far = np.where(rel > 1e-12)[0]
+        _say(f'  vs the default executor: max rel {rel.max():.2e}, {len(far)} events above 1e-12')
+        sel = np.union1d(np.arange(64), far)
+        assert_parity(got[sel], mom[sel], 6)
