@@ -110,7 +110,7 @@ def binding_resource(traffic, ms_per_launch, achieved_tflops):
             'resource': 'HBM (register-spill traffic)' if hbm > alu else 'FP64 vector ALU'}
 
 
-def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None):
+def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None, bg_variant=0):
     """Mixed colour sum + surrogate two-stage unweighting of the same workload.
 
     The surrogate is trained on separate events labelled by the exact path;
@@ -135,8 +135,10 @@ def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None)
         pipe = SurrogatePipeline(process, width=256, depth=4, seed=11, alpha_s=args.alpha_s,
                                  colorsum_mode=exact_mode)
     if executor is not None:
-        # the exact path on the executor the FP64 run was tuned to
+        # the exact path on the executor (and Berends-Giele kernel) the FP64 run was tuned to
         pipe.me.me_set_executor(executor)
+        if executor == binding.ME_EXEC_BG:
+            pipe.me.me_set_bg(bg_variant)
     train = torch.from_numpy(rambo.generate(npar, args.sur_train, 2001)).cuda()
     t0 = time.perf_counter()
     hist = pipe.fit(train, epochs=args.sur_epochs, batch=4096, lr=2e-3, lr_final=1e-4)
@@ -338,8 +340,8 @@ def main():
     executor = (tuned or {}).get('executor', 0)
     bg_variant = (tuned or {}).get('bg_variant', 0)
     kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>',
-             3: f'bg{"h" if bg_variant == 3 else ""}_kernel<{NPAR[process] - 2}>'}.get(executor,
-                                                                                    f'me_kernel<{process}>')
+             3: f'bg{"h" if bg_variant >= 3 else ""}_kernel<{NPAR[process] - 2}>'}.get(executor,
+                                                                                     f'me_kernel<{process}>')
     ncol = {'gg_ttx': 2, 'gg_ttxg': 6, 'gg_ttxgg': 24, 'gg_ttxggg': 120, 'gg_ttxgggg': 720}[process]
     cname = (f'colour_f64_tri_kernel<{ncol}>' if ncol > 128 else f'colour_f64_kernel<{ncol}>') \
         if executor in (2, 3) else 'colour_mfma_kernel'
@@ -353,7 +355,7 @@ def main():
                for k, name in ((binding.ME_KT_DIAGRAM, kname),
                                (binding.ME_KT_FLOWS, f'flows_kernel<{process}>'),
                                (binding.ME_KT_COLOUR, cname),
-                               (binding.ME_KT_REDUCE, 'reduce_rows_kernel' if executor == 3 and bg_variant == 3
+                               (binding.ME_KT_REDUCE, 'reduce_rows_kernel' if executor == 3 and bg_variant >= 3
                                 else 'reduce_chunks_kernel')) if launches[k]}
     line = {
         'metric': 'ME evals/s', 'value': value, 'unit': 'ME evals/s', 'n_gpus': 1,
@@ -381,7 +383,7 @@ def main():
         line['mixed'] = mixed
     if args.surrogate:
         line['surrogate'] = surrogate_leg(args, process, nevt, mom, dmom, binding, rambo,
-                                          (tuned or {}).get('executor'))
+                                          (tuned or {}).get('executor'), (tuned or {}).get('bg_variant', 0))
     if args.batch:
         print('# bench uneven batch', file=sys.stderr, flush=True)
         line['uneven_batch'] = batch_leg(args, binding, rambo)

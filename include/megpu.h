@@ -307,7 +307,8 @@ int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
  * receives the ME_TUNE_FIELDS integers (persistent, waves_per_simd, hel_per_item,
  * target_waves, executor, split waves per SIMD, flow chunk, split rounds, colour
  * grid, Berends-Giele launch shape; 0 in the last five = default).  The
- * Berends-Giele executor is a candidate in its three launch shapes. */
+ * Berends-Giele executor is a candidate in its three launch shapes and, for four
+ * and five gluons, with helicity recycling (variants 3 and 4). */
 #define ME_TUNE_FIELDS 10
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
@@ -325,9 +326,11 @@ int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid);
  * threads per workgroup, 1 = half of both, 2 = twice both; 3 = helicity
  * recycling (four and five gluons: one workgroup per event(s), every current and
  * row spinor formed once per helicity assignment of its own particles, the full
- * orderings walked in rotation cycles).  See me_autotune.  ME_EINVAL for other
- * values, and for 3 on other processes.  Results do not depend on it beyond
- * rounding. */
+ * orderings walked in rotation cycles); 4 = helicity recycling with the FP64 colour
+ * form of each row computed by the same workgroup on the matrix cores (no separate
+ * colour kernel; in the matrix-core colour-sum modes 4 behaves as 3).  See
+ * me_autotune.  ME_EINVAL for other values, and for 3 and 4 on other processes.
+ * Results do not depend on it beyond rounding. */
 int me_set_bg(me_handle h, int variant);
 
 /* Uneven multi-process batch in one persistent launch (the paper evaluates one

@@ -225,7 +225,7 @@ struct me_ctx {
   int split_fchunk = 0;       // flows kernel: group sums per LDS chunk (8, 16, 32)
   int split_rounds = 0;       // events per chunk as whole rounds of group-sum waves (0: as many as fit)
   int colour_grid = 0;        // workgroups of the FP64 colour kernel
-  int bg_variant = 0;         // Berends-Giele kernel: launch shape 0, 1, 2; 3 = helicity recycling
+  int bg_variant = 0;         // Berends-Giele kernel: launch shape 0, 1, 2; 3 = helicity recycling; 4 = the same, FP64 colour form fused
   bool tuned = false;         // me_autotune has run (or found its configuration in the cache)
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
@@ -939,22 +939,30 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       a.variant = h->bg_variant;
       if (h->d_bg_cyc)
         a.cyc = me::BgCycles{h->d_bg_cyc, h->d_bg_cyc + h->n_bg_cyc, h->d_bg_cyc + h->n_bg_cyc + h->n_bg_slot};
+      // variant 4 in FP64 mode: the recursion kernel forms the colour form of its rows
+      const bool fused = fp64 && h->bg_variant == 4;
+      if (fused) {
+        a.cft = h->d_cf64_tri;
+        a.rowout = h->d_partial;
+      }
       KernelMark kd(h, ME_KT_DIAGRAM, s);
       hipError_t e = h->bg->launch(a);
       if (e != hipSuccess) return hip_fail(e, "Berends-Giele kernel launch");
       kd.done();
-      KernelMark kc(h, ME_KT_COLOUR, s);
-      if (fp64) {
-        e = h->bg->colour64(h->d_sums, n * nhel, h->bg->colour_tri ? h->d_cf64_tri : h->d_cf64, h->d_partial, s);
-      } else {
-        me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
-                          h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
-        e = h->desc->colour(ca);
+      if (!fused) {
+        KernelMark kc(h, ME_KT_COLOUR, s);
+        if (fp64) {
+          e = h->bg->colour64(h->d_sums, n * nhel, h->bg->colour_tri ? h->d_cf64_tri : h->d_cf64, h->d_partial, s);
+        } else {
+          me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
+                            h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
+          e = h->desc->colour(ca);
+        }
+        if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+        kc.done();
       }
-      if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
-      kc.done();
       KernelMark kr(h, ME_KT_REDUCE, s);
-      if (h->bg_variant == 3)   // event-major rows
+      if (h->bg_variant >= 3)   // event-major rows
         hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
                            nhel, n, scale, out_me2 + off);
       else
@@ -1512,8 +1520,8 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
 int me_set_bg(me_handle h, int variant) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (variant < 0 || variant > 3) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
-  if (variant == 3 && !h->bg->recycle)
+  if (variant < 0 || variant > 4) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
+  if (variant >= 3 && !h->bg->recycle)
     return fail(ME_EINVAL, "helicity recycling is built for four and five gluons only");
   h->bg_variant = variant;
   drop_graph(h);
@@ -1669,7 +1677,8 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
     cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_TEAM, 0, 0, 0, 0, 0}});
   }
   for (int v : {0, 1, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
-  if (h->bg->recycle) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, 3}});
+  if (h->bg->recycle)
+    for (int v : {3, 4}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
   if (h->desc->split) {
     // group-sum kernel variants (waves per SIMD), flow chunk sizes and event chunks
     // (as many whole rounds of group-sum waves as fit the scratch, or two rounds)

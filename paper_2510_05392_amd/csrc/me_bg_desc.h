@@ -22,7 +22,7 @@ struct BgCycles {
 };
 
 // One chunk of rows: row = k n + e (good helicity k, event e of the chunk) for
-// variants 0 .. 2, row = e nhel + k for variant 3 (helicity recycling).
+// variants 0 .. 2, row = e nhel + k for variants 3 and 4 (helicity recycling).
 struct BgArgs {
   const double* mom;     // device, [n][npar][4] (the chunk's events)
   int64_t n;
@@ -35,8 +35,11 @@ struct BgArgs {
   const double* alphas;  // device, per-event alpha_s of the chunk, or nullptr
   double* jt;            // device, dual amplitudes [2 NCOL][n nhel]
   hipStream_t stream;
-  int variant = 0;       // 0, 1, 2: one row per item, launch shapes; 3: helicity recycling
-  BgCycles cyc{nullptr, nullptr, nullptr};   // variant 3 only
+  int variant = 0;       // 0, 1, 2: one row per item, launch shapes; 3: helicity recycling;
+                         // 4: helicity recycling with the FP64 colour form fused
+  BgCycles cyc{nullptr, nullptr, nullptr};   // variants 3 and 4 only
+  const double* cft = nullptr;   // variant 4: block-triangular FP64 colour matrix [16 MB][4 KS]
+  double* rowout = nullptr;      // variant 4: colour form of every row [n nhel] (nullptr: jt only)
 };
 
 using BgLauncher = hipError_t (*)(const BgArgs&);

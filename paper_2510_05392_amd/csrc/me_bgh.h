@@ -18,6 +18,12 @@
 // current J(sigma), the row spinors R(sigma[:N-2]) and R(sigma[:N-1]) of each top
 // helicity, W = sum_{k>=1} R(sigma[:k]) (i g gamma.J(sigma[k:])), and the
 // amplitudes Q.J(sigma) + W v of the four quark helicity pairs.
+//
+// With the colour form fused (launch variant 4, FP64 mode) the workgroup then reads
+// its own rows' dual amplitudes back and forms Re(J^H CF J) of each row on the FP64
+// matrix cores, the block-triangular colour matrix staged in the LDS the frames
+// held; the separate colour kernel and its launch go away, and the matrix-core work
+// of one workgroup overlaps the vector work of the others on the same compute unit.
 #pragma once
 #include "me_bg.h"
 
@@ -409,15 +415,105 @@ __device__ __forceinline__ void bgh_krow(const int* hrow, int gh, int* krow) {
 }
 
 #ifdef __HIPCC__
+typedef double bgh_f64x4 __attribute__((ext_vector_type(4)));
+
+// Block-triangular colour matrix staged in LDS as FP32 (exact: integer entries
+// below 2^24): the 16 x 16 blocks (mb, kb) with kb >= mb, block-row major, rows
+// BGH_CS floats apart (16 + 4 against bank conflicts).
+constexpr int BGH_CS = 20;
+template <int NCOL>
+struct BghColour {
+  static constexpr int KS = (NCOL + 3) / 4;     // K steps of 4 flows
+  static constexpr int KP = 4 * KS;             // row length of the FP64 matrix
+  static constexpr int MB = (NCOL + 15) / 16;   // 16-flow blocks
+  static constexpr int NBLK = MB * (MB + 1) / 2;
+  static constexpr int FLOATS = NBLK * 16 * BGH_CS;
+  static constexpr int blk(int mb, int kb) { return mb * MB - mb * (mb - 1) / 2 + (kb - mb); }
+};
+
+// FP64 colour form of the rows r0 .. r0 + nr - 1 of jt [2 NCOL][rows] into
+// out[row] = sum_ik CF'[i][k] (A_i A_k + B_i B_k), J = A + iB, CF' the block-
+// triangular matrix (cft: [16 MB][KP] FP64, diagonal blocks CF, blocks above 2 CF,
+// zero below; same quadratic form as CF).  Every thread of the workgroup takes
+// part; cfs holds at least BghColour<NCOL>::FLOATS floats.  One wave per tile of 8
+// rows: v_mfma_f64_16x16x4f64 with the matrix block as A (lane l: row l % 16, K
+// index l / 16) and the real and imaginary parts of the 8 rows as the 16 columns
+// of B; D[i][j] sits in lane j + 16 (i % 4), element i / 4.  The column blocks kb
+// are taken from the last to the first: block row kb then has all its products,
+// and its row dots use the B operands just loaded for block kb (the flows of a
+// lane's B elements are those of its D elements), so each operand is read once.
+template <int NCOL, int THREADS>
+__device__ __forceinline__ void bgh_colour_rows(const double* __restrict__ jt, int64_t rows, int64_t r0, int nr,
+                                                const double* __restrict__ cft, float* cfs,
+                                                double* __restrict__ out) {
+  using C = BghColour<NCOL>;
+  constexpr int KS = C::KS, MB = C::MB;
+  for (int i = threadIdx.x; i < C::NBLK * 256; i += THREADS) {
+    const int b = i >> 8, e = i & 255, r = e >> 4, c = e & 15;
+    int mb = 0;
+    while (mb + 1 < MB && C::blk(mb + 1, mb + 1) <= b) ++mb;
+    const int kb = mb + (b - C::blk(mb, mb));
+    const int col = 16 * kb + c;
+    cfs[b * 16 * BGH_CS + r * BGH_CS + c] = col < C::KP ? (float)cft[(int64_t)(16 * mb + r) * C::KP + col] : 0.0f;
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  const int j = l & 15, kq = l >> 4, part = j >> 3;
+  const int ntile = (nr + 7) >> 3;
+  for (int tile = threadIdx.x >> 6; tile < ntile; tile += THREADS / 64) {
+    // the matrix operands are read from LDS in each tile: kept out of registers
+    // across tiles (hoisted, the 128 of them would not fit)
+    asm volatile("" ::: "memory");
+    const int rr = 8 * tile + (j & 7);
+    const bool valid = rr < nr;
+    const double* x = jt + (int64_t)(part + 2 * kq) * rows + r0 + (valid ? rr : 0);
+    bgh_f64x4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = bgh_f64x4{0.0, 0.0, 0.0, 0.0};
+    double s = 0.0;
+#pragma unroll
+    for (int kb = MB - 1; kb >= 0; --kb) {
+      double b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ks = 4 * kb + q;
+        b[q] = (ks < KS && 4 * ks + kq < NCOL && valid) ? x[(int64_t)(8 * ks) * rows] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (4 * kb + q >= KS) continue;
+#pragma unroll
+        for (int mb = 0; mb <= kb; ++mb) {
+          const double a = (double)cfs[C::blk(mb, kb) * 16 * BGH_CS + j * BGH_CS + 4 * q + kq];
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[q], acc[mb], 0, 0, 0);
+        }
+      }
+      // row dots of block row kb: D[i][j], i = 16 kb + 4 v + kq, X[i][j] = b[v]
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (4 * kb + v < KS) s += b[v] * acc[kb][v];
+    }
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    s += __shfl_xor(s, 8);
+    if (l < 8 && valid) out[r0 + rr] = s;
+  }
+}
+
 // One workgroup: events blockIdx.x EV .. + EV - 1 of the chunk, all good
 // helicities; rows event-major (row = e nhel + k).  Levels: set-up, then for
 // L = 2 .. N-2 the currents of length L with the row spinors of length L - 1,
 // then the cycle items; barriers between levels.  Dynamic LDS: the EV frames,
-// the segment masks of every cycle, each thread's item table.
-template <int N, int EV, int THREADS>
-__global__ void __launch_bounds__(THREADS) bgh_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt,
+// the segment masks of every cycle, each thread's item table.  With COL the
+// workgroup then forms the FP64 colour form of its rows into rowout (cft: the
+// block-triangular colour matrix), the staged matrix taking the frames' place.
+// Two workgroups fit a compute unit's LDS: the registers are held to two waves
+// per SIMD.
+template <int N, int EV, int THREADS, bool COL>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2))) bgh_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt,
                                                       const int* __restrict__ hels, int nhel, BgTables t, BgCycles cy,
-                                                      const double* __restrict__ alphas, double* __restrict__ jt) {
+                                                      const double* __restrict__ alphas, double* __restrict__ jt,
+                                                      const double* __restrict__ cft, double* __restrict__ rowout) {
   using S = BgShape<N>;
   using H = BghShape<N>;
   constexpr int NPAR = N + 2;
@@ -466,6 +562,14 @@ __global__ void __launch_bounds__(THREADS) bgh_kernel(const double* __restrict__
     const BghItem<N> item{tab, THREADS, sm + z * N * N};
     bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, (e0 + ev) * nhel);
   }
+  if constexpr (COL) {
+    static_assert(BghColour<S::NCOL>::FLOATS * sizeof(float) <= EV * H::FRAME * sizeof(double),
+                  "the staged colour matrix must fit in the frames");
+    // every amplitude of this workgroup's rows is stored (workgroup-scope fence and
+    // barrier) and the frames are no longer read
+    __syncthreads();
+    bgh_colour_rows<S::NCOL, THREADS>(jt, rows, e0 * nhel, nev * nhel, cft, reinterpret_cast<float*>(lds), rowout);
+  }
 }
 
 // Events per workgroup and threads: the frames of EV events within about 56 KB.
@@ -473,31 +577,34 @@ template <int N> struct BghLaunchShape;
 template <> struct BghLaunchShape<4> { static constexpr int EV = 8, THREADS = 256; };
 template <> struct BghLaunchShape<5> { static constexpr int EV = 1, THREADS = 256; };
 
-template <int N>
+template <int N, bool COL>
 hipError_t launch_bgh(const BgArgs& a) {
   using H = BghShape<N>;
   constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
   const size_t lds = (size_t)EV * H::FRAME * sizeof(double) + ((H::NCYC * N * N + 15) & ~15) +
                      (size_t)N * (H::LC + H::LR) * THREADS * sizeof(uint16_t);
-  static const hipError_t attr = hipFuncSetAttribute((const void*)bgh_kernel<N, EV, THREADS>,
+  static const hipError_t attr = hipFuncSetAttribute((const void*)bgh_kernel<N, EV, THREADS, COL>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
   if (!a.cyc.seg) return hipErrorInvalidValue;
+  if (COL && (!a.cft || !a.rowout)) return hipErrorInvalidValue;
   if (a.n == 0 || a.nhel == 0) return hipSuccess;
   const BgTables t{a.sub, a.mask, a.last};
-  hipLaunchKernelGGL((bgh_kernel<N, EV, THREADS>), dim3((unsigned)((a.n + EV - 1) / EV)), dim3(THREADS), lds,
-                     a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt);
+  hipLaunchKernelGGL((bgh_kernel<N, EV, THREADS, COL>), dim3((unsigned)((a.n + EV - 1) / EV)), dim3(THREADS), lds,
+                     a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt, a.cft, a.rowout);
   return hipGetLastError();
 }
 
 // Launch of the executor's kernel in the chosen variant (3: helicity recycling,
-// built for four and five gluons).
+// 4: the same with the FP64 colour form fused when rowout is given; built for four
+// and five gluons).
 template <int N>
 hipError_t launch_bg(const BgArgs& a) {
   if constexpr (N == 4 || N == 5) {
-    if (a.variant == 3) return launch_bgh<N>(a);
+    if (a.variant == 4 && a.rowout) return launch_bgh<N, true>(a);
+    if (a.variant == 3 || a.variant == 4) return launch_bgh<N, false>(a);
   } else {
-    if (a.variant == 3) return hipErrorInvalidValue;
+    if (a.variant == 3 || a.variant == 4) return hipErrorInvalidValue;
   }
   if (a.variant == 1) return launch_bg_v<N, 1>(a);
   if (a.variant == 2) return launch_bg_v<N, 2>(a);

@@ -187,15 +187,22 @@ def diagram_kernel(name, executor, bg_variant=0):
     own, the recursion alone for the Berends-Giele executor (executor 3), whose
     colour form is a kernel of its own; with helicity recycling (launch variant 3)
     the kernel's flops per event divided by the 2^npar helicity rows (every helicity
-    of these processes is good)."""
+    of these processes is good), and with the FP64 colour form fused into it
+    (variant 4) the triangular colour form of each row on top (algorithmic count;
+    the matrix cores execute the block-triangular product)."""
     if executor == 2:
         return group_sums_flops(name) + QUARK_BRANCH_MEAN
     if executor == 3:
         from .gen import codegen
         npar = codegen.PROCESS_NPAR[name]
-        if bg_variant == 3:
+        if bg_variant in (3, 4):
             # per event over every helicity, shared out over the 2^npar rows
-            return (bgh_event(npar - 2)['total'] + 6 * QUARK_BRANCH_MEAN) / 2 ** npar
+            f = (bgh_event(npar - 2)['total'] + 6 * QUARK_BRANCH_MEAN) / 2 ** npar
+            if bg_variant == 4:
+                from .gen.colour import colour_matrix
+                cf, _ = colour_matrix(npar - 2)
+                f += colour_sum_flops(cf)
+            return f
         return bg_row(npar - 2)['total'] + QUARK_BRANCH_MEAN
     return per_event_helicity(name) + QUARK_BRANCH_MEAN
 

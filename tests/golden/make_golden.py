@@ -123,6 +123,13 @@ def wide_c4b():
     _save('batch_first1024.npz', **out)
 
 
+def c3_labels():
+    # the surrogate's training labels: the first 4096 events of the 2097152-event
+    # gg -> t tbar g g training sample (seed 2001), FP64 oracle values
+    mom = rambo.generate(6, 4096, 2001)
+    _save('gg_ttxgg_seed2001_first4096.npz', me=pooled_values(6, mom, chunk=256))
+
+
 def _kappa_chunk(args):
     """Condition number of the colour sum of each event: with J = A + iB per helicity,
     kappa = sum_h (|A|^T |C| |A| + |B|^T |C| |B|) / sum_h (A^T C A + B^T C B)."""
@@ -161,7 +168,8 @@ def kappa():
 
 
 GENERATORS = {'kappa': kappa, 'ggttggg': ggttggg, 'ggttgggg': ggttgggg, 'sde_ggttggg': sde_ggttggg,
-              'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4b': wide_c4b}
+              'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4b': wide_c4b,
+              'c3_labels': c3_labels}
 
 
 def main(which):

@@ -2,8 +2,8 @@
 process, FP64 within 1e-12 per event (extended-precision adjudication), the
 split-precision colour sums within their bound, gg -> tt gggg at its full
 32768-event size on the stored oracle values, and the helicity-recycling kernel
-(launch variant 3) on gg -> tt gg and gg -> tt ggg, up to the full 262144-event
-workload."""
+(launch variant 3, and 4 with the FP64 colour form fused into it) on gg -> tt gg
+and gg -> tt ggg, up to the full 262144-event workload."""
 import os
 import time
 
@@ -96,34 +96,51 @@ def test_bg_matches_team_program_ggttgggg(binding):
     assert np.max(np.abs(bg / team - 1)) < 1e-10
 
 
+@pytest.mark.parametrize('variant', [3, 4])
 @pytest.mark.parametrize('name,nevt,seed', [('gg_ttxgg', 64 * 3 + 5, 1006), ('gg_ttxgg', 1, 9),
-                                            ('gg_ttxgg', 8 * 512 + 3, 1002), ('gg_ttxggg', 3, 1003)])
-def test_bg_recycling_vs_oracle(binding, name, nevt, seed):
-    _say(f'case bg recycling {name} nevt={nevt} seed={seed}')
+                                            ('gg_ttxgg', 8 * 512 + 3, 1002), ('gg_ttxggg', 3, 1003),
+                                            ('gg_ttxggg', 130, 1007)])
+def test_bg_recycling_vs_oracle(binding, name, nevt, seed, variant):
+    _say(f'case bg recycling {name} nevt={nevt} seed={seed} variant={variant}')
     npar = NPAR8[name]
     mom = rambo.generate(npar, nevt, seed)
-    gpu, _ = _bg(binding, name, mom, variant=3)
+    gpu, _ = _bg(binding, name, mom, variant=variant)
     assert_parity(gpu, mom, npar)
 
 
-def test_bg_recycling_ggttggg_golden_and_mixed(binding):
-    _say('case bg recycling gg_ttxggg golden 197 events; split FP16 / BF16 colour sums')
+@pytest.mark.parametrize('variant', [3, 4])
+def test_bg_recycling_ggttggg_golden_and_mixed(binding, variant):
+    _say(f'case bg recycling gg_ttxggg golden 197 events, variant {variant}; split FP16 / BF16 colour sums')
     g = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_first197.npz'))
-    gpu, _ = _bg(binding, 'gg_ttxggg', g['momenta'], variant=3)
+    gpu, _ = _bg(binding, 'gg_ttxggg', g['momenta'], variant=variant)
     assert_parity(gpu, g['momenta'], 7, me64=g['me'], me_ext=g['me_ext'])
     for mode, bound in ((1, 1e-5), (2, 2e-4)):
-        mixed, _ = _bg(binding, 'gg_ttxggg', g['momenta'], mode, variant=3)
+        mixed, _ = _bg(binding, 'gg_ttxggg', g['momenta'], mode, variant=variant)
         rel = np.abs(mixed / g['me'] - 1)
         _say(f'  mode {mode}: max rel err {rel.max():.3e}')
         assert rel.max() < bound
 
 
-def test_bg_recycling_ggttggg_full_size(binding):
-    _say('case bg recycling gg_ttxggg 262144 events (the full workload): sampled golden events, '
-         'every event against the row kernel')
+def test_bg_fused_colour_matches_colour_kernel(binding):
+    _say('case bg recycling: fused FP64 colour form (variant 4) against the colour kernel (variant 3)')
+    for name, npar, nevt, seed in (('gg_ttxgg', 6, 8 * 300 + 5, 31), ('gg_ttxggg', 7, 515, 32)):
+        mom = rambo.generate(npar, nevt, seed)
+        a, _ = _bg(binding, name, mom, variant=3)
+        b, _ = _bg(binding, name, mom, variant=4)
+        rel = np.abs(b / a - 1)
+        _say(f'  {name}: max rel {rel.max():.3e}')
+        # the same products summed in another order (block-triangular matrix, row
+        # dots per block row)
+        assert rel.max() < 1e-13
+
+
+@pytest.mark.parametrize('variant', [3, 4])
+def test_bg_recycling_ggttggg_full_size(binding, variant):
+    _say(f'case bg recycling gg_ttxggg 262144 events (the full workload), variant {variant}: sampled golden '
+         'events, every event against the row kernel')
     s = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_n262144_sampled.npz'))
     mom = rambo.generate(7, 262144, 1003)
-    rec, dt = _bg(binding, 'gg_ttxggg', mom, variant=3)
+    rec, dt = _bg(binding, 'gg_ttxggg', mom, variant=variant)
     _say(f'  {262144 / dt:.0f} ME/s (first call, including set-up)')
     assert np.all(np.isfinite(rec)) and np.all(rec > 0)
     idx = s['index']

@@ -345,3 +345,57 @@ def test_maxima_quantiles_onestage_summary_vs_numpy(binding, n, q):
     rms, worst = binding.me_sur_log_error(d(y), d(me2), n, ymean, ystd)
     dl = y.astype(np.float64) * ystd + ymean - np.log(me2)
     assert abs(rms / np.sqrt(np.mean(dl ** 2)) - 1) < 1e-12 and abs(worst / np.abs(dl).max() - 1) < 1e-14
+
+
+def test_surrogate_at_configured_size(binding):
+    """The surrogate configuration on gg -> t tbar g g at its full size: training
+    on 2^21 events (seed 2001) labelled by the exact path (split-BF16 colour sum),
+    the first 4096 labels against the oracle within that mode's stated bound, and
+    two-stage unweighting of 2^20 events (seed 2002), unbiased against the exact
+    weights of the same events (chi^2 of an observable) with most exact calls
+    saved."""
+    import os
+
+    from paper_2510_05392_amd.surrogate import SurrogatePipeline
+    from test_gpu_parity import GOLDEN
+    _say('case surrogate at its configured size: 2097152 training events, 1048576 unweighted')
+    pipe = SurrogatePipeline('gg_ttxgg', width=256, depth=4, seed=11, colorsum_mode=binding.ME_CS_BF16X2)
+    train = torch.from_numpy(rambo.generate(6, 2097152, 2001)).cuda()
+    labels = pipe.exact(train[:4096]).cpu().numpy()
+    g = np.load(os.path.join(GOLDEN, 'gg_ttxgg_seed2001_first4096.npz'))
+    rel = np.abs(labels / g['me'] - 1)
+    _say(f'  labels vs oracle (first 4096): max rel {rel.max():.2e}')
+    assert rel.max() < 2e-4
+    hist = pipe.fit(train, epochs=4, batch=4096, lr=2e-3, lr_final=1e-4)
+    del train
+    _say(f'  training mse per epoch: {[round(h, 5) for h in hist]}')
+    assert hist[-1] < hist[0]
+    val = torch.from_numpy(rambo.generate(6, 65536, 2003)).cuda()
+    rms, worst = pipe.log_error(val)
+    _say(f'  validation RMS log-error {rms:.3f} (target spread {pipe.ystd:.3f})')
+    assert rms < 0.25 * pipe.ystd
+    n = 1048576
+    mom, wps = rambo.generate(6, n, 2002, return_weights=True)
+    dmom, dw = torch.from_numpy(mom).cuda(), torch.from_numpy(wps).cuda()
+    calm, calw = rambo.generate(6, 65536, 2005, return_weights=True)
+    dcal, dcw = torch.from_numpy(calm).cuda(), torch.from_numpy(calw).cuda()
+    what_max, x_max = pipe.calibrate(dcal, dcw, quantile=0.99)
+    gen = torch.Generator(device='cuda').manual_seed(21)
+    r1 = torch.rand(n, dtype=torch.float64, device='cuda', generator=gen)
+    r2 = torch.rand(n, dtype=torch.float64, device='cuda', generator=gen)
+    two = pipe.unweight(dmom, dw, r1, r2, what_max, x_max)
+    saved = 1 - two['stage1'] / n
+    _say(f"  stage-1 events {two['stage1']} (exact calls saved {saved:.1%}), accepted {two['accepted']}, "
+         f"overweights {two['overweight']}, ESS {two['ess']:.1f}")
+    assert saved > 0.9
+    w_exact = (pipe.exact(dmom) * dw).cpu().numpy()
+    obs = 0.5 * np.log((mom[:, 2, 0] + mom[:, 2, 3]) / (mom[:, 2, 0] - mom[:, 2, 3]))
+    edges = np.quantile(obs, np.linspace(0, 1, 9))
+    expect = np.histogram(obs, edges, weights=w_exact)[0]
+    expect = expect / expect.sum()
+    sel, res = obs[two['index'].cpu().numpy()], two['resid'].cpu().numpy()
+    got = np.histogram(sel, edges, weights=res)[0]
+    var = np.histogram(sel, edges, weights=res ** 2)[0]
+    chi2 = float((((got - got.sum() * expect) ** 2) / np.maximum(var, 1.0)).sum())
+    _say(f'  chi2 of the two-stage sample vs exact-weighted distribution: {chi2:.1f} (8 bins)')
+    assert chi2 < 30

@@ -37,7 +37,7 @@ def test_every_candidate_matches_the_oracle(binding):
             (1, 1, 1, 4096), (1, 2, 1, 4096)]
     cases = [('lane',) + c for c in lane] + [('team', 0, 1, 0, tw) for tw in (1024, 262144, 1048576)]
     cases += [('split', w, f, r) for w in (1, 2) for f in (8, 16, 32) for r in (0, 2)]
-    cases += [('bg', v) for v in (0, 1, 2, 3)]
+    cases += [('bg', v) for v in (0, 1, 2, 3, 4)]
     for c in cases:
         m = binding.MatrixElement('gg_ttxggg')
         if c[0] == 'lane':
@@ -68,9 +68,10 @@ def test_every_candidate_matches_the_oracle(binding):
     with pytest.raises(binding.MeError):
         binding.MatrixElement('gg_ttxgggg').me_set_split(1, 16, 0, 0)
     with pytest.raises(binding.MeError):
-        binding.MatrixElement('gg_ttxggg').me_set_bg(4)
-    with pytest.raises(binding.MeError):
-        binding.MatrixElement('gg_ttxgggg').me_set_bg(3)   # helicity recycling: four and five gluons
+        binding.MatrixElement('gg_ttxggg').me_set_bg(5)
+    for v in (3, 4):
+        with pytest.raises(binding.MeError):
+            binding.MatrixElement('gg_ttxgggg').me_set_bg(v)   # helicity recycling: four and five gluons
 
 
 def test_autotune_cache_and_parameter(binding, tmp_path, monkeypatch):

@@ -7,7 +7,8 @@ configurations the benchmark uses.
                    Berends-Giele kernel, and the split FP16 / BF16 colour sums;
   gg -> tt ggg     the first 16384 events of the 262144-event workload (seed
                    1003), FP64 and split FP16 on the split executor and on the
-                   helicity-recycling Berends-Giele kernel;
+                   helicity-recycling Berends-Giele kernel (with and without the
+                   fused FP64 colour form);
   gg -> tt gggg    the first 256 events of the 32768-event workload (seed 1005),
                    FP64 and split FP16 (team program);
   uneven batch     the first 1024 events of each segment, one persistent launch.
@@ -82,7 +83,7 @@ def _check_mixed(name, mode, gpu, ref, kappa_idx, kappa):
     assert rel.max() <= 10 * b.max(), rel.max()
 
 
-@pytest.mark.parametrize('executor,variant', [(0, None), (2, None), (3, 3)])
+@pytest.mark.parametrize('executor,variant', [(0, None), (2, None), (3, 3), (3, 4)])
 def test_ggttgg_every_event_fp64(binding, executor, variant):
     _say(f'case wide gg_ttxgg all 524288 events, executor {executor}, variant {variant}')
     g = _golden('gg_ttxgg_seed1002_n524288.npz')
@@ -114,7 +115,7 @@ def test_ggtt_mixed_bound(binding):
         _check_mixed('gg_ttx', mode, gpu, ref, np.arange(len(k)), k)
 
 
-@pytest.mark.parametrize('executor,variant', [(2, None), (3, 3)])
+@pytest.mark.parametrize('executor,variant', [(2, None), (3, 3), (3, 4)])
 def test_ggttggg_first16384(binding, executor, variant):
     _say(f'case wide gg_ttxggg first 16384 of 262144 events (executor {executor}, variant {variant}), '
          'FP64 and split FP16')
