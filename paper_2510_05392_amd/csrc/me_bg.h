@@ -100,25 +100,25 @@ __device__ __forceinline__ void bg_v3(const cx* a, const double* pa, const cx* b
   const cx c1 = rdot(kma, b);
   const cx c2 = vdot(a, b);
   const cx c3 = rdot(pbk, a);
+  // accumulated term by term (fused multiply-adds into acc)
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    cx v = a[u] * c1;
+    cx v = fma(acc[u], a[u], c1);
     v = fma(v, b[u], c3);
-    v = v + pamb[u] * c2;
-    acc[u] = acc[u] + v;
+    acc[u] = cx{v.r + pamb[u] * c2.r, v.i + pamb[u] * c2.i};
   }
 }
 
 // acc += W(a, b, c) (four-gluon vertex of the ordering a, b, c, no coupling or propagator)
 __device__ __forceinline__ void bg_v4(const cx* a, const cx* b, const cx* c, cx* acc) {
   const cx bc = vdot(b, c), ac = vdot(a, c), ab = vdot(a, b);
-  const cx ac2 = 2.0 * ac;
+  const cx mac2 = -2.0 * ac;
+  // accumulated term by term (fused multiply-adds into acc)
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    cx v = a[u] * bc;
-    v = v - b[u] * ac2;
-    v = fma(v, c[u], ab);
-    acc[u] = acc[u] + v;
+    cx v = fma(acc[u], a[u], bc);
+    v = fma(v, b[u], mac2);
+    acc[u] = fma(v, c[u], ab);
   }
 }
 

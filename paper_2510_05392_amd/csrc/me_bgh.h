@@ -80,7 +80,10 @@ struct BghShape {
   static constexpr int ROFF = COFF + NCV * BG_SLOT;      // row spinors
   static constexpr int MOFF = ROFF + NRV * BG_SLOT;      // momenta [NPAR][4]
   static constexpr int GOFF = MOFF + 4 * NPAR;           // coupling
-  static constexpr int FRAME = GOFF + 2;                 // doubles per event
+  static constexpr int GIOFF = GOFF + 2;                 // 1 / P(mask)^2 [2^N] (subsets of >= 2 gluons)
+  static constexpr int TQOFF = GIOFF + (1 << N);         // q = p3 - P(mask) [2^N][4]
+  static constexpr int TFOFF = TQOFF + (4 << N);         // 1 / (q^2 - mt^2) [2^N]
+  static constexpr int FRAME = TFOFF + (1 << N);         // doubles per event
 };
 
 template <int N>
@@ -111,6 +114,18 @@ __device__ __forceinline__ void bgh_setup_item(double* F, const BgCycles& cy, do
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u) F[H::PSOFF + 4 * i + u] = s[u];
+    // the gluon propagator of a current over this subset and the top propagator
+    // after a row spinor has absorbed it: helicity-independent, formed once here
+    F[H::GIOFF + i] = __builtin_popcount(i) >= 2 ? 1.0 / (s[0] * s[0] - s[1] * s[1] - s[2] * s[2] - s[3] * s[3])
+                                                   : 0.0;
+    const double* p3 = p[2];
+    double q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      q[u] = p3[u] - s[u];
+      F[H::TQOFF + 4 * i + u] = q[u];
+    }
+    F[H::TFOFF + i] = 1.0 / (q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3] - mt * mt);
   } else if (i < (1 << N) + 2 * N) {
     const int j = i - (1 << N), b = j >> 1, bit = j & 1;
     const int q = b < 2 ? b : b + 2;
@@ -168,14 +183,54 @@ __device__ __forceinline__ void bgh_current_item(double* F, const BgTables& t, c
       bg_v4(ja, jb, jc, a4);
     }
   }
-  double p[4];
-  bg_mom(F, t.mask[slot], p);
-  const double inv = 1.0 / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
+  const double inv = F[H::GIOFF + t.mask[slot]];
   const double f3 = -g * inv, f4 = -g * g * inv;
   cx out[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
   bg_store(F, H::COFF + (cy.cbase[slot] + hv) * BG_SLOT, out);
+}
+
+// acc += r . (gamma.J): a row-vertex product without its factor i g, which is
+// applied once to the sum (bgh_prop, or the amplitude).  gamma.J in blocks:
+// UR = [[J0 - J3, -(J1 - iJ2)], [-(J1 + iJ2), J0 + J3]], LL = [[J0 + J3, J1 - iJ2],
+// [J1 + iJ2, J0 - J3]]; r . gamma.J = (r2, r3) LL | (r0, r1) UR.
+__device__ __forceinline__ void bgh_rg_acc(const cx* r, const cx* j, cx* acc) {
+  const cx ij2 = times_i(j[2]);
+  const cx jp = j[0] + j[3], jm = j[0] - j[3], js = j[1] + ij2, jd = j[1] - ij2;
+  acc[0] = fma(fma(acc[0], r[2], jp), r[3], js);
+  acc[1] = fma(fma(acc[1], r[2], jd), r[3], jm);
+  acc[2] = fma(fma(acc[2], r[0], jm), r[1], -js);
+  acc[3] = fma(fma(acc[3], r[0], -jd), r[1], jp);
+}
+
+// out = r . (gamma.J) (as bgh_rg_acc, not accumulated)
+__device__ __forceinline__ void bgh_rg(const cx* r, const cx* j, cx* out) {
+  const cx ij2 = times_i(j[2]);
+  const cx jp = j[0] + j[3], jm = j[0] - j[3], js = j[1] + ij2, jd = j[1] - ij2;
+  out[0] = fma(r[2] * jp, r[3], js);
+  out[1] = fma(r[2] * jd, r[3], jm);
+  out[2] = fma(r[0] * jm, r[1], -js);
+  out[3] = fma(r[0] * (-jd), r[1], jp);
+}
+
+// Top propagator after a row-vertex sum: out = (i g acc) . i (qslash + m) f with
+// f = 1 / (q^2 - m^2), i.e. -(g f) acc . (qslash + m); q and f from the frame.
+__device__ __forceinline__ void bgh_prop(const cx* a, const double* q, double f, double m, double g, cx* out) {
+  const double sc = -g * f;
+  const double qp = q[0] + q[3], qm = q[0] - q[3];
+  const cx o0 = cx{m * a[0].r + qp * a[2].r + q[1] * a[3].r - q[2] * a[3].i,
+                   m * a[0].i + qp * a[2].i + q[2] * a[3].r + q[1] * a[3].i};
+  const cx o1 = cx{m * a[1].r + q[1] * a[2].r + q[2] * a[2].i + qm * a[3].r,
+                   m * a[1].i + q[1] * a[2].i - q[2] * a[2].r + qm * a[3].i};
+  const cx o2 = cx{m * a[2].r + qm * a[0].r - q[1] * a[1].r + q[2] * a[1].i,
+                   m * a[2].i + qm * a[0].i - q[1] * a[1].i - q[2] * a[1].r};
+  const cx o3 = cx{m * a[3].r - q[1] * a[0].r - q[2] * a[0].i + qp * a[1].r,
+                   m * a[3].i - q[1] * a[0].i + q[2] * a[0].r + qp * a[1].i};
+  out[0] = sc * o0;
+  out[1] = sc * o1;
+  out[2] = sc * o2;
+  out[3] = sc * o3;
 }
 
 // Stored row spinor of prefix `slot` (length L, 1 <= L <= N-3), top helicity u,
@@ -188,23 +243,19 @@ __device__ __forceinline__ void bgh_row_item(double* F, const BgTables& t, const
   const uint16_t* sub = t.sub + (int64_t)slot * S::T;
   const int gh = bg_pdep(hv, t.mask[slot]);
   const double g = F[H::GOFF];
-  cx acc[4] = {cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}, cx{0.0, 0.0}};
+  cx acc[4], r[4], jj[4];
+  bg_load(F, H::SPOFF + u * BG_SLOT, r);
+  bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(0, L)], gh), jj);
+  bgh_rg(r, jj, acc);
 #pragma unroll 1
-  for (int j = 0; j < L; ++j) {
-    cx r[4], jj[4], v[4];
-    bg_load(F, j == 0 ? H::SPOFF + u * BG_SLOT : bgh_raddr<N>(t, cy, sub[bg_tri(0, j)], j, u, gh), r);
+  for (int j = 1; j < L; ++j) {
+    bg_load(F, bgh_raddr<N>(t, cy, sub[bg_tri(0, j)], j, u, gh), r);
     bg_load(F, bgh_caddr<N>(t, cy, sub[bg_tri(j, L)], gh), jj);
-    row_vertex(r, jj, g, v);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) acc[w] = acc[w] + v[w];
+    bgh_rg_acc(r, jj, acc);
   }
-  double q[4];
-  bg_mom(F, t.mask[slot], q);
-  const double* p3 = F + H::MOFF + 8;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) q[w] = p3[w] - q[w];
+  const int m = t.mask[slot];
   cx out[4];
-  row_prop(acc, q, mt, out);
+  bgh_prop(acc, F + H::TQOFF + 4 * m, F[H::TFOFF + m], mt, g, out);
   bg_store(F, H::ROFF + (cy.rbase[slot] + (u << L) + hv) * BG_SLOT, out);
 }
 
@@ -213,13 +264,6 @@ __device__ __forceinline__ void bgh_copy(const cx* a, cx* b) {
   for (int u = 0; u < 4; ++u) b[u] = a[u];
 }
 
-// acc += R (i g gamma.J)
-__device__ __forceinline__ void bgh_rv_acc(const cx* r, const cx* j, double g, cx* acc) {
-  cx v[4];
-  row_vertex(r, j, g, v);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = acc[u] + v[u];
-}
 
 template <int N>
 __device__ __forceinline__ int bg_mod(int a) { return a >= N ? a - N : a; }
@@ -303,9 +347,7 @@ __device__ __forceinline__ void bgh_item_current(const double* F, const BghItem<
       bg_v4(ja, jb, jc, a4);
     }
   }
-  double p[4];
-  bg_mom(F, it.mask(s, L), p);
-  const double inv = 1.0 / (p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3]);
+  const double inv = F[BghShape<N>::GIOFF + it.mask(s, L)];
   const double f3 = -g * inv, f4 = -g * g * inv;
 #pragma unroll
   for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
@@ -325,7 +367,6 @@ __device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& 
   constexpr int LR = H::LR;
   const uint16_t* seg = cy.seg + (int64_t)z * N * N;
   const double g = F[H::GOFF];
-  const double* p3 = F + H::MOFF + 8;
   cx cfirst[4], ccur[4], cnext[4];
   bgh_item_current<N, N - 1>(F, it, 0, nullptr, nullptr, g, ccur);
   bgh_copy(ccur, cfirst);
@@ -336,54 +377,50 @@ __device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& 
     cx jf[4];
     bgh_item_current<N, N>(F, it, i, ccur, cnext, g, jf);
     const int col = seg[i * N + N - 1] - S::off(N);
+    const int m2 = it.mask(i, N - 2), m1 = it.mask(i, N - 1);
 #pragma unroll 1
     for (int u = 0; u < 2; ++u) {
       const int ka = u ? krow[2] : krow[0], kb = u ? krow[3] : krow[1];
       if (ka < 0 && kb < 0) continue;
+      // row-vertex sums are formed without their factor i g (bgh_rg): the
+      // propagators and the amplitude apply it once
       cx acc[4], rr[4], jj[4], rn2[4], w[4];
-      double q[4];
-      // R(sigma[:N-2]) = S . sum_{j < N-2} R(sigma[:j]) (i g gamma.J(sigma[j:N-2]))
+      // R(sigma[:N-2]) = S . i g sum_{j < N-2} R(sigma[:j]) gamma.J(sigma[j:N-2])
       bg_load(F, H::SPOFF + u * BG_SLOT, rr);
       bg_load(F, it.cur(i, N - 2), jj);
-      row_vertex(rr, jj, g, acc);
+      bgh_rg(rr, jj, acc);
 #pragma unroll 1
       for (int j = 1; j <= LR; ++j) {
         bg_load(F, it.row(i, j) + (u << j) * BG_SLOT, rr);
         bg_load(F, it.cur(bg_mod<N>(i + j), N - 2 - j), jj);
-        bgh_rv_acc(rr, jj, g, acc);
+        bgh_rg_acc(rr, jj, acc);
       }
-      bg_mom(F, it.mask(i, N - 2), q);
-#pragma unroll
-      for (int x = 0; x < 4; ++x) q[x] = p3[x] - q[x];
-      row_prop(acc, q, mt, rn2);
-      // W = sum_{k >= 1} R(sigma[:k]) (i g gamma.J(sigma[k:])), from k = N-2
+      bgh_prop(acc, F + H::TQOFF + 4 * m2, F[H::TFOFF + m2], mt, g, rn2);
+      // W / (i g) = sum_{k >= 1} R(sigma[:k]) gamma.J(sigma[k:]), from k = N-2
       bg_load(F, it.cur(bg_mod<N>(i + N - 2), 2), jj);
-      row_vertex(rn2, jj, g, w);
-      // R(sigma[:N-1]) = S . (R() (i g gamma.J(sigma[:N-1])) + sum_{1 <= j <= N-2} ...)
+      bgh_rg(rn2, jj, w);
+      // R(sigma[:N-1]) = S . i g (R() gamma.J(sigma[:N-1]) + sum_{1 <= j <= N-2} ...)
       bg_load(F, H::SPOFF + u * BG_SLOT, rr);
-      row_vertex(rr, ccur, g, acc);
+      bgh_rg(rr, ccur, acc);
 #pragma unroll 1
       for (int j = 1; j <= LR; ++j) {
         bg_load(F, it.row(i, j) + (u << j) * BG_SLOT, rr);
         bg_load(F, it.cur(bg_mod<N>(i + j), N - 1 - j), jj);
-        bgh_rv_acc(rr, jj, g, acc);
+        bgh_rg_acc(rr, jj, acc);
       }
       bg_load(F, it.cur(bg_mod<N>(i + N - 2), 1), jj);
-      bgh_rv_acc(rn2, jj, g, acc);
-      bg_mom(F, it.mask(i, N - 1), q);
-#pragma unroll
-      for (int x = 0; x < 4; ++x) q[x] = p3[x] - q[x];
-      row_prop(acc, q, mt, rr);   // rr = R(sigma[:N-1])
+      bgh_rg_acc(rn2, jj, acc);
+      bgh_prop(acc, F + H::TQOFF + 4 * m1, F[H::TFOFF + m1], mt, g, rr);   // rr = R(sigma[:N-1])
       bg_load(F, it.cur(bg_mod<N>(i + N - 1), 1), jj);
-      bgh_rv_acc(rr, jj, g, w);
+      bgh_rg_acc(rr, jj, w);
       // k = 1 (its current is cnext) and 2 <= k <= N-3 (stored rows)
       bg_load(F, it.row(i, 1) + (u << 1) * BG_SLOT, rr);
-      bgh_rv_acc(rr, cnext, g, w);
+      bgh_rg_acc(rr, cnext, w);
 #pragma unroll 1
       for (int k = 2; k <= LR; ++k) {
         bg_load(F, it.row(i, k) + (u << k) * BG_SLOT, rr);
         bg_load(F, it.cur(bg_mod<N>(i + k), N - k), jj);
-        bgh_rv_acc(rr, jj, g, w);
+        bgh_rg_acc(rr, jj, w);
       }
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
@@ -392,7 +429,9 @@ __device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& 
         cx qv[4], vs[4];
         bg_load(F, H::SPOFF + (4 + 2 * u + v) * BG_SLOT, qv);
         bg_load(F, H::SPOFF + (2 + v) * BG_SLOT, vs);
-        const cx a = vdot(qv, jf) + sdot(w, vs);
+        // Q.J(sigma) + (i g W') v
+        const cx qj = vdot(qv, jf), wv = sdot(w, vs);
+        const cx a = cx{qj.r - g * wv.i, qj.i + g * wv.r};
         jt[(int64_t)(2 * col) * rows + row0 + k] = a.r;
         jt[(int64_t)(2 * col + 1) * rows + row0 + k] = a.i;
       }
@@ -419,8 +458,9 @@ typedef double bgh_f64x4 __attribute__((ext_vector_type(4)));
 
 // Block-triangular colour matrix staged in LDS as FP32 (exact: integer entries
 // below 2^24): the 16 x 16 blocks (mb, kb) with kb >= mb, block-row major, rows
-// BGH_CS floats apart (16 + 4 against bank conflicts).
-constexpr int BGH_CS = 20;
+// BGH_CS floats apart (16 + 2: the 16 rows x 2 K indices of a half-wave read
+// fall in distinct banks).
+constexpr int BGH_CS = 18;
 template <int NCOL>
 struct BghColour {
   static constexpr int KS = (NCOL + 3) / 4;     // K steps of 4 flows

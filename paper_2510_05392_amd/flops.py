@@ -124,6 +124,15 @@ BG = {
     'v3q': 112,        # one split of a three-gluon vertex contracted with Q, accumulated
     'v4q': 116,        # one split of a four-gluon vertex contracted with Q, accumulated
     'qclose': 17,      # 1 / P^2, the couplings and their combination into Q . J(sigma)
+    # helicity-recycling kernel (csrc/me_bgh.h): propagator factors of every gluon
+    # subset formed once in the set-up, row-vertex sums without their factor i g
+    'close_h': 27,     # the couplings and their combination into the current (1 / P^2 read)
+    'rg': 64,          # bgh_rg: r . gamma.J, first term of a row-vertex sum
+    'rg_acc': 72,      # bgh_rg_acc: r . gamma.J accumulated
+    'prop_h': 67,      # bgh_prop: i g and the top propagator (q, 1 / (q^2 - m^2) read)
+    'amp_h': 64,       # Q . J(sigma) + i g W' v of one quark helicity pair
+    'subset_h': 14,    # per gluon subset: q = p3 - P and 1 / (q^2 - m^2)
+    'ginv_h': 8,       # per subset of >= 2 gluons: 1 / P^2
 }
 
 
@@ -154,8 +163,9 @@ def bg_row(n):
 
 def bgh_event(n):
     """FP64 flops of one event of the helicity-recycling Berends-Giele kernel with n
-    gluons (n = 4, 5) and every helicity good: currents of length L <= n-2 once per
-    helicity variant of their gluons (2^L), row spinors of length L <= n-3 once per
+    gluons (n = 4, 5) and every helicity good: the set-up (momentum sums, propagator
+    factors of every gluon subset, external states), currents of length L <= n-2 once
+    per helicity variant of their gluons (2^L), row spinors of length L <= n-3 once per
     variant (2^(L+1)), and (n-1)! 2^n cycle items, each forming the n currents of
     length n-1 along its rotation cycle and, per ordering, the full current, the two
     row spinors and W of each top helicity, and four amplitudes (beams along +-z; the
@@ -164,16 +174,19 @@ def bgh_event(n):
     cnt = [0] + [math.perm(n, L) for L in range(1, n + 1)]
 
     def current(L):
-        return (L - 1) * BG['v3'] + math.comb(L - 1, 2) * BG['v4'] + BG['close']
+        return (L - 1) * BG['v3'] + math.comb(L - 1, 2) * BG['v4'] + BG['close_h']
 
-    setup = 8 * n * 2 ** (n - 1) + 2 * (2 * ROUTINE['Gbeam'] + (n - 2) * ROUTINE['G']) \
-        + 6 * (ROUTINE['U'] + ROUTINE['V']) + 4 * BG['line']
+    def row(L):
+        return BG['rg'] + (L - 1) * BG['rg_acc'] + BG['prop_h']
+
+    setup = 8 * n * 2 ** (n - 1) + BG['subset_h'] * 2 ** n + BG['ginv_h'] * (2 ** n - n - 1) \
+        + 2 * (2 * ROUTINE['Gbeam'] + (n - 2) * ROUTINE['G']) + 6 * (ROUTINE['U'] + ROUTINE['V']) + 4 * BG['line']
     currents = sum(cnt[L] * 2 ** L * current(L) for L in range(2, n - 1))
-    rows = sum(cnt[L] * 2 ** (L + 1) * (L * BG['row_term'] + BG['row_close']) for L in range(1, n - 2))
-    # the first term of each row spinor and of W is assigned, not accumulated (-8)
-    per_u = ((n - 2) * BG['row_term'] - 8 + BG['row_close']) + ((n - 1) * BG['row_term'] - 8 + BG['row_close']) \
-        + ((n - 1) * BG['row_term'] - 8)
-    per_order = current(n) + 2 * per_u + 4 * (2 * ROUTINE['vdot'] + 2)
+    rows = sum(cnt[L] * 2 ** (L + 1) * row(L) for L in range(1, n - 2))
+    # per top helicity: R(sigma[:n-2]), R(sigma[:n-1]) and W' (the n-2 further terms
+    # of W after its first, from R(sigma[:n-2]))
+    per_u = row(n - 2) + row(n - 1) + BG['rg'] + (n - 2) * BG['rg_acc']
+    per_order = current(n) + 2 * per_u + 4 * BG['amp_h']
     items = cnt[n] // n * 2 ** n * (n * current(n - 1) + n * per_order)
     return {'setup': setup, 'currents': currents, 'rows': rows, 'items': items,
             'total': setup + currents + rows + items}

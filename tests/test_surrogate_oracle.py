@@ -179,3 +179,27 @@ def test_two_stage_overweights_with_quantile_maxima():
     for e in range(len(w)):
         r = resid[ev[acc] == e]
         assert np.allclose(r, max(1, w_hat[e] / what_max) * max(1, x[e] / x_max))
+
+
+def test_one_stage_overweights_with_a_quantile_maximum():
+    """One-stage unweighting with w_max below the largest weight (the calibration
+    quantile of the baseline): on a toy where min(1, w/w_max) is a multiple of 1/8
+    and each event meets the grid of 8 random numbers (i + 1/2)/8, event e is
+    accepted exactly 8 min(1, w_e/w_max) times, each accept carrying
+    max(1, w_e/w_max); the accepted residual weights then sum to 8 sum_e w_e/w_max
+    (unbiased), and the overweights are the accepts of the events above w_max.
+
+    Mutations caught: dropping the max(1, .) of the residual weight (the sum falls
+    short by the overweights' excess), min instead of max, or accepting on
+    w_max/w."""
+    w = np.array([0.5, 1.0, 2.0, 3.0, 4.0, 6.0])
+    w_max = 2.0
+    grid = (np.arange(8) + 0.5) / 8
+    ev = np.repeat(np.arange(len(w)), 8)
+    acc, resid = S.one_stage(w[ev], np.tile(grid, len(w)), w_max)
+    p = np.minimum(1.0, w / w_max)
+    assert acc.sum() == int(round(8 * p.sum()))
+    assert np.isclose(resid.sum(), 8 * w.sum() / w_max, rtol=1e-14)
+    assert (resid > 1).sum() == int(round(8 * p[w > w_max].sum()))
+    for e in range(len(w)):
+        assert np.allclose(resid[ev[acc] == e], max(1.0, w[e] / w_max))
