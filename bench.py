@@ -29,9 +29,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # what an item reads and writes); the numbers and the commands are in the named profile and hold
 # only for the kernel they were taken on.
 # key: (process, nevt, (persistent, hel_per_item, executor, split_wpe, split_rounds, bg_variant)) as me_autotune
-# reports them; no entry yet for the kernels as they are now (the momentum loads changed).
+# reports them.
 TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds', 'bg_variant')
 MEASURED_TRAFFIC = {
+    # helicity-recycling Berends-Giele kernel with the fused FP64 colour form, 4 launches per call
+    ('gg_ttxggg', 262144, (0, 0, 3, 0, 0, 4)): (3.246e10, 'profiles/bgh_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
@@ -107,7 +109,7 @@ def binding_resource(traffic, ms_per_launch, achieved_tflops):
     tbs = traffic[0] / (ms_per_launch * 1e-3) / 1e12
     hbm = tbs / HBM_PEAK_TBS
     return {'fp64_frac': alu, 'hbm_TBps': tbs, 'hbm_frac': hbm,
-            'resource': 'HBM (register-spill traffic)' if hbm > alu else 'FP64 vector ALU'}
+            'resource': 'HBM (register-spill traffic)' if hbm > alu else 'FP64 vector ALU issue'}
 
 
 def surrogate_leg(args, process, nevt, mom, dmom, binding, rambo, executor=None, bg_variant=0):
