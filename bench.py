@@ -32,8 +32,6 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # reports them.
 TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds', 'bg_variant')
 MEASURED_TRAFFIC = {
-    # helicity-recycling Berends-Giele kernel with the fused FP64 colour form, 4 launches per call
-    ('gg_ttxggg', 262144, (0, 0, 3, 0, 0, 4)): (3.246e10, 'profiles/bgh_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}

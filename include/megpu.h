@@ -86,6 +86,9 @@ extern "C" {
 #define ME_JAMP_SCRATCH_BYTES (4ull << 30)
 /* device scratch of the split executor's colour-group sums and colour flows */
 #define ME_SPLIT_SCRATCH_BYTES (16ull << 30)
+/* Scratch of the fused helicity-recycling launches (me_set_bg variant 4): one slot
+ * of dual amplitudes per workgroup of a launch. */
+#define ME_BG_FUSED_SCRATCH_BYTES (4ull << 30)
 
 typedef struct me_ctx* me_handle;
 
@@ -308,7 +311,7 @@ int me_kernel_times(me_handle h, double* total_ms, int64_t* launches);
  * target_waves, executor, split waves per SIMD, flow chunk, split rounds, colour
  * grid, Berends-Giele launch shape; 0 in the last five = default).  The
  * Berends-Giele executor is a candidate in its three launch shapes and, for four
- * and five gluons, with helicity recycling (variants 3 and 4). */
+ * and five gluons, with helicity recycling (variants 3, 4 and 5). */
 #define ME_TUNE_FIELDS 10
 int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s, double* out_me2,
                 void* stream, int32_t* best);
@@ -326,10 +329,13 @@ int me_set_split(me_handle h, int wpe, int fchunk, int rounds, int colour_grid);
  * threads per workgroup, 1 = half of both, 2 = twice both; 3 = helicity
  * recycling (four and five gluons: one workgroup per event(s), every current and
  * row spinor formed once per helicity assignment of its own particles, the full
- * orderings walked in rotation cycles); 4 = helicity recycling with the FP64 colour
- * form of each row computed by the same workgroup on the matrix cores (no separate
- * colour kernel; in the matrix-core colour-sum modes 4 behaves as 3).  See
- * me_autotune.  ME_EINVAL for other values, and for 3 and 4 on other processes.
+ * orderings walked in rotation cycles); 4 = helicity recycling with the colour
+ * form (FP64, or split FP16 / BF16, on the matrix cores) and the helicity sum of
+ * each event formed by the same workgroup, no colour or reduction kernel, launches
+ * of as many event blocks as ME_BG_FUSED_SCRATCH_BYTES of dual-amplitude slots
+ * hold; 5 = the same as one persistent launch over the whole batch (scratch: one
+ * slot per resident workgroup, about 126 MB for g g -> t tbar g g g).  See
+ * me_autotune.  ME_EINVAL for other values, and for 3, 4 and 5 on other processes.
  * Results do not depend on it beyond rounding. */
 int me_set_bg(me_handle h, int variant);
 
@@ -418,11 +424,12 @@ int me_unweight_stage2(const double* me_exact, const int64_t* idx, int64_t m, co
                        void* stream);
 
 /* Introspection for tests: the activations of the last forward pass (me_sur_predict
- * or me_sur_grads; of the last chunk of 65536 rows for larger predictions), first
+ * or me_sur_grads; of the last chunk of 262144 rows for larger predictions), first
  * `rows` rows, copied to host[rows][n]: kind 0 = the input of linear layer `layer`
  * (BF16 values as FP32, n = its input width; layer 0 = the feature rows), kind 1 =
- * its output before the activation (FP32, n = its output width).  Synchronises the
- * device. */
+ * its output before the activation (FP32, n = its output width; for the hidden
+ * layers only after me_sur_grads: inference keeps just the last layer's).
+ * Synchronises the device. */
 int me_sur_activations(me_surrogate s, int layer, int kind, int64_t rows, float* host);
 
 /* Normalisation of the surrogate's inputs and target from a training sample

@@ -53,7 +53,9 @@ def bg_unit(name, n):
             f'static hipError_t colour64_{name}(const double* jt, int64_t nrow, const double* cf64, double* out, '
             'hipStream_t s) {\n' + colour + '  return hipGetLastError();\n}\n'
             f'const BgDesc* bg_{name}() {{\n  static const BgDesc d = {{"{name}", {n}, {ncol}, &launch_bg<{n}>, '
-            f'&colour64_{name}, {tri}, {int(n in (4, 5))}}};\n  return &d;\n}}\n}}\n')
+            f'&colour64_{name}, {tri}, {int(n in (4, 5))}, &bgh_fused_per_cu<{n}>, &bgh_fused_slot_doubles<{n}>, '
+            f'&bgh_block_events<{n}>}};\n'
+            '  return &d;\n}\n}\n')
 ARCH = 'gfx950'
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-std=c++17', '-O3', '-fPIC', f'--offload-arch={ARCH}',

@@ -226,6 +226,8 @@ struct me_ctx {
   int split_rounds = 0;       // events per chunk as whole rounds of group-sum waves (0: as many as fit)
   int colour_grid = 0;        // workgroups of the FP64 colour kernel
   int bg_variant = 0;         // Berends-Giele kernel: launch shape 0, 1, 2; 3 = helicity recycling; 4 = the same, FP64 colour form fused
+  int bg_grid = 0;            // workgroups (scratch slots) per launch of the fused kernel
+  int bg_resident = 0;        // its resident workgroups on the device
   bool tuned = false;         // me_autotune has run (or found its configuration in the cache)
   int* d_counter = nullptr;   // persistent work counter
   int simds = 1024;           // compute units x 4
@@ -364,6 +366,25 @@ int ensure_bg_tables(me_ctx* c) {
 
 // Events per chunk of the Berends-Giele executor: the dual amplitudes of a chunk
 // (2 NCOL doubles per row, nhel rows per event) fill at most ME_SPLIT_SCRATCH_BYTES.
+// The Berends-Giele executor runs its persistent kernel with the colour form (FP64,
+// or split FP16 / BF16 on the matrix cores) and the helicity sum fused (launch
+// variant 4).
+bool bg_fused(const me_ctx* h) {
+  return h->executor == ME_EXEC_BG && (h->bg_variant == 4 || h->bg_variant == 5) && h->bg->recycle &&
+         h->bg->fused_slot_doubles;
+}
+
+// Event blocks per launch of the fused kernel: variant 5 = one persistent launch over
+// the resident workgroups; variant 4 = launches of as many blocks as
+// ME_BG_FUSED_SCRATCH_BYTES of slots hold, in whole rounds of the resident workgroups.
+int64_t bg_fused_blocks(const me_ctx* h, int nhel) {
+  if (h->bg_variant == 5) return h->bg_resident;
+  const int64_t slot = (int64_t)h->bg->fused_slot_doubles(nhel) * (int64_t)sizeof(double);
+  int64_t b = (int64_t)(ME_BG_FUSED_SCRATCH_BYTES / (uint64_t)slot);
+  if (b >= h->bg_resident) b = (b / h->bg_resident) * h->bg_resident;
+  return std::max<int64_t>(1, b);
+}
+
 int64_t bg_chunk(const me_ctx* h, int64_t nevt) {
   const size_t per_event = sizeof(double) * 2 * (size_t)h->desc->ncol * h->good.size();
   int64_t chunk = (int64_t)(ME_SPLIT_SCRATCH_BYTES / per_event);
@@ -858,10 +879,18 @@ namespace {
 int prepare(me_ctx* h, int64_t nevt) {
   const int nhel = (int)h->good.size();
   if (h->executor == ME_EXEC_BG) {
-    // dual amplitudes of an event chunk [2 NCOL][rows] in the split scratch, then
-    // one colour sum per row
     int rc = ensure_bg_tables(h);
     if (rc) return rc;
+    if (bg_fused(h)) {
+      // one scratch slot per workgroup of a launch
+      const int per_cu = h->bg->fused_per_cu ? h->bg->fused_per_cu() : 0;
+      if (per_cu < 1) return fail(ME_EHIP, "fused Berends-Giele kernel: no resident workgroup fits");
+      h->bg_resident = per_cu * std::max(1, h->simds / 4);
+      h->bg_grid = (int)bg_fused_blocks(h, nhel);
+      return ensure_sums(h, (size_t)h->bg_grid * (size_t)h->bg->fused_slot_doubles(nhel));
+    }
+    // dual amplitudes of an event chunk [2 NCOL][rows] in the split scratch, then
+    // one colour sum per row
     const int64_t chunk = bg_chunk(h, nevt);
     rc = ensure_sums(h, (size_t)chunk * nhel * 2 * h->desc->ncol);
     if (rc) return rc;
@@ -928,10 +957,37 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
     // event chunks: dual amplitudes of every (helicity, event) row by the recursion,
     // the colour form of every row (FP64 on the matrix cores, or split FP16 / BF16),
     // then the fixed-order helicity sum of the chunk
-    const int64_t chunk = bg_chunk(h, nevt);
     const int npar = h->desc->npar;
     const bool fp64 = h->params.colorsum_mode == ME_CS_FP64;
     const double scale = fp64 ? 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den) : 1.0 / h->desc->iden;
+    if (bg_fused(h)) {
+      // recursion, colour form and helicity sum of each event block in one kernel
+      // (every colour form in units of the integer matrix), one scratch slot per
+      // workgroup: variant 5 one persistent launch, variant 4 launches of bg_grid
+      // blocks
+      const int ev = h->bg->fused_block_events();
+      const int64_t chunk = h->bg_variant == 5 ? nevt : (int64_t)h->bg_grid * ev;
+      for (int64_t off = 0; off < nevt; off += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, nevt - off);
+        me::BgArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_bg_sub, h->d_bg_mask,
+                     h->d_bg_last, alphas ? alphas + off : nullptr, h->d_sums, s};
+        a.variant = h->bg_variant;
+        a.cyc = me::BgCycles{h->d_bg_cyc, h->d_bg_cyc + h->n_bg_cyc, h->d_bg_cyc + h->n_bg_cyc + h->n_bg_slot};
+        a.fmt = fp64 ? -1 : (h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1);   // CS_FMT_FP16, CS_FMT_BF16
+        a.cft = h->d_cf64_tri;
+        a.cf_hi = h->d_cf_hi;
+        a.cf_lo = h->d_cf_lo;
+        a.out = out_me2 + off;
+        a.out_scale = 1.0 / ((double)h->desc->iden * (double)h->desc->cf_den);
+        a.grid = h->bg_grid;
+        KernelMark kd(h, ME_KT_DIAGRAM, s);
+        hipError_t e = h->bg->launch(a);
+        if (e != hipSuccess) return hip_fail(e, "fused Berends-Giele kernel launch");
+        kd.done();
+      }
+      return ME_OK;
+    }
+    const int64_t chunk = bg_chunk(h, nevt);
     for (int64_t off = 0; off < nevt; off += chunk) {
       const int64_t n = std::min<int64_t>(chunk, nevt - off);
       me::BgArgs a{momenta + off * npar * 4, n, g, h->params.mt, h->d_hels, nhel, h->d_bg_sub, h->d_bg_mask,
@@ -939,28 +995,20 @@ int enqueue(me_ctx* h, const double* momenta, int64_t nevt, double alpha_s, doub
       a.variant = h->bg_variant;
       if (h->d_bg_cyc)
         a.cyc = me::BgCycles{h->d_bg_cyc, h->d_bg_cyc + h->n_bg_cyc, h->d_bg_cyc + h->n_bg_cyc + h->n_bg_slot};
-      // variant 4 in FP64 mode: the recursion kernel forms the colour form of its rows
-      const bool fused = fp64 && h->bg_variant == 4;
-      if (fused) {
-        a.cft = h->d_cf64_tri;
-        a.rowout = h->d_partial;
-      }
       KernelMark kd(h, ME_KT_DIAGRAM, s);
       hipError_t e = h->bg->launch(a);
       if (e != hipSuccess) return hip_fail(e, "Berends-Giele kernel launch");
       kd.done();
-      if (!fused) {
-        KernelMark kc(h, ME_KT_COLOUR, s);
-        if (fp64) {
-          e = h->bg->colour64(h->d_sums, n * nhel, h->bg->colour_tri ? h->d_cf64_tri : h->d_cf64, h->d_partial, s);
-        } else {
-          me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
-                            h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
-          e = h->desc->colour(ca);
-        }
-        if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
-        kc.done();
+      KernelMark kc(h, ME_KT_COLOUR, s);
+      if (fp64) {
+        e = h->bg->colour64(h->d_sums, n * nhel, h->bg->colour_tri ? h->d_cf64_tri : h->d_cf64, h->d_partial, s);
+      } else {
+        me::ColourArgs ca{h->d_sums, n * nhel, h->params.colorsum_mode == ME_CS_FP16X2 ? 0 : 1, h->d_cf_hi,
+                          h->d_cf_lo, 1.0 / h->desc->cf_den, h->d_partial, s, 1};
+        e = h->desc->colour(ca);
       }
+      if (e != hipSuccess) return hip_fail(e, "colour-sum kernel launch");
+      kc.done();
       KernelMark kr(h, ME_KT_REDUCE, s);
       if (h->bg_variant >= 3)   // event-major rows
         hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->d_partial,
@@ -1520,7 +1568,7 @@ int me_set_launch(me_handle h, int persistent, int waves_per_simd, int hel_per_i
 int me_set_bg(me_handle h, int variant) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (variant < 0 || variant > 4) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
+  if (variant < 0 || variant > 5) return fail(ME_EINVAL, "bad Berends-Giele launch shape");
   if (variant >= 3 && !h->bg->recycle)
     return fail(ME_EINVAL, "helicity recycling is built for four and five gluons only");
   h->bg_variant = variant;
@@ -1678,7 +1726,7 @@ int me_autotune(me_handle h, const double* momenta, int64_t nevt, double alpha_s
   }
   for (int v : {0, 1, 2}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
   if (h->bg->recycle)
-    for (int v : {3, 4}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
+    for (int v : {3, 4, 5}) cands.push_back(TuneCand{{0, 1, 0, 4096, ME_EXEC_BG, 0, 0, 0, 0, v}});
   if (h->desc->split) {
     // group-sum kernel variants (waves per SIMD), flow chunk sizes and event chunks
     // (as many whole rounds of group-sum waves as fit the scratch, or two rounds)

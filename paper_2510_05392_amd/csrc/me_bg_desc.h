@@ -38,8 +38,14 @@ struct BgArgs {
   int variant = 0;       // 0, 1, 2: one row per item, launch shapes; 3: helicity recycling;
                          // 4: helicity recycling with the FP64 colour form fused
   BgCycles cyc{nullptr, nullptr, nullptr};   // variants 3 and 4 only
-  const double* cft = nullptr;   // variant 4: block-triangular FP64 colour matrix [16 MB][4 KS]
-  double* rowout = nullptr;      // variant 4: colour form of every row [n nhel] (nullptr: jt only)
+  // variant 4 (persistent kernel): jt is grid slots of [2 NCOL][EV nhel]
+  int fmt = -1;                  // colour form: -1 FP64, 0 split FP16, 1 split BF16 (CS_FMT_*)
+  const double* cft = nullptr;   // FP64: block-triangular colour matrix [16 MB][4 KS]
+  const void* cf_hi = nullptr;   // split formats: colour-matrix tables [32 MB][16 KS] (lo may be null)
+  const void* cf_lo = nullptr;
+  double* out = nullptr;         // per-event |M|^2 [n] (nullptr: variant 4 runs as 3)
+  double out_scale = 1.0;        // 1 / (IDEN x colour denominator)
+  int grid = 0;                  // workgroups (= scratch slots)
 };
 
 using BgLauncher = hipError_t (*)(const BgArgs&);
@@ -54,7 +60,10 @@ struct BgDesc {
   BgLauncher launch;
   Colour64Launcher colour64;
   int colour_tri;        // 1: colour64 takes the block-triangular matrix, 0: the full one
-  int recycle;           // 1: launch variant 3 (helicity recycling) is built
+  int recycle;           // 1: launch variants 3 and 4 (helicity recycling) are built
+  int (*fused_per_cu)();                 // resident workgroups per CU of the fused kernel (variants 4, 5)
+  int64_t (*fused_slot_doubles)(int nhel);   // its scratch per workgroup
+  int (*fused_block_events)();           // its events per workgroup block
 };
 
 }  // namespace me

@@ -454,6 +454,10 @@ __device__ __forceinline__ void bgh_krow(const int* hrow, int gh, int* krow) {
 }
 
 #ifdef __HIPCC__
+}  // namespace me
+#include "colour_mfma.h"
+namespace me {
+
 typedef double bgh_f64x4 __attribute__((ext_vector_type(4)));
 
 // Block-triangular colour matrix staged in LDS as FP32 (exact: integer entries
@@ -498,15 +502,20 @@ __device__ __forceinline__ void bgh_colour_rows(const double* __restrict__ jt, i
   }
   __syncthreads();
   const int l = threadIdx.x & 63;
-  const int j = l & 15, kq = l >> 4, part = j >> 3;
+  const int j = l & 15, part = j >> 3;
   const int ntile = (nr + 7) >> 3;
   for (int tile = threadIdx.x >> 6; tile < ntile; tile += THREADS / 64) {
     // the matrix operands are read from LDS in each tile: kept out of registers
     // across tiles (hoisted, the 128 of them would not fit)
     asm volatile("" ::: "memory");
+    // the row stride is opaque in each tile: the flow offsets are formed as the loads
+    // need them instead of being hoisted out of the loops
+    int64_t rs = rows;
+    int kq = l >> 4;   // the lane's K index, likewise formed in each tile
+    asm volatile("" : "+s"(rs), "+v"(kq));
     const int rr = 8 * tile + (j & 7);
     const bool valid = rr < nr;
-    const double* x = jt + (int64_t)(part + 2 * kq) * rows + r0 + (valid ? rr : 0);
+    const double* x = jt + (int64_t)(part + 2 * kq) * rs + r0 + (valid ? rr : 0);
     bgh_f64x4 acc[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[mb] = bgh_f64x4{0.0, 0.0, 0.0, 0.0};
@@ -517,7 +526,7 @@ __device__ __forceinline__ void bgh_colour_rows(const double* __restrict__ jt, i
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int ks = 4 * kb + q;
-        b[q] = (ks < KS && 4 * ks + kq < NCOL && valid) ? x[(int64_t)(8 * ks) * rows] : 0.0;
+        b[q] = (ks < KS && 4 * ks + kq < NCOL && valid) ? x[(int64_t)(8 * ks) * rs] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -540,38 +549,124 @@ __device__ __forceinline__ void bgh_colour_rows(const double* __restrict__ jt, i
   }
 }
 
-// One workgroup: events blockIdx.x EV .. + EV - 1 of the chunk, all good
-// helicities; rows event-major (row = e nhel + k).  Levels: set-up, then for
-// L = 2 .. N-2 the currents of length L with the row spinors of length L - 1,
-// then the cycle items; barriers between levels.  Dynamic LDS: the EV frames,
-// the segment masks of every cycle, each thread's item table.  With COL the
-// workgroup then forms the FP64 colour form of its rows into rowout (cft: the
-// block-triangular colour matrix), the staged matrix taking the frames' place.
-// Two workgroups fit a compute unit's LDS: the registers are held to two waves
-// per SIMD.
-template <int N, int EV, int THREADS, bool COL>
-__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2))) bgh_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt,
-                                                      const int* __restrict__ hels, int nhel, BgTables t, BgCycles cy,
-                                                      const double* __restrict__ alphas, double* __restrict__ jt,
-                                                      const double* __restrict__ cft, double* __restrict__ rowout) {
+// Split-precision colour form (FMT = CS_FMT_FP16 or CS_FMT_BF16) of the rows
+// 0 .. nr - 1 of jt [2 NCOL][rows], by the whole workgroup, as colour_mfma_kernel
+// forms it: one wave per tile of 16 rows, each row split into hi + lo in the format
+// (FP16 rows first scaled by a power of two, exact), v_mfma_f32_32x32x16 against
+// the exact colour matrix, FP64 row dots.  The matrix's high part is staged in LDS
+// (cfs: 32 MB x 16 KS elements), its low part, when the format needs one, read from
+// global memory.  out[row] = ME_row in units of the integer matrix.
+template <int NCOL, int FMT, int THREADS>
+__device__ __forceinline__ void bgh_colour_rows_split(const double* __restrict__ jt, int64_t rows, int nr,
+                                                      const void* __restrict__ cf_hi_raw,
+                                                      const void* __restrict__ cf_lo_raw, void* cfs_raw,
+                                                      double* __restrict__ out) {
+  typedef cs_types<FMT> T;
+  typedef typename T::vec vec;
+  typedef typename T::elem elem;
+  constexpr int KS = (NCOL + 15) / 16, MB = (NCOL + 31) / 32, KP = KS * 16;
+  vec* cfs = reinterpret_cast<vec*>(cfs_raw);
+  const vec* cf_hi = reinterpret_cast<const vec*>(cf_hi_raw);
+  const vec* cf_lo = reinterpret_cast<const vec*>(cf_lo_raw);
+  for (int i = threadIdx.x; i < 32 * MB * KP / 8; i += THREADS) cfs[i] = cf_hi[i];
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  const int j = l & 31, r = j & 15, part = j >> 4;
+  const int ntile = (nr + 15) >> 4;
+  for (int tile = threadIdx.x >> 6; tile < ntile; tile += THREADS / 64) {
+    // the row stride is made opaque in each tile so that the flow offsets are formed
+    // as the loads need them, not hoisted out of the loops (64 of them would spill)
+    int64_t rs = rows;
+    int half = l >> 5;   // the lane's K half, likewise formed in each tile
+    asm volatile("" : "+s"(rs), "+v"(half) : : "memory");
+    const int row = 16 * tile + r;
+    const bool valid = row < nr;
+    const double* x = jt + (int64_t)part * rs + (valid ? row : 0);
+    double scale = 1.0, unscale = 1.0;
+    if (FMT == CS_FMT_FP16) {
+      double m = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int c = 16 * kk + 8 * half + t;
+          if (c < NCOL && valid) m = fmax(m, fabs(x[(int64_t)(2 * c) * rs]));
+        }
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if (m > 0.0) {
+        const int e = ilogb(m);
+        scale = ldexp(1.0, -e);
+        unscale = ldexp(1.0, e);
+      }
+    }
+    // the amplitudes are read again (from cache) by each pass rather than held in
+    // registers across them
+    asm volatile("" ::: "memory");
+    f32x16 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mb][v] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      vec bh, bl;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int c = 16 * kk + 8 * half + t;
+        const double v = (c < NCOL && valid) ? x[(int64_t)(2 * c) * rs] * scale : 0.0;
+        const elem hi = (elem)v;
+        bh[t] = hi;
+        bl[t] = (elem)(v - (double)hi);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int idx = ((32 * mb + j) * KP + 16 * kk + 8 * half) / 8;
+        const vec a = cfs[idx];
+        acc[mb] = T::mfma(a, bh, acc[mb]);
+        acc[mb] = T::mfma(a, bl, acc[mb]);
+        if (cf_lo) {
+          const vec a2 = cf_lo[idx];
+          acc[mb] = T::mfma(a2, bh, acc[mb]);
+          acc[mb] = T::mfma(a2, bl, acc[mb]);
+        }
+      }
+    }
+    asm volatile("" ::: "memory");
+    double sum = 0.0;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
+        if (i < NCOL && valid) sum += x[(int64_t)(2 * i) * rs] * (double)acc[mb][v];
+      }
+    sum += __shfl_xor(sum, 32);   // the two halves of the M rows
+    sum += __shfl_xor(sum, 16);   // real + imaginary parts
+    if (l < 16 && valid) out[row] = sum * unscale;
+  }
+}
+
+// The work of one block of EV events e0 .. e0 + nev - 1, all good helicities, by
+// the whole workgroup: set-up, then for L = 2 .. N-2 the currents of length L with
+// the row spinors of length L - 1, then the cycle items, barriers between levels.
+// Amplitudes go to jt[2 c][rows] at row rbase + ev nhel + k.  LDS (dynamic): the EV
+// frames, then (already filled) the segment masks of every cycle and each thread's
+// item table; hrow maps helicity -> good-helicity row.
+template <int N, int EV, int THREADS>
+__device__ __forceinline__ void bgh_block(double* lds, const uint8_t* sm, uint16_t* tabs, const int* hrow,
+                                          const double* __restrict__ mom, int64_t e0, int nev, double g0,
+                                          double mt, int nhel, const BgTables& t, const BgCycles& cy,
+                                          const double* __restrict__ alphas, double* __restrict__ jt, int64_t rows,
+                                          int64_t rbase) {
   using S = BgShape<N>;
   using H = BghShape<N>;
   constexpr int NPAR = N + 2;
-  extern __shared__ double lds[];
-  uint8_t* sm = reinterpret_cast<uint8_t*>(lds + EV * H::FRAME);
-  uint16_t* tabs = reinterpret_cast<uint16_t*>(sm + ((H::NCYC * N * N + 15) & ~15));
-  __shared__ int hrow[1 << NPAR];
-  const int64_t e0 = (int64_t)blockIdx.x * EV;
-  const int nev = (int)(n - e0 < EV ? n - e0 : EV);
-  const int64_t rows = n * nhel;
-  for (int i = threadIdx.x; i < (1 << NPAR); i += THREADS) hrow[i] = -1;
   for (int i = threadIdx.x; i < nev * NPAR * 4; i += THREADS)
     lds[(i / (NPAR * 4)) * H::FRAME + H::MOFF + i % (NPAR * 4)] = mom[e0 * NPAR * 4 + i];
   for (int i = threadIdx.x; i < nev; i += THREADS)
     lds[i * H::FRAME + H::GOFF] = alphas ? sqrt(4.0 * 3.14159265358979323846 * alphas[e0 + i]) : g0;
-  for (int i = threadIdx.x; i < H::NCYC * N * N; i += THREADS) sm[i] = t.mask[cy.seg[i]];
   __syncthreads();
-  for (int k = threadIdx.x; k < nhel; k += THREADS) hrow[hels[k]] = k;
   for (int it = threadIdx.x; it < nev * H::NSET; it += THREADS)
     bgh_setup_item<N>(lds + (it / H::NSET) * H::FRAME, cy, mt, it % H::NSET);
   __syncthreads();
@@ -600,15 +695,102 @@ __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)
     if (krow[0] < 0 && krow[1] < 0 && krow[2] < 0 && krow[3] < 0) continue;
     bgh_fill_item<N>(tab, THREADS, t, cy, z, gh);
     const BghItem<N> item{tab, THREADS, sm + z * N * N};
-    bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, (e0 + ev) * nhel);
+    bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, rbase + (int64_t)ev * nhel);
   }
-  if constexpr (COL) {
-    static_assert(BghColour<S::NCOL>::FLOATS * sizeof(float) <= EV * H::FRAME * sizeof(double),
-                  "the staged colour matrix must fit in the frames");
-    // every amplitude of this workgroup's rows is stored (workgroup-scope fence and
-    // barrier) and the frames are no longer read
+}
+
+// Kernel set-up shared by both launch forms: the helicity -> row map and the
+// segment masks of every cycle.
+template <int N, int THREADS>
+__device__ __forceinline__ void bgh_tables(int* hrow, uint8_t* sm, const int* __restrict__ hels, int nhel,
+                                           const BgTables& t, const BgCycles& cy) {
+  using H = BghShape<N>;
+  for (int i = threadIdx.x; i < (1 << (N + 2)); i += THREADS) hrow[i] = -1;
+  for (int i = threadIdx.x; i < H::NCYC * N * N; i += THREADS) sm[i] = t.mask[cy.seg[i]];
+  __syncthreads();
+  for (int k = threadIdx.x; k < nhel; k += THREADS) hrow[hels[k]] = k;
+}
+
+// Dynamic LDS of the recycling kernels: EV frames, the segment masks, the item tables.
+template <int N, int EV, int THREADS>
+constexpr size_t bgh_lds_bytes() {
+  using H = BghShape<N>;
+  return (size_t)EV * H::FRAME * sizeof(double) + ((H::NCYC * N * N + 15) & ~15) +
+         (size_t)N * (H::LC + H::LR) * THREADS * sizeof(uint16_t);
+}
+
+// Launch variant 3: one workgroup per block of EV events of the chunk (rows
+// event-major, row = e nhel + k); the colour form is a kernel of its own.
+template <int N, int EV, int THREADS>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+bgh_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt, const int* __restrict__ hels, int nhel,
+           BgTables t, BgCycles cy, const double* __restrict__ alphas, double* __restrict__ jt) {
+  using H = BghShape<N>;
+  extern __shared__ double lds[];
+  uint8_t* sm = reinterpret_cast<uint8_t*>(lds + EV * H::FRAME);
+  uint16_t* tabs = reinterpret_cast<uint16_t*>(sm + ((H::NCYC * N * N + 15) & ~15));
+  __shared__ int hrow[1 << (N + 2)];
+  bgh_tables<N, THREADS>(hrow, sm, hels, nhel, t, cy);
+  const int64_t e0 = (int64_t)blockIdx.x * EV;
+  const int nev = (int)(n - e0 < EV ? n - e0 : EV);
+  bgh_block<N, EV, THREADS>(lds, sm, tabs, hrow, mom, e0, nev, g0, mt, nhel, t, cy, alphas, jt, n * nhel, e0 * nhel);
+}
+
+// Launch variants 4 and 5: workgroup b takes the event blocks b, b + gridDim.x, ...
+// (one block each when the grid covers the launch's events, a persistent grid
+// otherwise).  For each block it writes the dual amplitudes to its own slot
+// of the scratch (jt + b [2 NCOL][EV nhel]), reads them back for the colour form of
+// its rows on the matrix cores (FMT < 0: FP64 with cft, the block-triangular colour
+// matrix staged in the LDS the frames held; else split FP16 / BF16 with the
+// format's tables cf_hi, cf_lo), sums each event's rows in helicity order and
+// writes out[e] = scale * sum.  No chunking: the scratch is the resident
+// workgroups' slots, and the whole batch is one launch.
+template <int N, int EV, int THREADS, int FMT, bool PERSIST>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+bgh_fused_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt, const int* __restrict__ hels,
+                 int nhel, BgTables t, BgCycles cy, const double* __restrict__ alphas, double* __restrict__ jt,
+                 const double* __restrict__ cft, const void* __restrict__ cf_hi, const void* __restrict__ cf_lo,
+                 double* __restrict__ out, double scale) {
+  using S = BgShape<N>;
+  using H = BghShape<N>;
+  using C = BghColour<S::NCOL>;
+  // row values after the staged matrix (float index, even): the FP64 form's
+  // block-triangular FP32 blocks, or the split forms' 32 MB x 16 KS table
+  constexpr int SPLIT_FLOATS = 32 * ((S::NCOL + 31) / 32) * 16 * ((S::NCOL + 15) / 16) / 2;
+  constexpr int RV = ((FMT < 0 ? C::FLOATS : SPLIT_FLOATS) + 1) & ~1;
+  static_assert(RV * sizeof(float) + (size_t)EV * (1 << (N + 2)) * sizeof(double) <=
+                    (size_t)EV * H::FRAME * sizeof(double),
+                "the staged colour matrix and the row values must fit in the frames");
+  extern __shared__ double lds[];
+  uint8_t* sm = reinterpret_cast<uint8_t*>(lds + EV * H::FRAME);
+  uint16_t* tabs = reinterpret_cast<uint16_t*>(sm + ((H::NCYC * N * N + 15) & ~15));
+  float* cfs = reinterpret_cast<float*>(lds);
+  double* rv = reinterpret_cast<double*>(cfs + RV);
+  __shared__ int hrow[1 << (N + 2)];
+  bgh_tables<N, THREADS>(hrow, sm, hels, nhel, t, cy);
+  const int64_t srows = (int64_t)EV * nhel;
+  double* slot = jt + (int64_t)blockIdx.x * 2 * S::NCOL * srows;
+  // PERSIST: workgroup b takes the blocks b, b + gridDim.x, ...; else block b only
+  // (a loop over one block would keep its invariants live across iterations)
+  for (int64_t e0 = (int64_t)blockIdx.x * EV; e0 < n; e0 += PERSIST ? (int64_t)gridDim.x * EV : n) {
+    const int nev = (int)(n - e0 < EV ? n - e0 : EV);
+    bgh_block<N, EV, THREADS>(lds, sm, tabs, hrow, mom, e0, nev, g0, mt, nhel, t, cy, alphas, slot, srows, 0);
+    // every amplitude of the block is stored (workgroup-scope fence and barrier)
+    // and the frames are no longer read
     __syncthreads();
-    bgh_colour_rows<S::NCOL, THREADS>(jt, rows, e0 * nhel, nev * nhel, cft, reinterpret_cast<float*>(lds), rowout);
+    if constexpr (FMT < 0)
+      bgh_colour_rows<S::NCOL, THREADS>(slot, srows, 0, nev * nhel, cft, cfs, rv);
+    else
+      bgh_colour_rows_split<S::NCOL, FMT, THREADS>(slot, srows, nev * nhel, cf_hi, cf_lo, cfs, rv);
+    __syncthreads();
+    // helicity sum of each event in row order (the order of reduce_rows_kernel)
+    for (int ev = threadIdx.x; ev < nev; ev += THREADS) {
+      double acc = 0.0;
+      for (int k = 0; k < nhel; ++k) acc += rv[ev * nhel + k];
+      out[e0 + ev] = scale * acc;
+    }
+    // the frames, the staged matrix and the slot are reused by the next block
+    if constexpr (PERSIST) __syncthreads();
   }
 }
 
@@ -617,34 +799,113 @@ template <int N> struct BghLaunchShape;
 template <> struct BghLaunchShape<4> { static constexpr int EV = 8, THREADS = 256; };
 template <> struct BghLaunchShape<5> { static constexpr int EV = 1, THREADS = 256; };
 
-template <int N, bool COL>
+template <int N>
 hipError_t launch_bgh(const BgArgs& a) {
-  using H = BghShape<N>;
   constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
-  const size_t lds = (size_t)EV * H::FRAME * sizeof(double) + ((H::NCYC * N * N + 15) & ~15) +
-                     (size_t)N * (H::LC + H::LR) * THREADS * sizeof(uint16_t);
-  static const hipError_t attr = hipFuncSetAttribute((const void*)bgh_kernel<N, EV, THREADS, COL>,
+  constexpr size_t lds = bgh_lds_bytes<N, EV, THREADS>();
+  static const hipError_t attr = hipFuncSetAttribute((const void*)bgh_kernel<N, EV, THREADS>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
   if (!a.cyc.seg) return hipErrorInvalidValue;
-  if (COL && (!a.cft || !a.rowout)) return hipErrorInvalidValue;
   if (a.n == 0 || a.nhel == 0) return hipSuccess;
   const BgTables t{a.sub, a.mask, a.last};
-  hipLaunchKernelGGL((bgh_kernel<N, EV, THREADS, COL>), dim3((unsigned)((a.n + EV - 1) / EV)), dim3(THREADS), lds,
-                     a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt, a.cft, a.rowout);
+  hipLaunchKernelGGL((bgh_kernel<N, EV, THREADS>), dim3((unsigned)((a.n + EV - 1) / EV)), dim3(THREADS), lds,
+                     a.stream, a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt);
   return hipGetLastError();
 }
 
+template <int N, int FMT, bool PERSIST>
+const void* bgh_fused_fn() {
+  constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
+  return (const void*)bgh_fused_kernel<N, EV, THREADS, FMT, PERSIST>;
+}
+
+// Resident workgroups per compute unit of the fused persistent kernel (0 if not
+// built), the least over its colour-sum formats.
+template <int N>
+int bgh_fused_per_cu() {
+  if constexpr (N == 4 || N == 5) {
+    constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
+    constexpr size_t lds = bgh_lds_bytes<N, EV, THREADS>();
+    int best = 1 << 20;
+    for (const void* fn : {bgh_fused_fn<N, -1, true>(), bgh_fused_fn<N, CS_FMT_FP16, true>(),
+                           bgh_fused_fn<N, CS_FMT_BF16, true>(), bgh_fused_fn<N, -1, false>(),
+                           bgh_fused_fn<N, CS_FMT_FP16, false>(), bgh_fused_fn<N, CS_FMT_BF16, false>()}) {
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, THREADS, lds) != hipSuccess) return 0;
+      best = nb < best ? nb : best;
+    }
+    return best;
+  } else {
+    return 0;
+  }
+}
+
+// Events per workgroup block of the fused kernel (0 if not built).
+template <int N>
+int bgh_block_events() {
+  if constexpr (N == 4 || N == 5) {
+    return BghLaunchShape<N>::EV;
+  } else {
+    return 0;
+  }
+}
+
+// Doubles of scratch per workgroup of the fused kernel.
+template <int N>
+int64_t bgh_fused_slot_doubles(int nhel) {
+  if constexpr (N == 4 || N == 5) {
+    return (int64_t)2 * BgShape<N>::NCOL * BghLaunchShape<N>::EV * nhel;
+  } else {
+    return 0;
+  }
+}
+
+// Variant 4: one workgroup per event block (the launch's blocks must not exceed
+// a.grid slots); variant 5: a persistent grid of a.grid workgroups.
+template <int N, int FMT, bool PERSIST>
+hipError_t launch_bgh_fused_fmt(const BgArgs& a) {
+  constexpr int EV = BghLaunchShape<N>::EV, THREADS = BghLaunchShape<N>::THREADS;
+  constexpr size_t lds = bgh_lds_bytes<N, EV, THREADS>();
+  static const hipError_t attr = hipFuncSetAttribute(bgh_fused_fn<N, FMT, PERSIST>(),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  if (!a.cyc.seg || !a.out || a.grid < 1 || (FMT < 0 ? !a.cft : !a.cf_hi)) return hipErrorInvalidValue;
+  if (a.n == 0 || a.nhel == 0) return hipSuccess;
+  const int64_t blocks = (a.n + EV - 1) / EV;
+  if (!PERSIST && blocks > a.grid) return hipErrorInvalidValue;   // one slot per block
+  const BgTables t{a.sub, a.mask, a.last};
+  const unsigned grid = (unsigned)(blocks < a.grid ? blocks : a.grid);
+  hipLaunchKernelGGL((bgh_fused_kernel<N, EV, THREADS, FMT, PERSIST>), dim3(grid), dim3(THREADS), lds, a.stream,
+                     a.mom, a.n, a.g, a.mt, a.hels, a.nhel, t, a.cyc, a.alphas, a.jt, a.cft, a.cf_hi, a.cf_lo, a.out,
+                     a.out_scale);
+  return hipGetLastError();
+}
+
+template <int N, bool PERSIST>
+hipError_t launch_bgh_fused_p(const BgArgs& a) {
+  if (a.fmt == CS_FMT_FP16) return launch_bgh_fused_fmt<N, CS_FMT_FP16, PERSIST>(a);
+  if (a.fmt == CS_FMT_BF16) return launch_bgh_fused_fmt<N, CS_FMT_BF16, PERSIST>(a);
+  return launch_bgh_fused_fmt<N, -1, PERSIST>(a);
+}
+
+template <int N>
+hipError_t launch_bgh_fused(const BgArgs& a) {
+  return a.variant == 5 ? launch_bgh_fused_p<N, true>(a) : launch_bgh_fused_p<N, false>(a);
+}
+
 // Launch of the executor's kernel in the chosen variant (3: helicity recycling,
-// 4: the same with the FP64 colour form fused when rowout is given; built for four
-// and five gluons).
+// 4 and 5: the kernel with the colour form and the helicity sum fused when a
+// per-event output is given, launched over a.grid workgroups; built for four and
+// five gluons).
 template <int N>
 hipError_t launch_bg(const BgArgs& a) {
   if constexpr (N == 4 || N == 5) {
-    if (a.variant == 4 && a.rowout) return launch_bgh<N, true>(a);
-    if (a.variant == 3 || a.variant == 4) return launch_bgh<N, false>(a);
+    if ((a.variant == 4 || a.variant == 5) && a.out) return launch_bgh_fused<N>(a);
+    if (a.variant >= 3) return launch_bgh<N>(a);
   } else {
-    if (a.variant == 3 || a.variant == 4) return hipErrorInvalidValue;
+    if (a.variant >= 3) return hipErrorInvalidValue;
   }
   if (a.variant == 1) return launch_bg_v<N, 1>(a);
   if (a.variant == 2) return launch_bg_v<N, 2>(a);

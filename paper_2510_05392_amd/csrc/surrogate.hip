@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -83,9 +84,114 @@ __global__ void __launch_bounds__(64) gemm_bf16_kernel(
   }
 }
 
+// C = A . B^T with both operands K-contiguous (A[i][k] at A[i lda + k], B[k][j] at
+// B[j ldb + k]: the layer products of the forward pass), BF16 in, FP32 accumulate,
+// epilogue as gemm_bf16_kernel.  Workgroup tile GT_BM x GT_BN, K in chunks of GT_BK
+// staged through LDS (double buffered: the next chunk's global loads are in flight
+// while the current one feeds the matrix cores); four waves as 2 x 2 blocks of
+// 64 x 64, each 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.  LDS rows are GT_LDS
+// elements apart (16 bytes of padding).  Rows i >= M, columns j >= N and k >= K
+// read as zero.  Needs lda, ldb multiples of 8 and 16-byte aligned A, B.
+constexpr int GT_BM = 128, GT_BN = 128, GT_BK = 64, GT_LDS = GT_BK + 8;
+__global__ void __launch_bounds__(256) gemm_nt_kernel(const __bf16* __restrict__ A, int64_t lda,
+                                                      const __bf16* __restrict__ B, int64_t ldb, int64_t M,
+                                                      int64_t N, int64_t K, const float* __restrict__ bias,
+                                                      float* __restrict__ cf, int64_t ldc,
+                                                      __bf16* __restrict__ ch, int64_t ldh, int silu_act) {
+  extern __shared__ __attribute__((aligned(16))) __bf16 gt_lds[];
+  __bf16(*sa)[GT_BM * GT_LDS] = reinterpret_cast<__bf16(*)[GT_BM * GT_LDS]>(gt_lds);
+  __bf16(*sb)[GT_BN * GT_LDS] = reinterpret_cast<__bf16(*)[GT_BN * GT_LDS]>(gt_lds + 2 * GT_BM * GT_LDS);
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * GT_BM, j0 = (int64_t)blockIdx.y * GT_BN;
+  // global -> LDS: thread t moves row t / 2, elements 32 (t % 2) .. + 31 of the chunk
+  constexpr int Q = GT_BK / 16;   // 16-byte pieces per thread and operand
+  const int lr = t >> 1, lk = (t & 1) * (GT_BK / 2);
+  const int64_t ai = i0 + lr, bj = j0 + lr;
+  bf16x8 ra[Q], rb[Q];
+  bf16x8 zero8;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) zero8[q] = to_bf16(0.0f);
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t kk = k0 + lk + 8 * q;
+      ra[q] = (ai < M && kk < K) ? *reinterpret_cast<const bf16x8*>(A + ai * lda + kk) : zero8;
+      rb[q] = (bj < N && kk < K) ? *reinterpret_cast<const bf16x8*>(B + bj * ldb + kk) : zero8;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      *reinterpret_cast<bf16x8*>(&sa[buf][lr * GT_LDS + lk + 8 * q]) = ra[q];
+      *reinterpret_cast<bf16x8*>(&sb[buf][lr * GT_LDS + lk + 8 * q]) = rb[q];
+    }
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.0f;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int nk = (int)((K + GT_BK - 1) / GT_BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((int64_t)(kc + 1) * GT_BK);
+#pragma unroll
+    for (int ks = 0; ks < GT_BK / 16; ++ks) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = *reinterpret_cast<const bf16x8*>(&sa[buf][(wm + 32 * x + (l & 31)) * GT_LDS + 16 * ks + 8 * (l >> 5)]);
+        b[x] = *reinterpret_cast<const bf16x8*>(&sb[buf][(wn + 32 * x + (l & 31)) * GT_LDS + 16 * ks + 8 * (l >> 5)]);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    // the other buffer was last read before the previous barrier
+    if (kc + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int64_t j = j0 + wn + 32 * y + (l & 31);
+    if (j >= N) continue;
+    const float bj_ = bias ? bias[j] : 0.0f;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t i = i0 + wm + 32 * x + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+        if (i < M) {
+          const float z = acc[x][y][v] + bj_;
+          if (cf) cf[i * ldc + j] = z;
+          if (ch) ch[i * ldh + j] = to_bf16(silu_act ? silu(z) : z);
+        }
+      }
+  }
+}
+
 hipError_t gemm(const __bf16* A, int64_t sai, int64_t sak, const __bf16* B, int64_t sbk,
                 int64_t sbj, int64_t M, int64_t N, int64_t K, const float* bias, float* cf,
                 int64_t ldc, __bf16* ch, int64_t ldh, bool act, hipStream_t s) {
+  if (sak == 1 && sbk == 1 && sai % 8 == 0 && sbj % 8 == 0 && N >= 64 &&
+      ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0) {
+    // both operands K-contiguous: the LDS-tiled kernel
+    constexpr size_t lds = (size_t)2 * (GT_BM + GT_BN) * GT_LDS * sizeof(__bf16);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)gemm_nt_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+    const dim3 grid((unsigned)((M + GT_BM - 1) / GT_BM), (unsigned)((N + GT_BN - 1) / GT_BN));
+    hipLaunchKernelGGL(gemm_nt_kernel, grid, dim3(256), lds, s, A, sai, B, sbj, M, N, K, bias, cf, ldc, ch, ldh,
+                       act ? 1 : 0);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(64), 0, s, A, sai, sak, B, sbk, sbj, M, N, K,
                      bias, cf, ldc, ch, ldh, act ? 1 : 0);
@@ -199,6 +305,21 @@ __global__ void cast_weights_kernel(const float* __restrict__ w, int out, int in
   const int o = (int)(k / kin), i = (int)(k % kin);
   const float x = (o < out && i < in) ? w[(int64_t)o * in + i] : 0.0f;
   w16[(int64_t)o * kin + i] = to_bf16(x);
+}
+
+// Clears n bytes (a multiple of 4) with vector stores: used instead of a memset in
+// everything a caller may capture into a graph.
+__global__ void zero_words_kernel(uint32_t* __restrict__ p, int64_t nwords) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+hipError_t zero_async(void* p, size_t bytes, hipStream_t s) {
+  const int64_t nw = (int64_t)(bytes / 4);
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
+                     static_cast<uint32_t*>(p), nw);
+  return hipGetLastError();
 }
 
 __global__ void copy_col_kernel(const float* __restrict__ z, int64_t ld, int64_t n, float* __restrict__ y) {
@@ -642,13 +763,14 @@ int refresh_bf16(me_sur_ctx* c, hipStream_t s) {
   return e == hipSuccess ? ME_OK : shipfail(e, "weight cast");
 }
 
-// forward pass over nb rows of h[0]; the output (normalised log ME) is column 0 of z[L-1]
-int forward(me_sur_ctx* c, int64_t nb, hipStream_t s) {
+// forward pass over nb rows of h[0]; the output (normalised log ME) is column 0 of z[L-1];
+// the hidden layers' FP32 pre-activations z[l] are kept only for training (keep_z)
+int forward(me_sur_ctx* c, int64_t nb, hipStream_t s, bool keep_z = true) {
   const int L = (int)c->in.size();
   for (int l = 0; l < L; ++l) {
     const bool last = l == L - 1;
     hipError_t e = gemm(c->h[l], c->kin[l], 1, c->w16[l], 1, c->kin[l], nb, c->out[l], c->kin[l],
-                        c->b[l], c->z[l], c->outp[l], last ? nullptr : c->h[l + 1],
+                        c->b[l], (last || keep_z) ? c->z[l] : nullptr, c->outp[l], last ? nullptr : c->h[l + 1],
                         last ? 0 : c->kin[l + 1], !last, s);
     if (e != hipSuccess) return shipfail(e, "forward gemm");
   }
@@ -827,7 +949,8 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
   if (n == 0) return ME_OK;
   if (!feat || !y) return sfail(ME_EINVAL, "null pointer");
   hipStream_t st = (hipStream_t)stream;
-  const int64_t chunk = 1 << 16;
+  // rows per forward pass: many workgroup rounds of the layer products per launch
+  const int64_t chunk = 1 << 18;
   rc = ensure_batch(s, std::min<int64_t>(n, chunk));
   if (rc) return rc;
   const int L = (int)s->in.size();
@@ -836,7 +959,7 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
     hipError_t e = hipMemcpyAsync(s->h[0], feat + off * s->kin0, (size_t)nb * s->kin0 * 2,
                                   hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return shipfail(e, "feature copy");
-    rc = forward(s, nb, st);
+    rc = forward(s, nb, st, false);
     if (rc) return rc;
     hipLaunchKernelGGL(copy_col_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, s->z[L - 1],
                        (int64_t)s->outp[L - 1], nb, y + off);
@@ -862,8 +985,8 @@ int me_sur_grads(me_surrogate s, const uint16_t* feat, const float* target, int6
   // output layer gradient (column 0), row stride outp of the last layer
   const int64_t ldo = s->outp[L - 1];
   const unsigned nblk = (unsigned)((nb + 255) / 256);
-  e = hipMemsetAsync(s->dzf, 0, (size_t)nb * ldo * 4, st);
-  if (e == hipSuccess) e = hipMemsetAsync(s->dzh, 0, (size_t)nb * ldo * 2, st);
+  e = zero_async(s->dzf, (size_t)nb * ldo * 4, st);
+  if (e == hipSuccess) e = zero_async(s->dzh, (size_t)nb * ldo * 2, st);
   if (e != hipSuccess) return shipfail(e, "gradient clear");
   hipLaunchKernelGGL(output_grad_kernel, dim3(nblk), dim3(256), 0, st, s->z[L - 1], ldo, target, nb, s->dzf,
                      s->dzh, ldo, s->partial);

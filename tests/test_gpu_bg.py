@@ -2,8 +2,9 @@
 process, FP64 within 1e-12 per event (extended-precision adjudication), the
 split-precision colour sums within their bound, gg -> tt gggg at its full
 32768-event size on the stored oracle values, and the helicity-recycling kernel
-(launch variant 3, and 4 with the FP64 colour form fused into it) on gg -> tt gg
-and gg -> tt ggg, up to the full 262144-event workload."""
+(launch variant 3, and 4 / 5 with the colour form and helicity sum fused into it,
+chunked / persistent) on gg -> tt gg and gg -> tt ggg, up to the full
+262144-event workload."""
 import os
 import time
 
@@ -96,7 +97,7 @@ def test_bg_matches_team_program_ggttgggg(binding):
     assert np.max(np.abs(bg / team - 1)) < 1e-10
 
 
-@pytest.mark.parametrize('variant', [3, 4])
+@pytest.mark.parametrize('variant', [3, 4, 5])
 @pytest.mark.parametrize('name,nevt,seed', [('gg_ttxgg', 64 * 3 + 5, 1006), ('gg_ttxgg', 1, 9),
                                             ('gg_ttxgg', 8 * 512 + 3, 1002), ('gg_ttxggg', 3, 1003),
                                             ('gg_ttxggg', 130, 1007)])
@@ -108,7 +109,7 @@ def test_bg_recycling_vs_oracle(binding, name, nevt, seed, variant):
     assert_parity(gpu, mom, npar)
 
 
-@pytest.mark.parametrize('variant', [3, 4])
+@pytest.mark.parametrize('variant', [3, 4, 5])
 def test_bg_recycling_ggttggg_golden_and_mixed(binding, variant):
     _say(f'case bg recycling gg_ttxggg golden 197 events, variant {variant}; split FP16 / BF16 colour sums')
     g = np.load(os.path.join(GOLDEN, 'gg_ttxggg_seed1003_first197.npz'))
@@ -122,19 +123,27 @@ def test_bg_recycling_ggttggg_golden_and_mixed(binding, variant):
 
 
 def test_bg_fused_colour_matches_colour_kernel(binding):
-    _say('case bg recycling: fused FP64 colour form (variant 4) against the colour kernel (variant 3)')
+    _say('case bg recycling: colour form and helicity sum fused (variants 4, 5) against the colour and '
+         'reduction kernels (variant 3), FP64 and split FP16 / BF16')
     for name, npar, nevt, seed in (('gg_ttxgg', 6, 8 * 300 + 5, 31), ('gg_ttxggg', 7, 515, 32)):
         mom = rambo.generate(npar, nevt, seed)
-        a, _ = _bg(binding, name, mom, variant=3)
-        b, _ = _bg(binding, name, mom, variant=4)
-        rel = np.abs(b / a - 1)
-        _say(f'  {name}: max rel {rel.max():.3e}')
-        # the same products summed in another order (block-triangular matrix, row
-        # dots per block row)
-        assert rel.max() < 1e-13
+        for mode in (0, 1, 2):
+            a, _ = _bg(binding, name, mom, mode, variant=3)
+            for v in (4, 5):
+                b, _ = _bg(binding, name, mom, mode, variant=v)
+                rel = np.abs(b / a - 1)
+                _say(f'  {name} mode {mode} variant {v}: max rel {rel.max():.3e}')
+                if mode == 0:
+                    # the same products summed in another order (block-triangular
+                    # matrix, row dots per block row)
+                    assert rel.max() < 1e-13
+                else:
+                    # the same split-precision products in the same order; only the
+                    # FP64 scaling of the row sums differs
+                    assert rel.max() < 1e-12
 
 
-@pytest.mark.parametrize('variant', [3, 4])
+@pytest.mark.parametrize('variant', [3, 4, 5])
 def test_bg_recycling_ggttggg_full_size(binding, variant):
     _say(f'case bg recycling gg_ttxggg 262144 events (the full workload), variant {variant}: sampled golden '
          'events, every event against the row kernel')

@@ -37,7 +37,7 @@ def test_every_candidate_matches_the_oracle(binding):
             (1, 1, 1, 4096), (1, 2, 1, 4096)]
     cases = [('lane',) + c for c in lane] + [('team', 0, 1, 0, tw) for tw in (1024, 262144, 1048576)]
     cases += [('split', w, f, r) for w in (1, 2) for f in (8, 16, 32) for r in (0, 2)]
-    cases += [('bg', v) for v in (0, 1, 2, 3, 4)]
+    cases += [('bg', v) for v in (0, 1, 2, 3, 4, 5)]
     for c in cases:
         m = binding.MatrixElement('gg_ttxggg')
         if c[0] == 'lane':
@@ -68,8 +68,8 @@ def test_every_candidate_matches_the_oracle(binding):
     with pytest.raises(binding.MeError):
         binding.MatrixElement('gg_ttxgggg').me_set_split(1, 16, 0, 0)
     with pytest.raises(binding.MeError):
-        binding.MatrixElement('gg_ttxggg').me_set_bg(5)
-    for v in (3, 4):
+        binding.MatrixElement('gg_ttxggg').me_set_bg(6)
+    for v in (3, 4, 5):
         with pytest.raises(binding.MeError):
             binding.MatrixElement('gg_ttxgggg').me_set_bg(v)   # helicity recycling: four and five gluons
 

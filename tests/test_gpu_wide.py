@@ -115,7 +115,7 @@ def test_ggtt_mixed_bound(binding):
         _check_mixed('gg_ttx', mode, gpu, ref, np.arange(len(k)), k)
 
 
-@pytest.mark.parametrize('executor,variant', [(2, None), (3, 3), (3, 4)])
+@pytest.mark.parametrize('executor,variant', [(2, None), (3, 3), (3, 4), (3, 5)])
 def test_ggttggg_first16384(binding, executor, variant):
     _say(f'case wide gg_ttxggg first 16384 of 262144 events (executor {executor}, variant {variant}), '
          'FP64 and split FP16')
