@@ -32,6 +32,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6      # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flops/c
 # reports them.
 TRAFFIC_KEY = ('persistent', 'hel_per_item', 'executor', 'split_wpe', 'split_rounds', 'bg_variant')
 MEASURED_TRAFFIC = {
+    # helicity-recycling kernel with the colour form and helicity sum fused, 16 launches per call
+    ('gg_ttxggg', 262144, (0, 0, 3, 0, 0, 4)): (8.099e9, 'profiles/bgh_kernel_gg_ttxggg_262144.md'),
 }
 
 NPAR = {'gg_ttx': 4, 'gg_ttxg': 5, 'gg_ttxgg': 6, 'gg_ttxggg': 7, 'gg_ttxgggg': 8}
@@ -339,9 +341,9 @@ def main():
         traffic = MEASURED_TRAFFIC.get(key)
     executor = (tuned or {}).get('executor', 0)
     bg_variant = (tuned or {}).get('bg_variant', 0)
+    bgk = {0: 'bg_kernel', 1: 'bg_kernel', 2: 'bg_kernel', 3: 'bgh_kernel'}.get(bg_variant, 'bgh_fused_kernel')
     kname = {1: f'team_kernel<{process}_team>', 2: f'sums_kernel<{process}>',
-             3: f'bg{"h" if bg_variant >= 3 else ""}_kernel<{NPAR[process] - 2}>'}.get(executor,
-                                                                                     f'me_kernel<{process}>')
+             3: f'{bgk}<{NPAR[process] - 2}>'}.get(executor, f'me_kernel<{process}>')
     ncol = {'gg_ttx': 2, 'gg_ttxg': 6, 'gg_ttxgg': 24, 'gg_ttxggg': 120, 'gg_ttxgggg': 720}[process]
     cname = (f'colour_f64_tri_kernel<{ncol}>' if ncol > 128 else f'colour_f64_kernel<{ncol}>') \
         if executor in (2, 3) else 'colour_mfma_kernel'

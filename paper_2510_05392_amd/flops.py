@@ -201,17 +201,17 @@ def diagram_kernel(name, executor, bg_variant=0):
     colour form is a kernel of its own; with helicity recycling (launch variant 3)
     the kernel's flops per event divided by the 2^npar helicity rows (every helicity
     of these processes is good), and with the FP64 colour form fused into it
-    (variant 4) the triangular colour form of each row on top (algorithmic count;
-    the matrix cores execute the block-triangular product)."""
+    (variants 4 and 5) the triangular colour form of each row on top (algorithmic
+    count; the matrix cores execute the block-triangular product)."""
     if executor == 2:
         return group_sums_flops(name) + QUARK_BRANCH_MEAN
     if executor == 3:
         from .gen import codegen
         npar = codegen.PROCESS_NPAR[name]
-        if bg_variant in (3, 4):
+        if bg_variant in (3, 4, 5):
             # per event over every helicity, shared out over the 2^npar rows
             f = (bgh_event(npar - 2)['total'] + 6 * QUARK_BRANCH_MEAN) / 2 ** npar
-            if bg_variant == 4:
+            if bg_variant in (4, 5):
                 from .gen.colour import colour_matrix
                 cf, _ = colour_matrix(npar - 2)
                 f += colour_sum_flops(cf)
