@@ -11,7 +11,11 @@
 // significant bits, BF16 8: a matrix that needs more is split into hi + lo, both
 // exact, and applied twice).
 // FP16 rows are first scaled by an exact power of two so that max |X| is in
-// [1, 2); the scale is undone on the FP64 result.
+// [1, 2); the scale is undone on the FP64 result.  Both parts are rounded to the
+// format through FP32 (native conversions; a direct FP64 -> FP16 rounding is a
+// long integer sequence): hi = rn(rn32(x)) is within (2^-p + 2^-24)|x| of x, so
+// the residual x - hi - lo stays within 2^-2p (1 + 2^-(24-p))|x|, p = 11 (FP16)
+// or 8 (BF16).
 //
 // MFMA operand layouts (32x32x16, wave64): A[i][k]: lane l holds i = l % 32,
 // k = 8 (l / 32) + t (t = 0..7); B[k][j]: j = l % 32, k = 8 (l / 32) + t;
@@ -27,6 +31,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 enum { CS_FMT_FP16 = 0, CS_FMT_BF16 = 1 };
+
+// x rounded to the MFMA format through FP32 with the native conversions.  The
+// FP32 value is made opaque: folded into one FP64 -> FP16 rounding, the compiler
+// emits a long integer sequence for it.
+template <typename E>
+__device__ __forceinline__ E cs_round(double x) {
+  float f = (float)x;
+  asm volatile("" : "+v"(f));
+  return (E)f;
+}
 
 template <int FMT>
 struct cs_types;
@@ -109,9 +123,9 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
         for (int t = 0; t < 8; ++t) {
           const int c = 16 * kk + 8 * half + t;
           const double v = (c < NCOL && valid) ? x[2 * c * st] * scale : 0.0;
-          const elem hi = (elem)v;
+          const elem hi = cs_round<elem>(v);
           bh[t] = hi;
-          bl[t] = (elem)(v - (double)hi);
+          bl[t] = cs_round<elem>(v - (double)hi);
         }
         const int idx = ((32 * mb + j) * KP + 16 * kk + 8 * half) / 8;
         const vec a = cf_hi[idx];
@@ -143,9 +157,9 @@ __global__ void __launch_bounds__(64) colour_mfma_kernel(const double* __restric
     for (int t = 0; t < 8; ++t) {
       const int c = 16 * kk + 8 * half + t;
       const double v = (c < NCOL && valid) ? x[2 * c * st] * scale : 0.0;
-      const elem hi = (elem)v;
+      const elem hi = cs_round<elem>(v);
       bh[t] = hi;
-      bl[t] = (elem)(v - (double)hi);
+      bl[t] = cs_round<elem>(v - (double)hi);
     }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {

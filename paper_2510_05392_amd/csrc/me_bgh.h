@@ -615,9 +615,9 @@ __device__ __forceinline__ void bgh_colour_rows_split(const double* __restrict__
       for (int t = 0; t < 8; ++t) {
         const int c = 16 * kk + 8 * half + t;
         const double v = (c < NCOL && valid) ? x[(int64_t)(2 * c) * rs] * scale : 0.0;
-        const elem hi = (elem)v;
+        const elem hi = cs_round<elem>(v);
         bh[t] = hi;
-        bl[t] = (elem)(v - (double)hi);
+        bl[t] = cs_round<elem>(v - (double)hi);
       }
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {

@@ -9,8 +9,9 @@ configurations the benchmark uses.
                    1003), FP64 and split FP16 on the split executor and on the
                    helicity-recycling Berends-Giele kernel (with and without the
                    fused FP64 colour form);
-  gg -> tt gggg    the first 256 events of the 32768-event workload (seed 1005),
-                   FP64 and split FP16 (team program);
+  gg -> tt gggg    the first 1024 events of the 32768-event workload (seed 1005)
+                   and 24 sampled over it, FP64 and split FP16 (team program and
+                   Berends-Giele rows);
   uneven batch     the first 1024 events of each segment, one persistent launch.
 
 FP64 is held to 1e-12 relative per event with extended-precision adjudication
@@ -136,19 +137,25 @@ def test_ggttggg_first16384(binding, executor, variant):
     _check_mixed('gg_ttxggg', 1, mixed[idx], ref, np.arange(n, n + len(k)), k)
 
 
-def test_ggttgggg_first256(binding):
-    _say('case wide gg_ttxgggg first 256 of 32768 events (team program), FP64; split FP16 on the first 1024')
-    g = _golden('gg_ttxgggg_seed1005_first256.npz')
+@pytest.mark.parametrize('executor,variant', [(1, None), (3, 2)])
+def test_ggttgggg_first1024(binding, executor, variant):
+    _say(f'case wide gg_ttxgggg first 1024 of 32768 events (executor {executor}, variant {variant}), FP64 and '
+         'split FP16')
+    g = _golden('gg_ttxgggg_seed1005_first1024.npz')
     s = _golden('gg_ttxgggg_seed1005_n32768_sampled.npz')
-    mom = rambo.generate(8, 32768, 1005)
-    gpu = _run(binding, 'gg_ttxgggg', mom)
+    full = rambo.generate(8, 32768, 1005)
     n = len(g['me'])
-    # no extended-precision values are stored for these 256 events: each must agree
+    # the Berends-Giele kernel (the benchmark's) runs the whole workload, the team
+    # program the parity set alone
+    mom = full if executor == 3 else np.concatenate([full[:n], full[s['index']]])
+    gpu = _run(binding, 'gg_ttxgggg', mom, executor, variant=variant)
+    sampled = gpu[s['index']] if executor == 3 else gpu[n:]
+    # no extended-precision values are stored for these events: each must agree
     # with the FP64 oracle itself to 1e-12
-    assert_parity(gpu[:n], mom[:n], 8, me64=g['me'], me_ext=g['me'])
-    assert_parity(gpu[s['index']], mom[s['index']], 8, me64=s['me'], me_ext=s['me_ext'])
-    mixed = _run(binding, 'gg_ttxgggg', mom[:1024], None, 1)
-    rel = np.abs(mixed / gpu[:1024] - 1)
+    assert_parity(gpu[:n], full[:n], 8, me64=g['me'], me_ext=g['me'])
+    assert_parity(sampled, s['momenta'], 8, me64=s['me'], me_ext=s['me_ext'])
+    mixed = _run(binding, 'gg_ttxgggg', full[:n], executor, 1, variant=variant)
+    rel = np.abs(mixed / gpu[:n] - 1)
     _say(f'  split FP16 vs FP64: max rel {rel.max():.3e}, rms {np.sqrt(np.mean(rel ** 2)):.3e}')
     assert rel.max() < 1e-5
 
