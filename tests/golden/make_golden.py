@@ -6,7 +6,7 @@ from the HIP path.  Run from the repository root:
     python tests/golden/make_golden.py [ggttggg] [ggttgggg] [sde_ggttggg] [wide_c1] ...
 
 (the wide_* sets run the oracle on every host core; wide_c2 takes about ten
-minutes of eight cores, wide_c4a about four minutes per eight events)
+minutes of eight cores, wide_c4a about half an hour)
 """
 import os
 import sys
@@ -106,10 +106,11 @@ def wide_c2():
     _save('gg_ttxggg_seed1003_first16384.npz', me=pooled_values(7, mom))
 
 
-def wide_c4a(n=256):
-    # g g -> t tbar g g g g, the first n events of the 32768-event workload (seed 1005)
+def wide_c4a(n=1024):
+    # g g -> t tbar g g g g, the first n events of the 32768-event workload (seed 1005);
+    # 64-event chunks (about 15 minutes each on one core)
     mom = rambo.generate(8, n, 1005)
-    _save(f'gg_ttxgggg_seed1005_first{n}.npz', me=pooled_values(8, mom, chunk=4))
+    _save(f'gg_ttxgggg_seed1005_first{n}.npz', me=pooled_values(8, mom, chunk=64))
 
 
 def wide_c4b():

@@ -77,7 +77,7 @@ def test_bg_ggttgggg_full_size(binding):
     idx = s['index']
     assert np.array_equal(mom[idx], s['momenta'])
     assert_parity(gpu[idx], mom[idx], 8, me64=s['me'], me_ext=s['me_ext'], nrot=0)
-    path = os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first256.npz')
+    path = os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first1024.npz')
     if os.path.exists(path):
         g = np.load(path)
         n = len(g['me'])

@@ -141,11 +141,7 @@ def test_ggttggg_first16384(binding, executor, variant):
 def test_ggttgggg_first1024(binding, executor, variant):
     _say(f'case wide gg_ttxgggg first 1024 of 32768 events (executor {executor}, variant {variant}), FP64 and '
          'split FP16')
-    # the first 1024 events (the first 256 where only that shorter set is stored)
-    name = 'gg_ttxgggg_seed1005_first1024.npz'
-    if not os.path.exists(os.path.join(GOLDEN, name)):
-        name = 'gg_ttxgggg_seed1005_first256.npz'
-    g = _golden(name)
+    g = _golden('gg_ttxgggg_seed1005_first1024.npz')
     s = _golden('gg_ttxgggg_seed1005_n32768_sampled.npz')
     full = rambo.generate(8, 32768, 1005)
     n = len(g['me'])
