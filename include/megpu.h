@@ -394,7 +394,10 @@ int me_sur_set_normalisation(me_surrogate s, const float* mean, const float* inv
  * and the raw log invariants raw[nevt][nfeat] (FP32) when raw is not NULL */
 int me_sur_features(me_surrogate s, const double* momenta, int64_t nevt, int npar, uint16_t* feat,
                     float* raw, void* stream);
-/* y[n] = network output (normalised log|M|^2) for feature rows feat[n] */
+/* y[n] = network output (normalised log|M|^2) for feature rows feat[n].  For hidden
+ * widths that are multiples of 32 up to 256 (and 16-byte aligned feat) the whole
+ * network runs in one kernel with the activations kept in registers; other widths
+ * run layer by layer through the handle's activation buffers. */
 int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, void* stream);
 /* loss gradients for a batch (targets: normalised log|M|^2, FP32); the batch's
  * summed squared error is added to *loss (device scalar) when loss is not NULL */
@@ -423,8 +426,9 @@ int me_unweight_stage2(const double* me_exact, const int64_t* idx, int64_t m, co
                        const double* what, const double* r2, double what_max, double x_max, double* resid,
                        void* stream);
 
-/* Introspection for tests: the activations of the last forward pass (me_sur_predict
- * or me_sur_grads; of the last chunk of 262144 rows for larger predictions), first
+/* Introspection for tests: the activations of the last layer-by-layer forward pass
+ * (me_sur_grads, or me_sur_predict on the widths it runs layer by layer; of the last
+ * chunk of 262144 rows for larger predictions), first
  * `rows` rows, copied to host[rows][n]: kind 0 = the input of linear layer `layer`
  * (BF16 values as FP32, n = its input width; layer 0 = the feature rows), kind 1 =
  * its output before the activation (FP32, n = its output width; for the hidden

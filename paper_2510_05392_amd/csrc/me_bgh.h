@@ -353,15 +353,22 @@ __device__ __forceinline__ void bgh_item_current(const double* F, const BghItem<
   for (int u = 0; u < 4; ++u) out[u] = f3 * a3[u] + f4 * a4[u];
 }
 
+// Observer of the amplitudes a cycle item writes: note(k, re, im) for row k of the
+// event.  The default observes nothing.
+struct BghNoNote {
+  template <typename R>
+  __device__ __forceinline__ void operator()(int, R, R) const {}
+};
+
 // One work item: cycle z, gluon helicities gh (bit b = helicity + of gluon b), the
 // N rotations sigma_i (segment (i, N)) and the four quark helicity pairs.
 // krow[2 u + v] = good-helicity row of (gh, u, v) or -1; the amplitude of flow c
 // goes to jt[2 c][row0 + k] (real) and jt[2 c + 1][row0 + k] (imaginary), row0 =
 // this event's first row.
-template <int N>
+template <int N, typename Note = BghNoNote>
 __device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& cy, const BghItem<N>& it, int z,
                                                const int* krow, double mt, double* __restrict__ jt, int64_t rows,
-                                               int64_t row0) {
+                                               int64_t row0, Note note = Note()) {
   using S = BgShape<N>;
   using H = BghShape<N>;
   constexpr int LR = H::LR;
@@ -434,6 +441,7 @@ __device__ __forceinline__ void bgh_cycle_item(const double* F, const BgCycles& 
         const cx a = cx{qj.r - g * wv.i, qj.i + g * wv.r};
         jt[(int64_t)(2 * col) * rows + row0 + k] = a.r;
         jt[(int64_t)(2 * col + 1) * rows + row0 + k] = a.i;
+        note(k, a.r, a.i);
       }
     }
     bgh_copy(cnext, ccur);
@@ -549,99 +557,145 @@ __device__ __forceinline__ void bgh_colour_rows(const double* __restrict__ jt, i
   }
 }
 
+// Records, for each row of an event, the largest |Re| and |Im| of its amplitudes
+// (bits of a non-negative double, which order as the unsigned integers) with LDS
+// atomics: the power-of-two scale of the FP16 colour form without a pass over the
+// row.
+struct BghRowMax {
+  unsigned long long* m;
+  __device__ __forceinline__ void operator()(int k, double re, double im) const {
+    atomicMax(m + k, (unsigned long long)__double_as_longlong(fmax(fabs(re), fabs(im))));
+  }
+};
+
+// Split-precision colour matrix staged in LDS for the fused kernel: flows in blocks
+// of 32, the block-triangular form (blocks (mb, kb), kb >= mb: CF on the diagonal,
+// 2 CF above; the same quadratic form as CF; the doubled entries stay exact), the
+// 32 rows of each block permuted so that a lane's accumulator rows are the flows
+// of its own B operand (M index i = 8 q + 4 h + s, q < 4, h < 2, s < 4 holds flow
+// 16 (q >> 1) + 8 h + 4 (q & 1) + s), rows of BGH_SV 16-byte vectors (4 + 1: the
+// pad puts the 16-byte reads of 8 consecutive rows on distinct banks).
+constexpr int BGH_SV = 5;
+template <int NCOL>
+struct BghSplit {
+  static constexpr int MB = (NCOL + 31) / 32;
+  static constexpr int NBLK = MB * (MB + 1) / 2;
+  static constexpr int VECS = NBLK * 32 * BGH_SV;   // 16-byte vectors per table
+  static constexpr int blk(int mb, int kb) { return mb * MB - mb * (mb - 1) / 2 + (kb - mb); }
+  static __device__ __forceinline__ int flow(int i) {
+    return 16 * (i >> 4) + 8 * ((i >> 2) & 1) + 4 * ((i >> 3) & 1) + (i & 3);
+  }
+};
+
 // Split-precision colour form (FMT = CS_FMT_FP16 or CS_FMT_BF16) of the rows
-// 0 .. nr - 1 of jt [2 NCOL][rows], by the whole workgroup, as colour_mfma_kernel
-// forms it: one wave per tile of 16 rows, each row split into hi + lo in the format
-// (FP16 rows first scaled by a power of two, exact), v_mfma_f32_32x32x16 against
-// the exact colour matrix, FP64 row dots.  The matrix's high part is staged in LDS
-// (cfs: 32 MB x 16 KS elements), its low part, when the format needs one, read from
-// global memory.  out[row] = ME_row in units of the integer matrix.
+// 0 .. nr - 1 of jt [2 NCOL][rows], by the whole workgroup: one wave per tile of 16
+// rows (32 B columns: real and imaginary parts), each row split into hi + lo in the
+// format (FP16 rows first scaled by the power of two that puts their largest
+// element, rmax[row], in [1, 2): exact), v_mfma_f32_32x32x16 against the staged
+// block-triangular matrix, FP64 row dots.  The column blocks kb are taken from the
+// last to the first, so that the rows of block kb are complete once kb is done and
+// their dots use the amplitudes just loaded for it: every amplitude is read once.
+// cf_hi / cf_lo: the format's [32 MB][16 KS] tables (cf_lo may be null); cfs holds
+// 2 BghSplit<NCOL>::VECS vectors.  out[row] = ME_row in units of the integer matrix.
 template <int NCOL, int FMT, int THREADS>
 __device__ __forceinline__ void bgh_colour_rows_split(const double* __restrict__ jt, int64_t rows, int nr,
                                                       const void* __restrict__ cf_hi_raw,
                                                       const void* __restrict__ cf_lo_raw, void* cfs_raw,
-                                                      double* __restrict__ out) {
+                                                      const unsigned long long* rmax, double* __restrict__ out) {
   typedef cs_types<FMT> T;
   typedef typename T::vec vec;
   typedef typename T::elem elem;
-  constexpr int KS = (NCOL + 15) / 16, MB = (NCOL + 31) / 32, KP = KS * 16;
+  using B = BghSplit<NCOL>;
+  constexpr int MB = B::MB;
+  constexpr int KP = 16 * ((NCOL + 15) / 16);   // row length of the global tables
   vec* cfs = reinterpret_cast<vec*>(cfs_raw);
-  const vec* cf_hi = reinterpret_cast<const vec*>(cf_hi_raw);
-  const vec* cf_lo = reinterpret_cast<const vec*>(cf_lo_raw);
-  for (int i = threadIdx.x; i < 32 * MB * KP / 8; i += THREADS) cfs[i] = cf_hi[i];
+  const bool two = cf_lo_raw != nullptr;
+  for (int i = threadIdx.x; i < (two ? 2 : 1) * B::NBLK * 128; i += THREADS) {
+    const int tb = i / (B::NBLK * 128), rem = i % (B::NBLK * 128);
+    const int b = rem >> 7, row = (rem >> 2) & 31, w = rem & 3;
+    int mb = 0;
+    while (mb + 1 < MB && B::blk(mb + 1, mb + 1) <= b) ++mb;
+    const int kb = mb + (b - B::blk(mb, mb));
+    const int fa = 32 * mb + B::flow(row), col = 32 * kb + 8 * w;
+    vec v;
+    if (fa < NCOL && col < KP) {
+      v = reinterpret_cast<const vec*>(tb ? cf_lo_raw : cf_hi_raw)[(fa * KP + col) / 8];
+      if (kb > mb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = (elem)(2.0f * (float)v[t]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = (elem)0.0f;
+    }
+    cfs[tb * B::VECS + (b * 32 + row) * BGH_SV + w] = v;
+  }
   __syncthreads();
   const int l = threadIdx.x & 63;
   const int j = l & 31, r = j & 15, part = j >> 4;
   const int ntile = (nr + 15) >> 4;
   for (int tile = threadIdx.x >> 6; tile < ntile; tile += THREADS / 64) {
-    // the row stride is made opaque in each tile so that the flow offsets are formed
-    // as the loads need them, not hoisted out of the loops (64 of them would spill)
+    // the row stride and the lane's K half are opaque in each tile, so that the flow
+    // offsets are formed as the loads need them, not hoisted out of the loops
     int64_t rs = rows;
-    int half = l >> 5;   // the lane's K half, likewise formed in each tile
+    int half = l >> 5;
     asm volatile("" : "+s"(rs), "+v"(half) : : "memory");
     const int row = 16 * tile + r;
     const bool valid = row < nr;
     const double* x = jt + (int64_t)part * rs + (valid ? row : 0);
     double scale = 1.0, unscale = 1.0;
     if (FMT == CS_FMT_FP16) {
-      double m = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int c = 16 * kk + 8 * half + t;
-          if (c < NCOL && valid) m = fmax(m, fabs(x[(int64_t)(2 * c) * rs]));
-        }
-      m = fmax(m, __shfl_xor(m, 16));
-      m = fmax(m, __shfl_xor(m, 32));
+      const double m = valid ? __longlong_as_double((long long)rmax[row]) : 0.0;
       if (m > 0.0) {
         const int e = ilogb(m);
         scale = ldexp(1.0, -e);
         unscale = ldexp(1.0, e);
       }
     }
-    // the amplitudes are read again (from cache) by each pass rather than held in
-    // registers across them
-    asm volatile("" ::: "memory");
+    const vec* ap = cfs + j * BGH_SV + half;
     f32x16 acc[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[mb][v] = 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      vec bh, bl;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int c = 16 * kk + 8 * half + t;
-        const double v = (c < NCOL && valid) ? x[(int64_t)(2 * c) * rs] * scale : 0.0;
-        const elem hi = cs_round<elem>(v);
-        bh[t] = hi;
-        bl[t] = cs_round<elem>(v - (double)hi);
-      }
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int idx = ((32 * mb + j) * KP + 16 * kk + 8 * half) / 8;
-        const vec a = cfs[idx];
-        acc[mb] = T::mfma(a, bh, acc[mb]);
-        acc[mb] = T::mfma(a, bl, acc[mb]);
-        if (cf_lo) {
-          const vec a2 = cf_lo[idx];
-          acc[mb] = T::mfma(a2, bh, acc[mb]);
-          acc[mb] = T::mfma(a2, bl, acc[mb]);
-        }
-      }
-    }
-    asm volatile("" ::: "memory");
     double sum = 0.0;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int kb = MB - 1; kb >= 0; --kb) {
+      double xv[2][8];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int i = 32 * mb + 8 * (v >> 2) + 4 * half + (v & 3);
-        if (i < NCOL && valid) sum += x[(int64_t)(2 * i) * rs] * (double)acc[mb][v];
+      for (int ss = 0; ss < 2; ++ss)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int c = 32 * kb + 16 * ss + 8 * half + t;
+          xv[ss][t] = (c < NCOL && valid) ? x[(int64_t)(2 * c) * rs] : 0.0;
+        }
+#pragma unroll
+      for (int ss = 0; ss < 2; ++ss) {
+        vec bh, bl;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const double v = xv[ss][t] * scale;
+          const elem hi = cs_round<elem>(v);
+          bh[t] = hi;
+          bl[t] = cs_round<elem>(v - (double)hi);
+        }
+#pragma unroll
+        for (int mb = 0; mb <= kb; ++mb) {
+          const vec a = ap[B::blk(mb, kb) * 32 * BGH_SV + 2 * ss];
+          acc[mb] = T::mfma(a, bh, acc[mb]);
+          acc[mb] = T::mfma(a, bl, acc[mb]);
+          if (two) {
+            const vec a2 = ap[B::VECS + B::blk(mb, kb) * 32 * BGH_SV + 2 * ss];
+            acc[mb] = T::mfma(a2, bh, acc[mb]);
+            acc[mb] = T::mfma(a2, bl, acc[mb]);
+          }
+        }
       }
-    sum += __shfl_xor(sum, 32);   // the two halves of the M rows
+      // rows of block kb: D element v is M row i = 8 (v >> 2) + 4 half + (v & 3),
+      // flow 32 kb + 16 (v >> 3) + 8 half + 4 ((v >> 2) & 1) + (v & 3)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) sum += xv[v >> 3][4 * ((v >> 2) & 1) + (v & 3)] * (double)acc[kb][v];
+    }
+    sum += __shfl_xor(sum, 32);   // the two K halves
     sum += __shfl_xor(sum, 16);   // real + imaginary parts
     if (l < 16 && valid) out[row] = sum * unscale;
   }
@@ -658,10 +712,14 @@ __device__ __forceinline__ void bgh_block(double* lds, const uint8_t* sm, uint16
                                           const double* __restrict__ mom, int64_t e0, int nev, double g0,
                                           double mt, int nhel, const BgTables& t, const BgCycles& cy,
                                           const double* __restrict__ alphas, double* __restrict__ jt, int64_t rows,
-                                          int64_t rbase) {
+                                          int64_t rbase, unsigned long long* rmax = nullptr) {
   using S = BgShape<N>;
   using H = BghShape<N>;
   constexpr int NPAR = N + 2;
+  // rmax (optional, LDS): largest |Re|, |Im| of the amplitudes of each row, at
+  // ev nhel + k
+  if (rmax)
+    for (int i = threadIdx.x; i < nev * nhel; i += THREADS) rmax[i] = 0ull;
   for (int i = threadIdx.x; i < nev * NPAR * 4; i += THREADS)
     lds[(i / (NPAR * 4)) * H::FRAME + H::MOFF + i % (NPAR * 4)] = mom[e0 * NPAR * 4 + i];
   for (int i = threadIdx.x; i < nev; i += THREADS)
@@ -695,7 +753,11 @@ __device__ __forceinline__ void bgh_block(double* lds, const uint8_t* sm, uint16
     if (krow[0] < 0 && krow[1] < 0 && krow[2] < 0 && krow[3] < 0) continue;
     bgh_fill_item<N>(tab, THREADS, t, cy, z, gh);
     const BghItem<N> item{tab, THREADS, sm + z * N * N};
-    bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, rbase + (int64_t)ev * nhel);
+    if (rmax)
+      bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, rbase + (int64_t)ev * nhel,
+                        BghRowMax{rmax + ev * nhel});
+    else
+      bgh_cycle_item<N>(lds + ev * H::FRAME, cy, item, z, krow, mt, jt, rows, rbase + (int64_t)ev * nhel);
   }
 }
 
@@ -755,8 +817,8 @@ bgh_fused_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt
   using H = BghShape<N>;
   using C = BghColour<S::NCOL>;
   // row values after the staged matrix (float index, even): the FP64 form's
-  // block-triangular FP32 blocks, or the split forms' 32 MB x 16 KS table
-  constexpr int SPLIT_FLOATS = 32 * ((S::NCOL + 31) / 32) * 16 * ((S::NCOL + 15) / 16) / 2;
+  // block-triangular FP32 blocks, or the split forms' two block-triangular tables
+  constexpr int SPLIT_FLOATS = 2 * BghSplit<S::NCOL>::VECS * 4;
   constexpr int RV = ((FMT < 0 ? C::FLOATS : SPLIT_FLOATS) + 1) & ~1;
   static_assert(RV * sizeof(float) + (size_t)EV * (1 << (N + 2)) * sizeof(double) <=
                     (size_t)EV * H::FRAME * sizeof(double),
@@ -767,6 +829,8 @@ bgh_fused_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt
   float* cfs = reinterpret_cast<float*>(lds);
   double* rv = reinterpret_cast<double*>(cfs + RV);
   __shared__ int hrow[1 << (N + 2)];
+  // the rows' largest amplitude components (FP16 scaling), written by the cycle items
+  __shared__ unsigned long long rmax[FMT == CS_FMT_FP16 ? EV << (N + 2) : 1];
   bgh_tables<N, THREADS>(hrow, sm, hels, nhel, t, cy);
   const int64_t srows = (int64_t)EV * nhel;
   double* slot = jt + (int64_t)blockIdx.x * 2 * S::NCOL * srows;
@@ -774,14 +838,15 @@ bgh_fused_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt
   // (a loop over one block would keep its invariants live across iterations)
   for (int64_t e0 = (int64_t)blockIdx.x * EV; e0 < n; e0 += PERSIST ? (int64_t)gridDim.x * EV : n) {
     const int nev = (int)(n - e0 < EV ? n - e0 : EV);
-    bgh_block<N, EV, THREADS>(lds, sm, tabs, hrow, mom, e0, nev, g0, mt, nhel, t, cy, alphas, slot, srows, 0);
+    bgh_block<N, EV, THREADS>(lds, sm, tabs, hrow, mom, e0, nev, g0, mt, nhel, t, cy, alphas, slot, srows, 0,
+                              FMT == CS_FMT_FP16 ? rmax : nullptr);
     // every amplitude of the block is stored (workgroup-scope fence and barrier)
     // and the frames are no longer read
     __syncthreads();
     if constexpr (FMT < 0)
       bgh_colour_rows<S::NCOL, THREADS>(slot, srows, 0, nev * nhel, cft, cfs, rv);
     else
-      bgh_colour_rows_split<S::NCOL, FMT, THREADS>(slot, srows, nev * nhel, cf_hi, cf_lo, cfs, rv);
+      bgh_colour_rows_split<S::NCOL, FMT, THREADS>(slot, srows, nev * nhel, cf_hi, cf_lo, cfs, rmax, rv);
     __syncthreads();
     // helicity sum of each event in row order (the order of reduce_rows_kernel)
     for (int ev = threadIdx.x; ev < nev; ev += THREADS) {

@@ -36,9 +36,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU z sigma(z) and its derivative, sigma(z) = 1 / (1 + e^-z) with the hardware
+// reciprocal (within 1 ulp of FP32; the activations are rounded to BF16 after it)
+// instead of an IEEE division, which costs three times the instructions in the
+// epilogues that apply it to every output
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float dsilu(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -175,6 +180,152 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const __bf16* __restrict__
         }
       }
   }
+}
+
+// The network's layers for the fused inference kernel (at most 17 linear layers).
+struct MlpNet {
+  const __bf16* w[17];   // BF16 weights [outp][kin], zero padded
+  const float* b[17];    // biases [out]
+  int out[17];
+  int layers;
+};
+
+// Inference through the whole network in one kernel, for hidden widths 32 MB
+// (MB <= 8).  A workgroup of four waves takes 4 x 32 NT rows; each wave holds NT
+// tiles of 32 rows.  Each layer is the transposed product Z^T = W H^T on
+// v_mfma_f32_32x32x16_bf16 with the rows as the 32 B columns, the layer's weights
+// staged in LDS (rows padded by 16 bytes, so that the 16-byte reads of 8
+// consecutive rows fall on distinct banks) and read once per MFMA for all NT tiles.
+// The weight rows of each 32-row block are taken in the order M index
+// i = 8 q + 4 h + s -> output 16 (q >> 1) + 8 h + 4 (q & 1) + s, which makes the
+// accumulator elements of a lane (h = lane / 32) exactly the B operand elements of
+// the next layer that the lane supplies (inputs 16 k + 8 h + t): bias, SiLU and the
+// BF16 rounding are applied in registers and the next product starts, with nothing
+// written between layers.  Each layer sums its K steps in order, as gemm_nt_kernel
+// does, so the outputs equal the layer-by-layer forward pass.  feat: [n][kin0]
+// BF16 rows (kin0 a multiple of 16, at most 256); y[n] = the output.  Dynamic LDS:
+// mlp_infer_lds(MB, kin0) bytes.
+inline size_t mlp_infer_lds(int mb, int kin0) {
+  const int kmax = std::max(kin0, 32 * mb);
+  return (size_t)32 * mb * (kmax / 8 + 1) * 16;
+}
+template <int MB, int NT, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __restrict__ feat, int64_t n,
+                                                               int kin0, MlpNet net, float* __restrict__ y) {
+  constexpr int KS = 2 * MB, THREADS = 64 * WAVES;   // K steps of a hidden layer's input
+  constexpr int QS = 64 / WAVES;                     // staging loads in flight per thread
+  extern __shared__ bf16x8 wl[];
+  const int l = threadIdx.x & 63, h = l >> 5, j = l & 31;
+  const int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 32 * NT + j;
+  // output of A row j within a block
+  const int fj = 16 * (j >> 4) + 8 * ((j >> 2) & 1) + 4 * ((j >> 3) & 1) + (j & 3);
+  const int ks0 = kin0 >> 4;
+  bf16x8 hb[NT][16];
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int64_t e = e0 + 32 * c;
+      if (kk < ks0 && e < n) {
+        hb[c][kk] = *reinterpret_cast<const bf16x8*>(feat + e * kin0 + 16 * kk + 8 * h);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) hb[c][kk][t] = to_bf16(0.0f);
+      }
+    }
+  // one layer's weights [rows][kv vectors] into LDS rows of kv + 1 vectors, QS
+  // loads in flight per thread
+  auto stage = [&](const __bf16* __restrict__ w, int rows, int kv) {
+    __syncthreads();   // the previous layer's reads are done
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(w);
+    const int total = rows * kv;
+    for (int i0 = threadIdx.x; i0 < total; i0 += QS * THREADS) {
+      bf16x8 tmp[QS];
+#pragma unroll
+      for (int q = 0; q < QS; ++q)
+        if (i0 + THREADS * q < total) tmp[q] = src[i0 + THREADS * q];
+#pragma unroll
+      for (int q = 0; q < QS; ++q) {
+        const int i = i0 + THREADS * q;
+        if (i < total) wl[(i / kv) * (kv + 1) + i % kv] = tmp[q];
+      }
+    }
+    __syncthreads();
+  };
+  f32x16 acc[NT][MB];
+  auto zero = [&]() {
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[c][mb][v] = 0.0f;
+  };
+  // bias, SiLU and BF16 rounding of a hidden layer's outputs into the next B operands
+  auto activate = [&](const float* __restrict__ bias, int nout) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int o = 32 * mb + 16 * (v >> 3) + 8 * h + 4 * ((v >> 2) & 1) + (v & 3);
+        const float bo = o < nout ? bias[o] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+          hb[c][2 * mb + (v >> 3)][4 * ((v >> 2) & 1) + (v & 3)] = to_bf16(silu(acc[c][mb][v] + bo));
+      }
+  };
+  // layer 0: K = kin0
+  {
+    const int sv = ks0 * 2 + 1;
+    stage(net.w[0], 32 * MB, ks0 * 2);
+    zero();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+      if (kk < ks0)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bf16x8 a = wl[(32 * mb + fj) * sv + 2 * kk + h];
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+        }
+    activate(net.b[0], net.out[0]);
+  }
+  // hidden layers: K = 32 MB
+  constexpr int SV = 2 * KS + 1;
+  const int L = net.layers;
+  for (int ly = 1; ly + 1 < L; ++ly) {
+    stage(net.w[ly], 32 * MB, 2 * KS);
+    zero();
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 a = wl[(32 * mb + fj) * SV + 2 * kk + h];
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+          acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+      }
+    activate(net.b[ly], net.out[ly]);
+  }
+  // output layer: one 32-row block (row 0 the output, the others zero)
+  stage(net.w[L - 1], 32, 2 * KS);
+  f32x16 o[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[c][v] = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const bf16x8 a = wl[fj * SV + 2 * kk + h];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) o[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], o[c], 0, 0, 0);
+  }
+  // output 0 is accumulator element 0 of the lanes h = 0
+  const float b0 = net.b[L - 1][0];
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+    if (h == 0 && e0 + 32 * c < n) y[e0 + 32 * c] = o[c][0] + b0;
 }
 
 hipError_t gemm(const __bf16* A, int64_t sai, int64_t sak, const __bf16* B, int64_t sbk,
@@ -949,11 +1100,42 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
   if (n == 0) return ME_OK;
   if (!feat || !y) return sfail(ME_EINVAL, "null pointer");
   hipStream_t st = (hipStream_t)stream;
-  // rows per forward pass: many workgroup rounds of the layer products per launch
+  const int L = (int)s->in.size();
+  if (s->width % 32 == 0 && s->width <= 256 && ((uintptr_t)feat & 15) == 0 && (n + 127) / 128 < (1ll << 31)) {
+    // the whole network in one kernel, activations kept in registers
+    MlpNet net{};
+    for (int l = 0; l < L; ++l) {
+      net.w[l] = s->w16[l];
+      net.b[l] = s->b[l];
+      net.out[l] = s->out[l];
+    }
+    net.layers = L;
+    // four waves of two 32-row tiles each (one wave per SIMD: the accumulators of both
+    // tiles take the whole register file; each weight fragment read from LDS feeds two
+    // products)
+    constexpr int NT = 2, WAVES = 4;
+    constexpr int64_t rows_per_wg = WAVES * 32 * NT;
+    const dim3 grid((unsigned)((n + rows_per_wg - 1) / rows_per_wg));
+    const __bf16* f = reinterpret_cast<const __bf16*>(feat);
+    const int mb = s->width / 32;
+    const size_t lds = mlp_infer_lds(mb, s->kin0);
+    const void* fns[8] = {(const void*)mlp_infer_kernel<1, NT, WAVES>, (const void*)mlp_infer_kernel<2, NT, WAVES>,
+                          (const void*)mlp_infer_kernel<3, NT, WAVES>, (const void*)mlp_infer_kernel<4, NT, WAVES>,
+                          (const void*)mlp_infer_kernel<5, NT, WAVES>, (const void*)mlp_infer_kernel<6, NT, WAVES>,
+                          (const void*)mlp_infer_kernel<7, NT, WAVES>, (const void*)mlp_infer_kernel<8, NT, WAVES>};
+    hipError_t e = hipFuncSetAttribute(fns[mb - 1], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return shipfail(e, "inference kernel LDS");
+    void* args[] = {&f, &n, &s->kin0, &net, &y};
+    e = hipLaunchKernel(fns[mb - 1], grid, dim3(64 * WAVES), args, lds, st);
+    if (e != hipSuccess) return shipfail(e, "inference kernel");
+    e = hipGetLastError();
+    return e == hipSuccess ? ME_OK : shipfail(e, "inference kernel");
+  }
+  // other widths: the layer-by-layer forward pass, rows in chunks (many workgroup
+  // rounds of the layer products per launch)
   const int64_t chunk = 1 << 18;
   rc = ensure_batch(s, std::min<int64_t>(n, chunk));
   if (rc) return rc;
-  const int L = (int)s->in.size();
   for (int64_t off = 0; off < n; off += chunk) {
     const int64_t nb = std::min<int64_t>(chunk, n - off);
     hipError_t e = hipMemcpyAsync(s->h[0], feat + off * s->kin0, (size_t)nb * s->kin0 * 2,

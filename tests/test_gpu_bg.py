@@ -127,20 +127,21 @@ def test_bg_fused_colour_matches_colour_kernel(binding):
          'reduction kernels (variant 3), FP64 and split FP16 / BF16')
     for name, npar, nevt, seed in (('gg_ttxgg', 6, 8 * 300 + 5, 31), ('gg_ttxggg', 7, 515, 32)):
         mom = rambo.generate(npar, nevt, seed)
-        for mode in (0, 1, 2):
+        ref, _ = _bg(binding, name, mom, 0, variant=3)
+        for mode, bound in ((0, 1e-13), (1, 1e-5), (2, 2e-4)):
             a, _ = _bg(binding, name, mom, mode, variant=3)
             for v in (4, 5):
                 b, _ = _bg(binding, name, mom, mode, variant=v)
                 rel = np.abs(b / a - 1)
-                _say(f'  {name} mode {mode} variant {v}: max rel {rel.max():.3e}')
-                if mode == 0:
-                    # the same products summed in another order (block-triangular
-                    # matrix, row dots per block row)
-                    assert rel.max() < 1e-13
-                else:
-                    # the same split-precision products in the same order; only the
-                    # FP64 scaling of the row sums differs
-                    assert rel.max() < 1e-12
+                err = np.abs(b / ref - 1)
+                _say(f'  {name} mode {mode} variant {v}: max rel {rel.max():.3e} against the colour kernel, '
+                     f'{err.max():.3e} against FP64')
+                # FP64: the same products summed in another order (block-triangular
+                # matrix, row dots per block row); split: the block-triangular matrix
+                # too, so the FP32 sums differ and each form is held to the bound of
+                # the split colour sum against FP64
+                assert err.max() < bound
+                assert rel.max() < 2 * bound
 
 
 @pytest.mark.parametrize('variant', [3, 4, 5])

@@ -65,7 +65,7 @@ def _dsilu64(z):
 GAMMA_FP32 = 2.0 ** -24   # unit roundoff of the FP32 accumulation
 
 
-@pytest.mark.parametrize('width,depth,nb', [(256, 4, 300)])
+@pytest.mark.parametrize('width,depth,nb', [(256, 4, 300), (96, 3, 130), (48, 2, 70)])
 def test_surrogate_layers_and_gradients_elementwise(binding, width, depth, nb):
     """Every layer of the GPU network element by element against an FP64 reference
     that takes the GPU's own BF16 inputs and BF16 weights: pre-activations within
@@ -157,6 +157,14 @@ def test_surrogate_layers_and_gradients_elementwise(binding, width, depth, nb):
         z = h @ pb[l][0].T + pb[l][1]
         h = _bf16(_silu64(z)) if l + 1 < L else z
     assert np.max(np.abs(Z[L - 1][:, 0] - h[:, 0])) <= 1e-2 * max(1.0, np.abs(h).max())
+    # inference (for widths 32 MB <= 256 the whole network in one kernel, with the
+    # same products summed in the same order) against the forward pass just run
+    yp = torch.empty(nb, dtype=torch.float32, device='cuda')
+    sur.me_sur_predict(feat, nb, yp)
+    yp = yp.cpu().numpy().astype(np.float64)
+    d = np.abs(yp - Z[L - 1][:, 0])
+    _say(f'  predict vs forward pass: {int((d == 0).sum())} of {nb} identical, max abs diff {d.max():.3e}')
+    assert d.max() <= 1e-3 * max(1.0, np.abs(Z[L - 1][:, 0]).max())
 
 
 def test_adam_step_matches_reference(binding):
