@@ -113,6 +113,28 @@ def wide_c4a(n=1024):
     _save(f'gg_ttxgggg_seed1005_first{n}.npz', me=pooled_values(8, mom, chunk=64))
 
 
+def _rotate(mom, seed):
+    # one random proper rotation of the three-momenta of each event: the
+    # helicity-summed |M|^2 is unchanged, the FP64 rounding of its evaluation is not
+    rng = np.random.default_rng(seed)
+    out = np.array(mom, dtype=np.float64, copy=True)
+    for e in range(len(out)):
+        q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        out[e, :, 1:] = out[e, :, 1:] @ q.T
+    return out
+
+
+def wide_c4a_rot(n=1024, workers=None):
+    # the FP64 conditioning of the oracle on the same events: its values on one random
+    # rotation of each (two FP64 evaluations differ by about their rounding error; no
+    # extended-precision values are stored for these events)
+    mom = _rotate(rambo.generate(8, n, 1005), 4242)
+    _save(f'gg_ttxgggg_seed1005_first{n}_rot.npz', me_rot=pooled_values(8, mom, chunk=16, workers=workers))
+
+
 def wide_c4b():
     # the uneven batch: the first 1024 events of each segment
     out = {}
@@ -169,7 +191,8 @@ def kappa():
 
 
 GENERATORS = {'kappa': kappa, 'ggttggg': ggttggg, 'ggttgggg': ggttgggg, 'sde_ggttggg': sde_ggttggg,
-              'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4b': wide_c4b,
+              'wide_c1': wide_c1, 'wide_c2': wide_c2, 'wide_c4a': wide_c4a, 'wide_c4a_rot': wide_c4a_rot,
+              'wide_c4b': wide_c4b,
               'c3_labels': c3_labels}
 
 

@@ -77,11 +77,10 @@ def test_bg_ggttgggg_full_size(binding):
     idx = s['index']
     assert np.array_equal(mom[idx], s['momenta'])
     assert_parity(gpu[idx], mom[idx], 8, me64=s['me'], me_ext=s['me_ext'], nrot=0)
-    path = os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first1024.npz')
-    if os.path.exists(path):
-        g = np.load(path)
-        n = len(g['me'])
-        assert_parity(gpu[:n], mom[:n], 8, me64=g['me'], me_ext=g['me'], nrot=0)
+    g = np.load(os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first1024.npz'))
+    rot = np.load(os.path.join(GOLDEN, 'gg_ttxgggg_seed1005_first1024_rot.npz'))
+    n = len(g['me'])
+    assert_parity(gpu[:n], mom[:n], 8, me64=g['me'], me_rot=rot['me_rot'])
     mixed, _ = _bg(binding, 'gg_ttxgggg', mom[:2048], 1)
     rel = np.abs(mixed / gpu[:2048] - 1)
     _say(f'  split FP16 colour sum vs FP64: max rel {rel.max():.3e}')

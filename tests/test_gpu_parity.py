@@ -55,7 +55,7 @@ def _rotations(mom, k, seed):
     return out
 
 
-def assert_parity(gpu, mom, npar, tol=1e-12, me64=None, me_ext=None, nrot=4):
+def assert_parity(gpu, mom, npar, tol=1e-12, me64=None, me_ext=None, nrot=4, me_rot=None):
     """GPU FP64 vs oracle within `tol` relative per event, with adjudication.
 
     Events off by more than `tol` are re-evaluated by the oracle in extended
@@ -66,6 +66,11 @@ def assert_parity(gpu, mom, npar, tol=1e-12, me64=None, me_ext=None, nrot=4):
     within max(tol, 10 x that FP64 error) of the extended result, i.e. as good as
     a plain FP64 evaluation; otherwise within `tol`.  Returns the number of
     ill-conditioned events.
+
+    Where no extended-precision values exist (`me_rot` given instead: the FP64
+    oracle on a rotated copy of each event), the FP64 error is estimated by how far
+    the two FP64 oracle values are apart, and the GPU value must be within
+    max(tol, 10 x that) of the unrotated one.
     """
     if me64 is None:
         me64 = ome.matrix_element(ome.process(npar), mom, AS)
@@ -73,6 +78,15 @@ def assert_parity(gpu, mom, npar, tol=1e-12, me64=None, me_ext=None, nrot=4):
     bad = np.where(rel > tol)[0]
     if len(bad) == 0:
         return 0
+    if me_rot is not None:
+        own = np.abs(np.asarray(me_rot)[bad] / me64[bad] - 1)
+        err = rel[bad]
+        ill = own > 1e-13
+        allowed = np.where(ill, np.maximum(tol, 10 * own), tol)
+        _say(f'  adjudicated {len(bad)} events: ill-conditioned {int(ill.sum())}, '
+             f'oracle FP64 scatter {own.max():.2e}, GPU vs FP64 oracle {err.max():.2e}')
+        assert np.all(err <= allowed), (bad[err > allowed], err[err > allowed], own[err > allowed])
+        return int(ill.sum())
     if me_ext is None:
         ext = ome.matrix_element(ome.process(npar), np.asarray(mom)[bad].astype(np.longdouble),
                                  AS).astype(np.float64)

@@ -151,8 +151,10 @@ def test_ggttgggg_first1024(binding, executor, variant):
     gpu = _run(binding, 'gg_ttxgggg', mom, executor, variant=variant)
     sampled = gpu[s['index']] if executor == 3 else gpu[n:]
     # no extended-precision values are stored for these events: each must agree
-    # with the FP64 oracle itself to 1e-12
-    assert_parity(gpu[:n], full[:n], 8, me64=g['me'], me_ext=g['me'])
+    # with the FP64 oracle to 1e-12, or, where the oracle's own FP64 values on the
+    # event and on a rotated copy of it are further apart, to 10 x that
+    rot = _golden('gg_ttxgggg_seed1005_first1024_rot.npz')
+    assert_parity(gpu[:n], full[:n], 8, me64=g['me'], me_rot=rot['me_rot'])
     assert_parity(sampled, s['momenta'], 8, me64=s['me'], me_ext=s['me_ext'])
     mixed = _run(binding, 'gg_ttxgggg', full[:n], executor, 1, variant=variant)
     rel = np.abs(mixed / gpu[:n] - 1)
