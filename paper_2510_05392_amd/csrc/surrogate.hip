@@ -191,8 +191,8 @@ struct MlpNet {
 };
 
 // Inference through the whole network in one kernel, for hidden widths 32 MB
-// (MB <= 8).  A workgroup of four waves takes 4 x 32 NT rows; each wave holds NT
-// tiles of 32 rows.  Each layer is the transposed product Z^T = W H^T on
+// (MB <= 8).  A workgroup of WAVES waves takes WAVES x 32 NT rows; each wave holds
+// NT tiles of 32 rows.  Each layer is the transposed product Z^T = W H^T on
 // v_mfma_f32_32x32x16_bf16 with the rows as the 32 B columns, the layer's weights
 // staged in LDS (rows padded by 16 bytes, so that the 16-byte reads of 8
 // consecutive rows fall on distinct banks) and read once per MFMA for all NT tiles.
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __r
     zero();
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk)
-      if (kk < ks0)
+      if (kk < ks0) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           const bf16x8 a = wl[(32 * mb + fj) * sv + 2 * kk + h];
@@ -289,6 +289,8 @@ __global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __r
           for (int c = 0; c < NT; ++c)
             acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
         }
+        if (NT == 1) __builtin_amdgcn_sched_barrier(0);
+      }
     activate(net.b[0], net.out[0]);
   }
   // hidden layers: K = 32 MB
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __r
     stage(net.w[ly], 32 * MB, 2 * KS);
     zero();
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk)
+    for (int kk = 0; kk < KS; ++kk) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const bf16x8 a = wl[(32 * mb + fj) * SV + 2 * kk + h];
@@ -306,6 +308,10 @@ __global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __r
         for (int c = 0; c < NT; ++c)
           acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
       }
+      // with two waves per SIMD the weight fragments of one K step at a time keep
+      // the kernel within its 256 registers
+      if (NT == 1) __builtin_amdgcn_sched_barrier(0);
+    }
     activate(net.b[ly], net.out[ly]);
   }
   // output layer: one 32-row block (row 0 the output, the others zero)
@@ -1110,10 +1116,10 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
       net.out[l] = s->out[l];
     }
     net.layers = L;
-    // four waves of two 32-row tiles each (one wave per SIMD: the accumulators of both
-    // tiles take the whole register file; each weight fragment read from LDS feeds two
-    // products)
-    constexpr int NT = 2, WAVES = 4;
+    // eight waves of one 32-row tile each, two per SIMD, so that one wave's SiLU
+    // epilogue (vector ALU) overlaps the other's matrix products; 256 rows share each
+    // staged layer
+    constexpr int NT = 1, WAVES = 8;
     constexpr int64_t rows_per_wg = WAVES * 32 * NT;
     const dim3 grid((unsigned)((n + rows_per_wg - 1) / rows_per_wg));
     const __bf16* f = reinterpret_cast<const __bf16*>(feat);
