@@ -194,8 +194,9 @@ struct MlpNet {
 // (MB <= 8).  A workgroup of WAVES waves takes WAVES x 32 NT rows; each wave holds
 // NT tiles of 32 rows.  Each layer is the transposed product Z^T = W H^T on
 // v_mfma_f32_32x32x16_bf16 with the rows as the 32 B columns, the layer's weights
-// staged in LDS (rows padded by 16 bytes, so that the 16-byte reads of 8
-// consecutive rows fall on distinct banks) and read once per MFMA for all NT tiles.
+// staged in LDS MQ 32-row blocks at a time (rows padded by 16 bytes, so that the
+// 16-byte reads of 8 consecutive rows fall on distinct banks) and read once per MFMA
+// for all NT tiles.
 // The weight rows of each 32-row block are taken in the order M index
 // i = 8 q + 4 h + s -> output 16 (q >> 1) + 8 h + 4 (q & 1) + s, which makes the
 // accumulator elements of a lane (h = lane / 32) exactly the B operand elements of
@@ -204,16 +205,17 @@ struct MlpNet {
 // written between layers.  Each layer sums its K steps in order, as gemm_nt_kernel
 // does, so the outputs equal the layer-by-layer forward pass.  feat: [n][kin0]
 // BF16 rows (kin0 a multiple of 16, at most 256); y[n] = the output.  Dynamic LDS:
-// mlp_infer_lds(MB, kin0) bytes.
-inline size_t mlp_infer_lds(int mb, int kin0) {
+// mlp_infer_lds(MB, MQ, kin0) bytes.
+inline size_t mlp_infer_lds(int mb, int mq, int kin0) {
   const int kmax = std::max(kin0, 32 * mb);
-  return (size_t)32 * mb * (kmax / 8 + 1) * 16;
+  return (size_t)32 * std::min(mb, mq) * (kmax / 8 + 1) * 16;
 }
-template <int MB, int NT, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __restrict__ feat, int64_t n,
+template <int MB, int NT, int WAVES, int MQ>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2))) mlp_infer_kernel(const __bf16* __restrict__ feat, int64_t n,
                                                                int kin0, MlpNet net, float* __restrict__ y) {
   constexpr int KS = 2 * MB, THREADS = 64 * WAVES;   // K steps of a hidden layer's input
-  constexpr int QS = 64 / WAVES;                     // staging loads in flight per thread
+  constexpr int NQ = (MB + MQ - 1) / MQ;             // weight chunks per layer
+  constexpr int QS = 8;                              // staging loads in flight per thread
   extern __shared__ bf16x8 wl[];
   const int l = threadIdx.x & 63, h = l >> 5, j = l & 31;
   const int64_t e0 = ((int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 32 * NT + j;
@@ -277,40 +279,50 @@ __global__ void __launch_bounds__(64 * WAVES) mlp_infer_kernel(const __bf16* __r
   // layer 0: K = kin0
   {
     const int sv = ks0 * 2 + 1;
-    stage(net.w[0], 32 * MB, ks0 * 2);
     zero();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk)
-      if (kk < ks0) {
+    for (int q = 0; q < NQ; ++q) {
+      const int m0 = q * MQ;
+      stage(net.w[0] + (int64_t)32 * m0 * kin0, 32 * (MB - m0 < MQ ? MB - m0 : MQ), ks0 * 2);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const bf16x8 a = wl[(32 * mb + fj) * sv + 2 * kk + h];
+      for (int kk = 0; kk < 16; ++kk)
+        if (kk < ks0) {
 #pragma unroll
-          for (int c = 0; c < NT; ++c)
-            acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+          for (int mb = 0; mb < MB; ++mb) {
+            if (mb < m0 || mb >= m0 + MQ) continue;
+            const bf16x8 a = wl[(32 * (mb - m0) + fj) * sv + 2 * kk + h];
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+              acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+          }
+          if (NT == 1) __builtin_amdgcn_sched_barrier(0);
         }
-        if (NT == 1) __builtin_amdgcn_sched_barrier(0);
-      }
+    }
     activate(net.b[0], net.out[0]);
   }
   // hidden layers: K = 32 MB
   constexpr int SV = 2 * KS + 1;
   const int L = net.layers;
   for (int ly = 1; ly + 1 < L; ++ly) {
-    stage(net.w[ly], 32 * MB, 2 * KS);
     zero();
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
+    for (int q = 0; q < NQ; ++q) {
+      const int m0 = q * MQ;
+      stage(net.w[ly] + (int64_t)32 * m0 * (32 * MB), 32 * (MB - m0 < MQ ? MB - m0 : MQ), 2 * KS);
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const bf16x8 a = wl[(32 * mb + fj) * SV + 2 * kk + h];
+      for (int kk = 0; kk < KS; ++kk) {
 #pragma unroll
-        for (int c = 0; c < NT; ++c)
-          acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+        for (int mb = 0; mb < MB; ++mb) {
+          if (mb < m0 || mb >= m0 + MQ) continue;
+          const bf16x8 a = wl[(32 * (mb - m0) + fj) * SV + 2 * kk + h];
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            acc[c][mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb[c][kk], acc[c][mb], 0, 0, 0);
+        }
+        // with two waves per SIMD the weight fragments of one K step at a time keep
+        // the kernel within its 256 registers
+        if (NT == 1) __builtin_amdgcn_sched_barrier(0);
       }
-      // with two waves per SIMD the weight fragments of one K step at a time keep
-      // the kernel within its 256 registers
-      if (NT == 1) __builtin_amdgcn_sched_barrier(0);
     }
     activate(net.b[ly], net.out[ly]);
   }
@@ -1116,19 +1128,21 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
       net.out[l] = s->out[l];
     }
     net.layers = L;
-    // eight waves of one 32-row tile each, two per SIMD, so that one wave's SiLU
-    // epilogue (vector ALU) overlaps the other's matrix products; 256 rows share each
-    // staged layer
-    constexpr int NT = 1, WAVES = 8;
+    // four waves of one 32-row tile each, the weights staged four 32-row blocks at a
+    // time (68 KB for width 256): two workgroups per compute unit and two waves per
+    // SIMD, so that one wave's SiLU epilogue (vector ALU) and one workgroup's staging
+    // overlap the other's matrix products
+    constexpr int NT = 1, WAVES = 4, MQ = 4;
     constexpr int64_t rows_per_wg = WAVES * 32 * NT;
     const dim3 grid((unsigned)((n + rows_per_wg - 1) / rows_per_wg));
     const __bf16* f = reinterpret_cast<const __bf16*>(feat);
     const int mb = s->width / 32;
-    const size_t lds = mlp_infer_lds(mb, s->kin0);
-    const void* fns[8] = {(const void*)mlp_infer_kernel<1, NT, WAVES>, (const void*)mlp_infer_kernel<2, NT, WAVES>,
-                          (const void*)mlp_infer_kernel<3, NT, WAVES>, (const void*)mlp_infer_kernel<4, NT, WAVES>,
-                          (const void*)mlp_infer_kernel<5, NT, WAVES>, (const void*)mlp_infer_kernel<6, NT, WAVES>,
-                          (const void*)mlp_infer_kernel<7, NT, WAVES>, (const void*)mlp_infer_kernel<8, NT, WAVES>};
+    const size_t lds = mlp_infer_lds(mb, MQ, s->kin0);
+    const void* fns[8] = {
+        (const void*)mlp_infer_kernel<1, NT, WAVES, MQ>, (const void*)mlp_infer_kernel<2, NT, WAVES, MQ>,
+        (const void*)mlp_infer_kernel<3, NT, WAVES, MQ>, (const void*)mlp_infer_kernel<4, NT, WAVES, MQ>,
+        (const void*)mlp_infer_kernel<5, NT, WAVES, MQ>, (const void*)mlp_infer_kernel<6, NT, WAVES, MQ>,
+        (const void*)mlp_infer_kernel<7, NT, WAVES, MQ>, (const void*)mlp_infer_kernel<8, NT, WAVES, MQ>};
     hipError_t e = hipFuncSetAttribute(fns[mb - 1], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return shipfail(e, "inference kernel LDS");
     void* args[] = {&f, &n, &s->kin0, &net, &y};
