@@ -381,3 +381,30 @@ def test_extended_precision_mode():
     assert np.max(np.abs(a / b - 1)) < 1e-17
     c = me.matrix_element(me.process(4), mom.astype(np.float64), AS)
     assert np.max(np.abs(c / a.astype(np.float64) - 1)) < 1e-13
+
+
+def test_rotation_invariance_on_the_stored_ggttgggg_set():
+    """The stored oracle values of the first 1024 g g -> t t~ g g g g events of the
+    32768-event workload against the oracle's values on a random rotation of each
+    (tests/golden/make_golden.py wide_c4a, wide_c4a_rot): the helicity-summed |M|^2 is
+    rotation invariant, so the two agree to FP64 rounding (a wrong rotation, or an
+    oracle term that is not a Lorentz scalar, would put them far apart)."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'golden')
+    spec = importlib.util.spec_from_file_location('make_golden', os.path.join(here, 'make_golden.py'))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    # the rotation keeps energies and every invariant p_i . p_j
+    mom = rambo.generate(8, 16, 1005)
+    rot = mg._rotate(mom, 4242)
+    assert np.array_equal(rot[..., 0], mom[..., 0])
+    for i in range(8):
+        for j in range(8):
+            assert np.allclose(mdot(rot[:, i], rot[:, j]), mdot(mom[:, i], mom[:, j]), rtol=1e-12, atol=1e-9)
+    assert np.max(np.abs(rot[..., 1:] - mom[..., 1:])) > 1.0
+    g = np.load(os.path.join(here, 'gg_ttxgggg_seed1005_first1024.npz'))['me']
+    r = np.load(os.path.join(here, 'gg_ttxgggg_seed1005_first1024_rot.npz'))['me_rot']
+    d = np.abs(r / g - 1)
+    assert len(g) == len(r) == 1024
+    assert np.median(d) < 1e-13 and np.mean(d < 1e-13) > 0.9 and d.max() < 5e-11
