@@ -65,7 +65,7 @@ def _dsilu64(z):
 GAMMA_FP32 = 2.0 ** -24   # unit roundoff of the FP32 accumulation
 
 
-@pytest.mark.parametrize('width,depth,nb', [(256, 4, 300), (96, 3, 130), (48, 2, 70)])
+@pytest.mark.parametrize('width,depth,nb', [(256, 4, 300), (96, 3, 130), (48, 2, 70), (32, 1, 33)])
 def test_surrogate_layers_and_gradients_elementwise(binding, width, depth, nb):
     """Every layer of the GPU network element by element against an FP64 reference
     that takes the GPU's own BF16 inputs and BF16 weights: pre-activations within
