@@ -186,7 +186,6 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(const __bf16* __restrict__
 struct MlpNet {
   const __bf16* w[17];   // BF16 weights [outp][kin], zero padded
   const float* b[17];    // biases [out]
-  int out[17];
   int layers;
 };
 
@@ -264,16 +263,20 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         for (int v = 0; v < 16; ++v) acc[c][mb][v] = 0.0f;
   };
   // bias, SiLU and BF16 rounding of a hidden layer's outputs into the next B operands
-  auto activate = [&](const float* __restrict__ bias, int nout) {
+  // (a hidden layer has exactly 32 MB outputs: the bias is read as float4, the four
+  // consecutive outputs v & 3 of each group v >> 2)
+  auto activate = [&](const float* __restrict__ bias) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int o = 32 * mb + 16 * (v >> 3) + 8 * h + 4 * ((v >> 2) & 1) + (v & 3);
-        const float bo = o < nout ? bias[o] : 0.0f;
+      for (int g = 0; g < 4; ++g) {
+        const float4 b4 = *reinterpret_cast<const float4*>(bias + 32 * mb + 16 * (g >> 1) + 8 * h + 4 * (g & 1));
+        const float bo[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-        for (int c = 0; c < NT; ++c)
-          hb[c][2 * mb + (v >> 3)][4 * ((v >> 2) & 1) + (v & 3)] = to_bf16(silu(acc[c][mb][v] + bo));
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            hb[c][2 * mb + (g >> 1)][4 * (g & 1) + s] = to_bf16(silu(acc[c][mb][4 * g + s] + bo[s]));
       }
   };
   // layer 0: K = kin0
@@ -298,7 +301,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           if (NT == 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
-    activate(net.b[0], net.out[0]);
+    activate(net.b[0]);
   }
   // hidden layers: K = 32 MB
   constexpr int SV = 2 * KS + 1;
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         if (NT == 1) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    activate(net.b[ly], net.out[ly]);
+    activate(net.b[ly]);
   }
   // output layer: one 32-row block (row 0 the output, the others zero)
   stage(net.w[L - 1], 32, 2 * KS);
@@ -1125,7 +1128,6 @@ int me_sur_predict(me_surrogate s, const uint16_t* feat, int64_t n, float* y, vo
     for (int l = 0; l < L; ++l) {
       net.w[l] = s->w16[l];
       net.b[l] = s->b[l];
-      net.out[l] = s->out[l];
     }
     net.layers = L;
     // four waves of one 32-row tile each, the weights staged four 32-row blocks at a
