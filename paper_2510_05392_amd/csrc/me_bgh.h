@@ -843,10 +843,14 @@ bgh_fused_kernel(const double* __restrict__ mom, int64_t n, double g0, double mt
     // every amplitude of the block is stored (workgroup-scope fence and barrier)
     // and the frames are no longer read
     __syncthreads();
+    // the colour phase (matrix cores, LDS) at a raised wave priority, so that its
+    // issue is not held behind the other workgroup's recursion (vector ALU)
+    __builtin_amdgcn_s_setprio(1);
     if constexpr (FMT < 0)
       bgh_colour_rows<S::NCOL, THREADS>(slot, srows, 0, nev * nhel, cft, cfs, rv);
     else
       bgh_colour_rows_split<S::NCOL, FMT, THREADS>(slot, srows, nev * nhel, cf_hi, cf_lo, cfs, rmax, rv);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // helicity sum of each event in row order (the order of reduce_rows_kernel)
     for (int ev = threadIdx.x; ev < nev; ev += THREADS) {
