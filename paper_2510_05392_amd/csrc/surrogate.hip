@@ -283,6 +283,9 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   {
     const int sv = ks0 * 2 + 1;
     zero();
+    // the products at a raised wave priority: the other wave's SiLU epilogue fills
+    // the vector ALU around them
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int m0 = q * MQ;
@@ -301,6 +304,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
           if (NT == 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     activate(net.b[0]);
   }
   // hidden layers: K = 32 MB
@@ -308,6 +312,9 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   const int L = net.layers;
   for (int ly = 1; ly + 1 < L; ++ly) {
     zero();
+    // the products at a raised wave priority: the other wave's SiLU epilogue fills
+    // the vector ALU around them
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int m0 = q * MQ;
@@ -327,6 +334,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         if (NT == 1) __builtin_amdgcn_sched_barrier(0);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     activate(net.b[ly]);
   }
   // output layer: one 32-row block (row 0 the output, the others zero)
